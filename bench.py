@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""PSTT2-onepass benchmark on one MI355X.
+
+One step = the whole hot path over the resident tensor: reset the context,
+stream X once through the dual-sketch kernel (right and left sketches of the
+middle unfolding), recover the TT cores in FP64 on the GPU (derived sketches,
+TSQR + pivoted QR bases, outer cores, least-squares middle core), and
+evaluate the relative error ||X - X~||_F / ||X||_F in a second streaming pass.
+
+Default workload: FP64 d=6, n=32 (1.07e9 entries, 8.6 GB), X = random Gaussian
+TT with ranks 10 scaled to ||X||_F = 1 plus N(0, 1e-8) noise, target ranks 10,
+sketch size 20.  Inputs are synthetic and seeded (inputs/).
+
+Prints one JSON line.  `value` is whole-step throughput (bytes of X per step
+time; X is read twice per step: sketch and error).  `roofline` covers the
+dominant kernel (the streaming sketch), timed with HIP events on the stream it
+runs on.  `cpu_baseline` times the CPU FP64 oracle on a bounded sub-tensor.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 (vector = matrix)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2111_10448_amd", "csrc", "sketch.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str, launches_per_step: int):
+    """HBM bytes per sketch launch from the committed counter summary, if it matches this kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_sketch_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel source sha256\[:16\]:\s*`?([0-9a-f]{16})", txt)
+    b = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 15.0):
+    """Time the oracle (sketches + recovery + error) on a sub-tensor of the same tensor."""
+    from oracle import tt_sketch as O
+    try:
+        import threadpoolctl
+        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    n = list(w.n)
+    d = len(n)
+    # keep the first modes whole, cut the two slowest modes to s entries each
+    s = 8
+    sub = x.reshape(n[::-1])[:s, :s].reshape(-1)      # C-order view (i_d slowest)
+    ns = n[:-2] + [s, s]
+    sub = np.ascontiguousarray(sub)
+    psi_s = {q: psi[q][:ns[q - 1]] for q in psi}
+    om_s = {q: omega[q][:ns[q - 1]] for q in omega}
+    drm = O.NestedKR(psi_s, om_s)
+    t0 = time.perf_counter()
+    out = O.pstt2(sub, ns, drm, ranks=w.ranks())
+    t1 = time.perf_counter()
+    err = O.tt_error(sub, out["cores"])
+    t2 = time.perf_counter()
+    gbs = sub.nbytes / (t2 - t0) / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"sub-tensor n={tuple(ns)} ({sub.size} entries, {sub.nbytes / 1e9:.2f} GB) of the same "
+                      f"tensor: oracle sketches+recovery {t1 - t0:.1f} s, error pass {t2 - t1:.1f} s, "
+                      f"rel. error {err:.3e}"}
+
+
+def run_workload(name, prec, steps, warmup, ranks_from=None):
+    import torch
+    import inputs
+    import paper_2111_10448_amd as P
+
+    w = inputs.WORKLOADS[name]
+    t0 = time.perf_counter()
+    x = inputs.make_tensor(w)
+    psi, omega = inputs.drm_factors(w)
+    fac = inputs.pack_factors(psi, omega, w.d)
+    log(f"[bench] {name}: generated {x.nbytes / 1e9:.2f} GB on the host in {time.perf_counter() - t0:.1f} s")
+    xg = torch.from_numpy(x).to("cuda:0")
+    torch.cuda.synchronize()
+    kw = dict(dtype=w.dtype, prec=prec)
+    if ranks_from is not None:
+        kw["ranks"] = ranks_from
+    elif w.rank is not None:
+        kw["ranks"] = w.ranks()
+    else:
+        kw["eps"] = w.eps
+        kw["rmax"] = w.rmax
+    ctx = P.PSTT2(w.n, w.ell, fac, **kw)
+
+    def step():
+        ctx.reset()
+        ctx.sketch(xg)
+        tt = ctx.recover()
+        e = tt.error(xg)
+        return tt, e
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read()
+    t_dec = 0.0
+    t0 = time.perf_counter()
+    tt = err = None
+    for _ in range(steps):
+        a = time.perf_counter()
+        ctx.reset()
+        ctx.sketch(xg)
+        tt = ctx.recover()
+        b = time.perf_counter()
+        err = tt.error(xg)
+        t_dec += b - a
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, launches = ctx.profile_read()
+    ctx.profile(False)
+    res = {
+        "workload": w, "x": x, "psi": psi, "omega": omega, "ranks": tt.ranks, "err": err,
+        "ms_per_step": (t1 - t0) * 1e3 / steps, "decomp_ms": t_dec * 1e3 / steps,
+        "kernel_ms": kms / max(launches, 1), "launches_per_step": launches // max(steps, 1),
+        "bytes": x.nbytes,
+    }
+    ctx.close()
+    del xg
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--prec", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time the Chebyshev 1/sum workload in FP64, FP32, split-BF16 and BF16")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run a 2 GiB device copy (counter calibration under rocprofv3) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calib:
+        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 3}))
+        return
+
+    import inputs
+    name = args.workload
+    w = inputs.WORKLOADS[name]
+    prec = args.prec or ("f64" if w.dtype == "f64" else "f32")
+    r = run_workload(name, prec, args.steps, args.warmup)
+    w = r["workload"]
+    value = r["bytes"] / (r["ms_per_step"] * 1e-3) / 1e9
+    kb = r["bytes"] / r["launches_per_step"] if r["launches_per_step"] else r["bytes"]
+    achieved = kb / (r["kernel_ms"] * 1e-3) / 1e9
+    flops = 4.0 * w.ell * w.numel
+    record = {
+        "metric": "PSTT2 sketch GB/s & % HBM roofline, FP64 vs mixed-prec at stated TT error",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": f"{name}: d={w.d} n={w.n[0]} ({w.numel} entries, {w.dtype}), random Gaussian TT "
+                               f"rank {w.tt_rank}, noise {w.noise:g}, target rank {w.rank}, sketch size {w.ell}",
+                   "ranks": r["ranks"], "tt_rel_error": r["err"], "decompose_ms": round(r["decomp_ms"], 4),
+                   "sketch_kernel_ms": round(r["kernel_ms"], 4),
+                   "sketch_gbs": round(achieved, 2), "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(name, 1),
+                     "fp64_frac": round(flops / (r["kernel_ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)},
+    }
+    if args.variants:
+        var = {}
+        for vp in ("f64", "f32", "bf16x3", "bf16"):
+            wn = "c3_f64" if vp == "f64" else "c3"
+            try:
+                rv = run_workload(wn, vp, max(3, args.steps // 2), 1)
+                wv = rv["workload"]
+                kbv = rv["bytes"] / max(rv["launches_per_step"], 1)
+                var[vp] = {"workload": wn, "sketch_kernel_ms": round(rv["kernel_ms"], 4),
+                           "sketch_gbs": round(kbv / (rv["kernel_ms"] * 1e-3) / 1e9, 2),
+                           "ms_per_step": round(rv["ms_per_step"], 4), "ranks": rv["ranks"],
+                           "tt_rel_error": rv["err"]}
+            except Exception as e:   # report, keep the headline line
+                var[vp] = {"error": str(e)}
+        record["variants"] = var
+    if not args.no_cpu_baseline:
+        record["cpu_baseline"] = cpu_baseline(r["x"], w, r["psi"], r["omega"])
+    print(json.dumps(record), flush=True)
+
+
+if __name__ == "__main__":
+    main()

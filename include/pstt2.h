@@ -1,0 +1,197 @@
+/*
+ * pstt2.h -- C ABI of the MI355X PSTT2 library (libpstt2.so).
+ *
+ * What it computes (Shi, Ruth, Townsend, "Parallel Algorithms for computing the
+ * Tensor-train decomposition"):
+ *   input  a dense d-way tensor X (n_1 x ... x n_d, column-major, i_1 fastest;
+ *          Section 2.1) and either target TT ranks r_1..r_{d-1} or a tolerance eps;
+ *   output TT cores G_k (r_{k-1} x n_k x r_k, r_0 = r_d = 1) with
+ *          ||X - X~||_F <= eps ||X||_F in the tolerance form of the problem
+ *          statement (Section 1, equation "FrobeniusNorm").
+ * The method is PSTT2-onepass (Section 3.2, final paragraphs; Section 4.2):
+ * a single streaming pass over X forms, with Khatri-Rao Gaussian DRMs
+ * (Section 3.2, equation "sketch_orig"), the right sketch Y_R = X_m Omega_m and
+ * the left sketch T_m = Psi_m^T X_m of the middle unfolding (m = ceil(d/2)),
+ * from which every other split's sketch S_k = X_k Omega_k (k < m) and
+ * T_k = Psi_k^T X_k (k > m) follows by contracting one mode at a time (the
+ * nested DRM scheme: one Gaussian factor per mode, shared by every split).
+ * Column bases Q_k (k < m) and row bases P_k (k >= m) come from column-pivoted
+ * QR of those sketches (Algorithm PSTT, CPQR step), outer cores from
+ * neighbouring bases (Theorem 2, equation "core", and its row-space mirror),
+ * and the middle core from two small products and a least-squares solve
+ * (equation "onepass_final_core" applied to the middle unfolding).
+ *
+ * Conventions
+ *   - Every pointer named *_dev is device memory on the current HIP device;
+ *     every other pointer is host memory.
+ *   - Every call returns a pstt2_status; nothing throws across the ABI.  On an
+ *     error the outputs are left untouched and pstt2_last_error() describes it.
+ *   - Calls marked "async" enqueue work on the context's (or the given) HIP
+ *     stream and return before it runs; device-side failures of async work are
+ *     reported by the next synchronising call.  Calls marked "sync" block the
+ *     host until their stream is idle.
+ *   - A context is bound to one stream and is not thread-safe.
+ *   - Sizes are int64; flat indices and byte offsets exceed 2^31.
+ */
+#ifndef PSTT2_H
+#define PSTT2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSTT2_MAX_D 32   /* largest supported order d */
+#define PSTT2_MAX_ELL 32 /* largest supported sketch size ell */
+
+typedef enum {
+  PSTT2_OK = 0,
+  PSTT2_EINVAL = -1,   /* bad argument or descriptor field */
+  PSTT2_ESHAPE = -2,   /* sizes inconsistent with the context */
+  PSTT2_ENOMEM = -3,   /* device or host allocation failed */
+  PSTT2_EDEVICE = -4,  /* a HIP runtime call failed */
+  PSTT2_ENUMERIC = -5, /* non-finite values in X or a singular sketch */
+  PSTT2_ESTATE = -6    /* call out of order (e.g. overlapping or missing slabs) */
+} pstt2_status;
+
+/* Element type of X in device memory. */
+typedef enum { PSTT2_F64 = 0, PSTT2_F32 = 1 } pstt2_dtype;
+
+/* Arithmetic of the sketch contractions.  Recovery is always FP64.
+ *   F64     FP64 products and sums (FP64 matrix cores)
+ *   F32     FP32 products, FP32 accumulation within a tile, FP64 across tiles
+ *   BF16    X and the DRM rounded to bfloat16, FP32 accumulation
+ *   BF16X3  X = hi + lo and DRM = hi + lo in bfloat16, hi*hi + hi*lo + lo*hi,
+ *           FP32 accumulation (split precision)
+ * F32 / BF16 / BF16X3 need dtype F32. */
+typedef enum { PSTT2_P_F64 = 0, PSTT2_P_F32 = 1, PSTT2_P_BF16 = 2, PSTT2_P_BF16X3 = 3 } pstt2_prec;
+
+/* Middle-core rule.  ONEPASS: least squares from the extra right sketch of the
+ * middle unfolding (PSTT2-onepass).  TWOPASS: second stream over X,
+ * G_m = reshape(X, R_{m-1}, n_m, C_m) x_1 Q_{m-1}^T x_3 P_m^T
+ * (equation "PSTT2_final_core"); see pstt2_middle_pass. */
+typedef enum { PSTT2_MID_ONEPASS = 0, PSTT2_MID_TWOPASS = 1 } pstt2_mid;
+
+typedef struct {
+  int32_t d;                  /* order, 2 <= d <= PSTT2_MAX_D */
+  int64_t n[PSTT2_MAX_D];     /* mode sizes n_1..n_d in n[0..d-1], each >= 1 */
+  pstt2_dtype dtype;          /* element type of X */
+  pstt2_prec prec;            /* sketch arithmetic */
+  pstt2_mid mid;              /* middle-core rule */
+  int32_t ranks[PSTT2_MAX_D]; /* r_1..r_{d-1} in ranks[0..d-2]; ranks[0] <= 0 selects tolerance mode */
+  double eps;                 /* tolerance mode: target relative Frobenius error, 0 < eps < 1 */
+  int32_t rmax;               /* tolerance mode: rank cap (<= 0: ell - 2) */
+  int32_t ell;                /* sketch size r + p, 1 <= ell <= PSTT2_MAX_ELL */
+  const double* drm_factors;  /* host, copied at create: psi_1..psi_{d-1} then omega_2..omega_d,
+                                 factor q is n_q x ell with ell fastest (element (i, c) at i*ell + c),
+                                 iid standard Gaussian in the paper's DRMs (Section 3.2) */
+} pstt2_desc;
+
+/* A tensor train.  Core k (0-based) is r[k] x n[k] x r[k+1], column-major
+ * (element (a, i, b) at a + r[k]*(i + n[k]*b)), FP64, device memory. */
+typedef struct {
+  int32_t d;
+  int64_t n[PSTT2_MAX_D];
+  int32_t r[PSTT2_MAX_D + 1];  /* r[0] = r[d] = 1 */
+  double* core[PSTT2_MAX_D];   /* device pointers */
+  int32_t owned;               /* 1: allocated by the library, release with tt_cores_free */
+} tt_cores;
+
+typedef struct pstt2_ctx pstt2_ctx;
+
+/* Create a context: validate the descriptor, upload the DRM factors, allocate
+ * the sketch accumulators (R_m x ell and ell x C_m, FP64) and the tile
+ * partials.  hip_stream may be NULL (the null stream).  sync.
+ * Errors: EINVAL (descriptor), ENOMEM, EDEVICE. */
+pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** out);
+
+/* Stream one slab of X into the sketches (Algorithm "parsketch": every sketch
+ * from one read of each sub-tensor).  x_dev points at the slab's first entry,
+ * which is flat column-major index `first` of X; the slab holds `count`
+ * entries of the context's dtype.  first and count must be multiples of n_1
+ * (whole mode-1 fibres); slabs may arrive in any order, each entry exactly
+ * once.  x_dev must stay valid until the context's stream passes the work.
+ * async.  Errors: EINVAL (alignment, range), ESTATE (overlaps an earlier slab). */
+pstt2_status pstt2_sketch(pstt2_ctx* ctx, const void* x_dev, int64_t first, int64_t count);
+
+/* The same for nslabs slabs in one launch (slab s at xs_dev[s], flat range
+ * [firsts[s], firsts[s] + counts[s])).  Host arrays; async. */
+pstt2_status pstt2_sketch_slabs(pstt2_ctx* ctx, int32_t nslabs, const void* const* xs_dev,
+                                const int64_t* firsts, const int64_t* counts);
+
+/* Recover the TT cores from the accumulated sketches: derive every split's
+ * sketch, bases by TSQR + column-pivoted QR of the small R factor (sign fixed
+ * so that diag(R) >= 0), outer cores, middle core.  In tolerance mode the
+ * ranks follow the rule sum_{i>r} sigma_i(S_k)^2 <= eps^2/(d-1) ||S_k||_F^2
+ * capped at rmax.  out->core[k] are library-allocated (out->owned = 1).  sync.
+ * For PSTT2_MID_TWOPASS the middle core is computed by pstt2_middle_pass calls
+ * made after this one; until then out->core[m-1] is allocated and zero.
+ * Errors: ESTATE (not every entry of X was streamed exactly once),
+ * ENUMERIC (non-finite sketch, rank-deficient least-squares system), ENOMEM, EDEVICE. */
+pstt2_status pstt2_recover(pstt2_ctx* ctx, tt_cores* out);
+
+/* Two-pass middle core (equation "PSTT2_final_core"): add the contribution of a
+ * slab of X to out->core[m-1] of the cores returned by pstt2_recover.  Same slab
+ * rules as pstt2_sketch.  async.  Errors: ESTATE (context not in two-pass mode or
+ * recover not called), EINVAL. */
+pstt2_status pstt2_middle_pass(pstt2_ctx* ctx, tt_cores* cores, const void* x_dev, int64_t first,
+                               int64_t count);
+
+/* Copy an accumulated or derived sketch to host memory (FP64, column-major).
+ * which = 0: the right sketch of split k (1 <= k <= m; k = m is Y_R), R_k x ell.
+ * which = 1: the transposed left sketch T_k^T of split k (m <= k <= d-1), C_k x ell.
+ * Valid after pstt2_recover.  *rows/*cols receive the shape; host_out must hold
+ * rows*cols doubles (pass host_out = NULL to query the shape).  sync. */
+pstt2_status pstt2_get_sketch(pstt2_ctx* ctx, int32_t which, int32_t k, double* host_out, int64_t* rows,
+                              int64_t* cols);
+
+/* Pivot order chosen for split k's basis (0-based column indices, ell of them). sync. */
+pstt2_status pstt2_get_pivots(pstt2_ctx* ctx, int32_t k, int32_t* host_piv);
+
+/* Kernel timing: with enable = 1 every later sketch launch of this context is
+ * bracketed by HIP events recorded on the context's stream (around the
+ * streaming sketch kernel only, not its partial reduction).  enable = 0 stops
+ * and clears the record.  Host-side; async.  Errors: EINVAL. */
+pstt2_status pstt2_profile(pstt2_ctx* ctx, int32_t enable);
+
+/* Sum of the recorded sketch-kernel durations (milliseconds) and the number of
+ * launches, then clear the record.  sync.  Errors: EINVAL, EDEVICE. */
+pstt2_status pstt2_profile_read(pstt2_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Forget all streamed data (zero the sketches and the coverage record); the DRM
+ * factors are kept, so the same context sketches the next tensor.  async. */
+pstt2_status pstt2_reset(pstt2_ctx* ctx);
+
+/* Release the context.  sync.  NULL is ignored. */
+void pstt2_destroy(pstt2_ctx* ctx);
+
+/* Relative error ||X - X~||_F / ||X||_F by entrywise differences over one
+ * streaming pass, sums in FP64 (Section 4.1: the error measured for every
+ * trial).  cores may point at caller memory.  sync.  Errors: EINVAL, EDEVICE. */
+pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* rel_err,
+                      void* hip_stream);
+
+/* Write entries [first, first + count) of X~ (flat column-major, entry formula
+ * of Section 2.2) to x_out_dev in the given dtype.  sync.  Errors: EINVAL, EDEVICE. */
+pstt2_status tt_reconstruct(const tt_cores* cores, void* x_out_dev, pstt2_dtype dtype, int64_t first,
+                            int64_t count, void* hip_stream);
+
+/* Copy the core values of src into the buffers of dst (same d, n, r; dst's
+ * core pointers are caller-provided device memory).  sync.  Errors: EINVAL, EDEVICE. */
+pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream);
+
+/* Release library-owned cores (owned == 1) and clear the struct.  NULL is ignored. */
+void tt_cores_free(tt_cores* cores);
+
+/* Message for the last failing call on ctx, or (ctx == NULL) on this thread. */
+const char* pstt2_last_error(const pstt2_ctx* ctx);
+
+/* Library version string. */
+const char* pstt2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSTT2_H */

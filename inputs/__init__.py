@@ -77,6 +77,8 @@ WORKLOADS = {
     "c2": Workload("c2", 1, (32,) * 6, "f64", "tt", tt_rank=10, noise=1e-8, unit_norm=True, ell=20, rank=10),
     # d=5, n=64 FP32 samples of 1/(x1+..+x5) on a Chebyshev grid over [1,2]^5, eps=1e-5, ranks <= 16, sketch size 32
     "c3": Workload("c3", 2, (64,) * 5, "f32", "invsum", ell=32, eps=1e-5, rmax=16),
+    # the same samples kept in FP64 (the plain-FP64 comparator of the precision study)
+    "c3_f64": Workload("c3_f64", 2, (64,) * 5, "f64", "invsum", ell=32, eps=1e-5, rmax=16),
     # d=8, n=12 FP32, TT ranks 8, noise 1e-4, rank 8, sketch size 16, 64 contiguous slabs
     "c4": Workload("c4", 3, (12,) * 8, "f32", "tt", tt_rank=8, noise=1e-4, ell=16, rank=8, nslabs=64),
     # d=4, n=48 FP32, TT ranks 6, noise 1e-3, rank 6, sketch size 12 (differentiation workload)

@@ -1,0 +1,308 @@
+"""MI355X PSTT2: streaming two-sided sketching tensor-train decomposition.
+
+Thin Python binding of libpstt2 (C ABI in include/pstt2.h).  Every step of the
+method runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch provides device memory (tensors) and the current HIP
+stream.
+
+    import paper_2111_10448_amd as P
+    ctx = P.PSTT2(n, ell, factors, dtype="f32", prec="bf16x3", eps=1e-5, rmax=16)
+    ctx.sketch(x_gpu)              # one pass over X (or several slabs)
+    tt = ctx.recover()             # TT cores on the GPU
+    err = tt.error(x_gpu)          # ||X - X~||_F / ||X||_F
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import PSTT2Error  # noqa: F401
+
+__all__ = ["PSTT2", "TT", "PSTT2Error", "decompose", "tt_error", "tt_reconstruct", "version", "cores_struct"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return L.F64
+    if t.dtype == torch.float32:
+        return L.F32
+    raise TypeError(f"X must be float64 or float32, got {t.dtype}")
+
+
+def _check_dev(t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor (flat column-major slab)")
+
+
+def version() -> str:
+    return L.lib().pstt2_version().decode()
+
+
+class TT:
+    """Tensor-train cores produced by the library (device memory)."""
+
+    def __init__(self, cs: L.TTCores, stream=None):
+        self._c = cs
+        self._stream = stream
+
+    @property
+    def d(self) -> int:
+        return self._c.d
+
+    @property
+    def n(self) -> List[int]:
+        return [int(self._c.n[k]) for k in range(self._c.d)]
+
+    @property
+    def ranks(self) -> List[int]:
+        return [int(self._c.r[k]) for k in range(self._c.d + 1)]
+
+    def struct(self) -> L.TTCores:
+        return self._c
+
+    def cores_torch(self):
+        """Copies of the cores as flat FP64 CUDA tensors (column-major r_{k-1} x n_k x r_k)."""
+        torch = _torch()
+        out = []
+        dst = L.TTCores()
+        dst.d = self._c.d
+        for k in range(self._c.d):
+            dst.n[k] = self._c.n[k]
+            sz = self._c.r[k] * self._c.n[k] * self._c.r[k + 1]
+            t = torch.empty(int(sz), dtype=torch.float64, device="cuda")
+            out.append(t)
+            dst.core[k] = t.data_ptr()
+        for k in range(self._c.d + 1):
+            dst.r[k] = self._c.r[k]
+        L.check(L.lib().tt_cores_copy(ctypes.byref(self._c), ctypes.byref(dst), _stream_handle(self._stream)))
+        return out
+
+    def cores_numpy(self) -> List[np.ndarray]:
+        """Host copies shaped (r_{k-1}, n_k, r_k)."""
+        r = self.ranks
+        n = self.n
+        return [t.cpu().numpy().reshape((r[k], n[k], r[k + 1]), order="F")
+                for k, t in enumerate(self.cores_torch())]
+
+    def error(self, x) -> float:
+        return tt_error(self, x, stream=self._stream)
+
+    def reconstruct(self, first: int = 0, count: Optional[int] = None, dtype=None):
+        return tt_reconstruct(self, first, count, dtype, stream=self._stream)
+
+    def free(self) -> None:
+        if self._c is not None and self._c.owned:
+            L.lib().tt_cores_free(ctypes.byref(self._c))
+        self._c = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def cores_struct(cores: Sequence, n: Sequence[int], ranks: Sequence[int]) -> L.TTCores:
+    """A non-owning tt_cores view of caller cores.
+
+    cores[k] is a contiguous FP64 CUDA tensor holding core k column-major
+    (element (a, i, b) at a + r_k (i + n_k b)); ranks = (1, r_1, ..., r_{d-1}, 1).
+    Keep the tensors alive while the struct is used.
+    """
+    torch = _torch()
+    cs = L.TTCores()
+    d = len(n)
+    if len(ranks) != d + 1 or ranks[0] != 1 or ranks[d] != 1:
+        raise ValueError("ranks must be (1, r_1, ..., r_{d-1}, 1)")
+    cs.d = d
+    cs.owned = 0
+    for k in range(d):
+        t = cores[k]
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("cores must be contiguous float64 CUDA tensors")
+        if t.numel() != ranks[k] * n[k] * ranks[k + 1]:
+            raise ValueError(f"core {k} has {t.numel()} entries, expected {ranks[k] * n[k] * ranks[k + 1]}")
+        cs.n[k] = int(n[k])
+        cs.core[k] = t.data_ptr()
+    for k in range(d + 1):
+        cs.r[k] = int(ranks[k])
+    return cs
+
+
+class PSTT2:
+    """A PSTT2-onepass (or two-pass) context: DRM factors, sketches, slab coverage."""
+
+    def __init__(self, n: Sequence[int], ell: int, factors: np.ndarray, *, dtype: str = "f64",
+                 prec: Optional[str] = None, ranks: Optional[Sequence[int]] = None, eps: Optional[float] = None,
+                 rmax: int = 0, mid: str = "onepass", stream=None):
+        self.n = [int(v) for v in n]
+        self.d = len(self.n)
+        self.ell = int(ell)
+        self.dtype = dtype
+        prec = prec or dtype
+        self._stream = stream
+        desc = L.Desc()
+        desc.d = self.d
+        for k, v in enumerate(self.n):
+            desc.n[k] = v
+        desc.dtype = L.F64 if dtype == "f64" else L.F32
+        desc.prec = L.PREC[prec]
+        desc.mid = L.MID[mid]
+        if ranks is not None:
+            for k, v in enumerate(ranks):
+                desc.ranks[k] = int(v)
+        else:
+            desc.ranks[0] = 0
+            desc.eps = float(eps if eps is not None else 0.0)
+            desc.rmax = int(rmax)
+        desc.ell = self.ell
+        self._fac = np.ascontiguousarray(factors, dtype=np.float64)
+        desc.drm_factors = self._fac.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._ctx = ctypes.c_void_p()
+        L.check(L.lib().pstt2_create(ctypes.byref(desc), ctypes.c_void_p(_stream_handle(stream)),
+                                     ctypes.byref(self._ctx)))
+        self._keep = []   # slabs kept alive until the stream passes them
+
+    def _c(self):
+        if not self._ctx:
+            raise RuntimeError("context closed")
+        return self._ctx
+
+    def sketch(self, x, first: int = 0) -> None:
+        """Stream a flat column-major slab of X starting at flat index `first` (async)."""
+        _check_dev(x)
+        self._keep.append(x)
+        L.check(L.lib().pstt2_sketch(self._c(), ctypes.c_void_p(x.data_ptr()), int(first), int(x.numel())),
+                self._ctx)
+
+    def sketch_slabs(self, xs: Sequence, firsts: Sequence[int]) -> None:
+        """Stream several slabs in one launch (async)."""
+        ns = len(xs)
+        ptrs = (ctypes.c_void_p * ns)()
+        fs = (ctypes.c_int64 * ns)()
+        cs = (ctypes.c_int64 * ns)()
+        for i, (x, f) in enumerate(zip(xs, firsts)):
+            _check_dev(x)
+            ptrs[i] = x.data_ptr()
+            fs[i] = int(f)
+            cs[i] = int(x.numel())
+        self._keep.extend(xs)
+        L.check(L.lib().pstt2_sketch_slabs(self._c(), ns, ptrs, fs, cs), self._ctx)
+
+    def recover(self) -> TT:
+        cs = L.TTCores()
+        L.check(L.lib().pstt2_recover(self._c(), ctypes.byref(cs)), self._ctx)
+        self._keep = []
+        return TT(cs, self._stream)
+
+    def middle_pass(self, tt: TT, x, first: int = 0) -> None:
+        _check_dev(x)
+        L.check(L.lib().pstt2_middle_pass(self._c(), ctypes.byref(tt.struct()), ctypes.c_void_p(x.data_ptr()),
+                                          int(first), int(x.numel())), self._ctx)
+        self._keep.append(x)
+
+    def get_sketch(self, which: int, k: int) -> np.ndarray:
+        """which = 0: right sketch of split k (R_k x ell); 1: transposed left sketch (C_k x ell)."""
+        rows = ctypes.c_int64()
+        cols = ctypes.c_int64()
+        L.check(L.lib().pstt2_get_sketch(self._c(), which, k, None, ctypes.byref(rows), ctypes.byref(cols)),
+                self._ctx)
+        out = np.empty(rows.value * cols.value, dtype=np.float64)
+        L.check(L.lib().pstt2_get_sketch(self._c(), which, k, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         ctypes.byref(rows), ctypes.byref(cols)), self._ctx)
+        return out.reshape((rows.value, cols.value), order="F")
+
+    def pivots(self, k: int) -> np.ndarray:
+        out = (ctypes.c_int32 * self.ell)()
+        L.check(L.lib().pstt2_get_pivots(self._c(), k, out), self._ctx)
+        return np.array(out[:], dtype=np.int64)
+
+    def profile(self, enable: bool = True) -> None:
+        """Bracket every later sketch-kernel launch with HIP events on the context's stream."""
+        L.check(L.lib().pstt2_profile(self._c(), 1 if enable else 0), self._ctx)
+
+    def profile_read(self):
+        """(total milliseconds, launches) of the sketch kernel since the last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        L.check(L.lib().pstt2_profile_read(self._c(), ctypes.byref(ms), ctypes.byref(n)), self._ctx)
+        return ms.value, n.value
+
+    def reset(self) -> None:
+        L.check(L.lib().pstt2_reset(self._c()), self._ctx)
+        self._keep = []
+
+    def close(self) -> None:
+        if self._ctx:
+            L.lib().pstt2_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+        self._keep = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tt_error(tt, x, stream=None) -> float:
+    """||X - X~||_F / ||X||_F over one streaming pass (FP64 sums)."""
+    _check_dev(x)
+    cs = tt.struct() if isinstance(tt, TT) else tt
+    out = ctypes.c_double()
+    L.check(L.lib().tt_error(ctypes.byref(cs), ctypes.c_void_p(x.data_ptr()), _dtype_code(x), ctypes.byref(out),
+                             ctypes.c_void_p(_stream_handle(stream))))
+    return out.value
+
+
+def tt_reconstruct(tt, first: int = 0, count: Optional[int] = None, dtype=None, stream=None):
+    """Entries [first, first+count) of X~ as a flat CUDA tensor (FP64 by default)."""
+    torch = _torch()
+    cs = tt.struct() if isinstance(tt, TT) else tt
+    n = [int(cs.n[k]) for k in range(cs.d)]
+    total = int(np.prod(n))
+    if count is None:
+        count = total - first
+    dtype = dtype or torch.float64
+    out = torch.empty(int(count), dtype=dtype, device="cuda")
+    L.check(L.lib().tt_reconstruct(ctypes.byref(cs), ctypes.c_void_p(out.data_ptr()), _dtype_code(out), int(first),
+                                   int(count), ctypes.c_void_p(_stream_handle(stream))))
+    return out
+
+
+def decompose(x, n: Sequence[int], ell: int, factors: np.ndarray, *, prec: Optional[str] = None,
+              ranks: Optional[Sequence[int]] = None, eps: Optional[float] = None, rmax: int = 0,
+              mid: str = "onepass") -> TT:
+    """One-shot PSTT2 of a whole flat column-major CUDA tensor."""
+    dtype = "f64" if _dtype_code(x) == L.F64 else "f32"
+    with PSTT2(n, ell, factors, dtype=dtype, prec=prec, ranks=ranks, eps=eps, rmax=rmax, mid=mid) as ctx:
+        ctx.sketch(x.reshape(-1))
+        tt = ctx.recover()
+        if mid == "twopass":
+            ctx.middle_pass(tt, x.reshape(-1))
+            _torch().cuda.synchronize()
+        return tt

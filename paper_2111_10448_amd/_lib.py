@@ -1,0 +1,108 @@
+"""ctypes declarations of the C ABI in include/pstt2.h (argument marshalling only).
+
+The shared library is built in-tree (paper_2111_10448_amd/libpstt2.so) by
+paper_2111_10448_amd/build.py.  Importing this module without it raises an
+error: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpstt2.so")
+
+MAX_D = 32
+MAX_ELL = 32
+
+OK, EINVAL, ESHAPE, ENOMEM, EDEVICE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENUMERIC", -6: "ESTATE"}
+F64, F32 = 0, 1
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
+MID = {"onepass": 0, "twopass": 1}
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32),
+        ("n", ctypes.c_int64 * MAX_D),
+        ("dtype", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("mid", ctypes.c_int),
+        ("ranks", ctypes.c_int32 * MAX_D),
+        ("eps", ctypes.c_double),
+        ("rmax", ctypes.c_int32),
+        ("ell", ctypes.c_int32),
+        ("drm_factors", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class TTCores(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32),
+        ("n", ctypes.c_int64 * MAX_D),
+        ("r", ctypes.c_int32 * (MAX_D + 1)),
+        ("core", ctypes.c_void_p * MAX_D),
+        ("owned", ctypes.c_int32),
+    ]
+
+
+class PSTT2Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libpstt2 with argument types declared; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2111_10448_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+    L.pstt2_create.argtypes = [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]
+    L.pstt2_sketch.argtypes = [vp, vp, i64, i64]
+    L.pstt2_sketch_slabs.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.pstt2_recover.argtypes = [vp, ctypes.POINTER(TTCores)]
+    L.pstt2_middle_pass.argtypes = [vp, ctypes.POINTER(TTCores), vp, i64, i64]
+    L.pstt2_get_sketch.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                   ctypes.POINTER(i64)]
+    L.pstt2_get_pivots.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.pstt2_profile.argtypes = [vp, i32]
+    L.pstt2_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.pstt2_reset.argtypes = [vp]
+    L.pstt2_destroy.argtypes = [vp]
+    L.pstt2_destroy.restype = None
+    L.tt_error.argtypes = [ctypes.POINTER(TTCores), vp, st, ctypes.POINTER(ctypes.c_double), vp]
+    L.tt_reconstruct.argtypes = [ctypes.POINTER(TTCores), vp, st, i64, i64, vp]
+    L.tt_cores_copy.argtypes = [ctypes.POINTER(TTCores), ctypes.POINTER(TTCores), vp]
+    L.tt_cores_free.argtypes = [ctypes.POINTER(TTCores)]
+    L.tt_cores_free.restype = None
+    L.pstt2_last_error.argtypes = [vp]
+    L.pstt2_last_error.restype = ctypes.c_char_p
+    L.pstt2_version.argtypes = []
+    L.pstt2_version.restype = ctypes.c_char_p
+    for f in ("pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass",
+              "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_reset", "tt_error", "tt_reconstruct", "tt_cores_copy",
+              "pstt2_profile", "pstt2_profile_read"):
+        getattr(L, f).restype = st
+    _lib = L
+    return L
+
+
+def check(status: int, ctx=None) -> None:
+    if status != OK:
+        msg = lib().pstt2_last_error(ctx).decode(errors="replace")
+        raise PSTT2Error(status, msg)
+
+
+# Every symbol include/pstt2.h declares.
+EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass",
+           "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_profile", "pstt2_profile_read", "pstt2_reset",
+           "pstt2_destroy", "tt_error", "tt_reconstruct",
+           "tt_cores_copy", "tt_cores_free", "pstt2_last_error", "pstt2_version"]

@@ -1,0 +1,684 @@
+// C ABI of libpstt2 (declared in include/pstt2.h): context lifecycle, slab
+// bookkeeping and the host orchestration of the PSTT2-onepass pipeline.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace pstt2;
+
+static thread_local std::string g_tls_err;
+void pstt2_set_tls_error(const std::string& msg) { g_tls_err = msg; }
+
+namespace pstt2 {
+hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s);
+hipError_t tt_reconstruct_run(const tt_cores* c, void* out, int dtype, int64_t first, int64_t count, hipStream_t s);
+}
+
+struct pstt2_ctx {
+  pstt2_desc desc;
+  hipStream_t stream = nullptr;
+  int d = 0, m = 0, ell = 0, lp = 0, prec = 0, dtype = 0, ncu = 256;
+  int64_t n[PSTT2_MAX_D] = {};
+  int64_t Rk[PSTT2_MAX_D + 1] = {};  // Rk[k] = n_1 ... n_k
+  int64_t N = 0, R = 0, C = 0;       // entries; rows / columns of X_m
+  double* fac = nullptr;
+  int64_t psi_off[PSTT2_MAX_D] = {}, omega_off[PSTT2_MAX_D] = {};
+  double* Y = nullptr;   // R x ell column-major
+  double* Tt = nullptr;  // C x ell column-major (T_m transposed)
+  void* ypart = nullptr;
+  void* tpart = nullptr;
+  int gi = 1, gj_max = 1;
+  int* flag = nullptr;     // device: bit 0 non-finite sketch, bit 1 singular LS
+  int* piv_dev = nullptr;  // (d + 1) x ell pivots of every split
+  std::map<int64_t, int64_t> cover;  // first -> end of streamed ranges
+  int64_t covered = 0;
+  // recovery products kept for queries and the two-pass middle core
+  std::vector<double*> S;      // S[k], k = 1..m-1, R_k x ell (S[m] aliases Y)
+  std::vector<double*> Tk;     // Tk[k], k = m+1..d-1, C_k x ell (Tk[m] aliases Tt)
+  std::vector<double*> basis;  // Q_k (k < m) or P_k (k >= m)
+  int ranks[PSTT2_MAX_D + 1] = {};
+  bool recovered = false;
+  double* one = nullptr;       // device scalar 1.0 (Q_0 when m == 1)
+  double* om_tab = nullptr;    // Omega_m table, C x L4
+  int L4 = 4;
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_pool;
+  std::string err;
+};
+
+namespace {
+
+pstt2_status fail(pstt2_ctx* c, pstt2_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  pstt2_set_tls_error(msg);
+  return st;
+}
+
+pstt2_status hfail(pstt2_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? PSTT2_ENOMEM : PSTT2_EDEVICE, m);
+}
+
+#define HIPCK(ctx, call)                                      \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return hfail((ctx), e_, #call);     \
+  } while (0)
+
+void free_recovery(pstt2_ctx* c) {
+  for (size_t k = 0; k < c->S.size(); ++k)
+    if (c->S[k] && c->S[k] != c->Y) (void)hipFreeAsync(c->S[k], c->stream);
+  for (size_t k = 0; k < c->Tk.size(); ++k)
+    if (c->Tk[k] && c->Tk[k] != c->Tt) (void)hipFreeAsync(c->Tk[k], c->stream);
+  for (auto p : c->basis)
+    if (p) (void)hipFreeAsync(p, c->stream);
+  c->S.assign(c->d + 1, nullptr);
+  c->Tk.assign(c->d + 1, nullptr);
+  c->basis.assign(c->d + 1, nullptr);
+  c->recovered = false;
+}
+
+SketchArgs base_args(const pstt2_ctx* c) {
+  SketchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.R = c->R;
+  a.C = c->C;
+  a.ell = c->ell;
+  a.d = c->d;
+  a.m = c->m;
+  for (int q = 0; q < c->d; ++q) a.n[q] = (int32_t)c->n[q];
+  a.fac = c->fac;
+  for (int q = 0; q < PSTT2_MAX_D; ++q) {
+    a.psi_off[q] = c->psi_off[q];
+    a.omega_off[q] = c->omega_off[q];
+  }
+  a.ypart = c->ypart;
+  a.tpart = c->tpart;
+  a.gi_count = c->gi;
+  a.om_tab = c->om_tab;
+  a.L4 = c->L4;
+  return a;
+}
+
+pstt2_status check_range(pstt2_ctx* c, int64_t first, int64_t count) {
+  if (first < 0 || count < 0 || first + count > c->N)
+    return fail(c, PSTT2_EINVAL, "slab range outside the tensor");
+  if (first % c->n[0] != 0 || count % c->n[0] != 0)
+    return fail(c, PSTT2_EINVAL, "slab first/count must be multiples of n_1 (whole mode-1 fibres)");
+  if (count == 0) return PSTT2_OK;
+  auto it = c->cover.upper_bound(first);
+  if (it != c->cover.end() && it->first < first + count)
+    return fail(c, PSTT2_ESTATE, "slab overlaps an earlier slab");
+  if (it != c->cover.begin()) {
+    auto pv = std::prev(it);
+    if (pv->second > first) return fail(c, PSTT2_ESTATE, "slab overlaps an earlier slab");
+  }
+  return PSTT2_OK;
+}
+
+void add_cover(pstt2_ctx* c, int64_t first, int64_t count) {
+  if (count == 0) return;
+  c->cover[first] = first + count;
+  c->covered += count;
+}
+
+struct Piece {
+  const void* x;   // slab pointer
+  int64_t first;   // flat index of x[0]
+  int64_t count;
+};
+
+// Stream a list of slabs: partial columns one by one, whole columns batched.
+pstt2_status run_slabs(pstt2_ctx* c, const std::vector<Piece>& ps) {
+  const int esz = c->dtype == PSTT2_F64 ? 8 : 4;
+  const int64_t R = c->R;
+  std::vector<Seg> segs;
+  for (const Piece& p : ps) {
+    if (p.count == 0) continue;
+    const int64_t lo = p.first, hi = p.first + p.count;
+    const int64_t c0 = (lo + R - 1) / R, c1 = hi / R;   // whole columns [c0, c1)
+    const char* base = (const char*)p.x;
+    if (lo % R != 0) {   // head piece of column lo / R
+      const int64_t col = lo / R;
+      const int64_t r0 = lo % R, r1 = std::min<int64_t>(R, r0 + p.count);
+      SketchArgs a = base_args(c);
+      HIPCK(c, launch_partial_col(c->dtype, base, r0, r1, col, a, c->Y, c->Tt, c->stream));
+    }
+    if (c1 > c0) segs.push_back(Seg{base + (c0 * R - lo) * esz, c0, c1 - c0, 0});
+    if (hi % R != 0 && hi / R >= c0 && (lo / R != hi / R || lo % R == 0)) {   // tail piece
+      const int64_t col = hi / R;
+      SketchArgs a = base_args(c);
+      HIPCK(c, launch_partial_col(c->dtype, base + (col * R - lo) * esz, 0, hi % R, col, a, c->Y, c->Tt,
+                                  c->stream));
+    }
+  }
+  for (size_t s0 = 0; s0 < segs.size(); s0 += kMaxSeg) {
+    SketchArgs a = base_args(c);
+    const size_t s1 = std::min(segs.size(), s0 + kMaxSeg);
+    int64_t nch = 0;
+    a.nseg = (int32_t)(s1 - s0);
+    for (size_t i = s0; i < s1; ++i) {
+      Seg g = segs[i];
+      g.chunk0 = nch;
+      nch += (g.ncols + 15) / 16;
+      a.seg[i - s0] = g;
+    }
+    a.nchunks = nch;
+    a.gj_count = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nch, c->gj_max));
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (c->profile) {
+      if (c->ev_pool.empty()) {
+        HIPCK(c, hipEventCreate(&ev.first));
+        HIPCK(c, hipEventCreate(&ev.second));
+      } else {
+        ev = c->ev_pool.back();
+        c->ev_pool.pop_back();
+      }
+      HIPCK(c, hipEventRecord(ev.first, c->stream));
+    }
+    HIPCK(c, launch_sketch(c->prec, c->lp, a, c->stream));
+    if (c->profile) {
+      HIPCK(c, hipEventRecord(ev.second, c->stream));
+      c->ev_used.push_back(ev);
+    }
+    HIPCK(c, launch_reduce(c->prec, a, c->Y, c->Tt, c->flag, c->stream));
+  }
+  return PSTT2_OK;
+}
+
+__global__ void k_transpose_last(const double* P, int64_t rows, int r, double* G) {
+  // G_d(a, i) = P(i, a): P is rows x r column-major, G is r x rows column-major
+  const int64_t tot = rows * r;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(t % r);
+    const int64_t i = t / r;
+    G[t] = P[(int64_t)a * rows + i];
+  }
+}
+
+// smallest r with sum_{i>r} sigma_i^2 <= eps^2/(d-1) * sum sigma_i^2, at least 1
+int tolerance_rank(const double* s, int ell, double eps, int d) {
+  double tot = 0.0;
+  for (int i = 0; i < ell; ++i) tot += s[i] * s[i];
+  const double thr = eps * eps / (d - 1) * tot;
+  int rr = ell;
+  double tail = 0.0;
+  for (int i = ell - 1; i >= 0; --i) {
+    if (tail + s[i] * s[i] <= thr) {
+      tail += s[i] * s[i];
+      rr = i;
+    } else {
+      break;
+    }
+  }
+  return std::max(rr, 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pstt2_version(void) { return "pstt2-mi355x 0.2 (gfx950)"; }
+
+const char* pstt2_last_error(const pstt2_ctx* ctx) { return ctx ? ctx->err.c_str() : g_tls_err.c_str(); }
+
+pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** out) {
+  if (!desc || !out) return fail(nullptr, PSTT2_EINVAL, "null descriptor or output");
+  *out = nullptr;
+  const int d = desc->d;
+  if (d < 2 || d > PSTT2_MAX_D) return fail(nullptr, PSTT2_EINVAL, "d must be in [2, 32]");
+  if (desc->ell < 1 || desc->ell > PSTT2_MAX_ELL) return fail(nullptr, PSTT2_EINVAL, "ell must be in [1, 32]");
+  if (desc->dtype != PSTT2_F64 && desc->dtype != PSTT2_F32) return fail(nullptr, PSTT2_EINVAL, "bad dtype");
+  if (desc->prec < PSTT2_P_F64 || desc->prec > PSTT2_P_BF16X3) return fail(nullptr, PSTT2_EINVAL, "bad prec");
+  if (desc->dtype == PSTT2_F64 && desc->prec != PSTT2_P_F64)
+    return fail(nullptr, PSTT2_EINVAL, "FP64 tensors use PSTT2_P_F64 arithmetic");
+  if (desc->dtype == PSTT2_F32 && desc->prec == PSTT2_P_F64)
+    return fail(nullptr, PSTT2_EINVAL, "FP32 tensors use PSTT2_P_F32, PSTT2_P_BF16 or PSTT2_P_BF16X3");
+  if (desc->mid != PSTT2_MID_ONEPASS && desc->mid != PSTT2_MID_TWOPASS) return fail(nullptr, PSTT2_EINVAL, "bad mid");
+  if (!desc->drm_factors) return fail(nullptr, PSTT2_EINVAL, "drm_factors is required");
+  const bool tol = desc->ranks[0] <= 0;
+  if (tol && !(desc->eps > 0.0 && desc->eps < 1.0)) return fail(nullptr, PSTT2_EINVAL, "tolerance mode needs 0 < eps < 1");
+  int64_t N = 1;
+  for (int q = 0; q < d; ++q) {
+    if (desc->n[q] < 1) return fail(nullptr, PSTT2_EINVAL, "mode sizes must be >= 1");
+    if (desc->n[q] > (1 << 30)) return fail(nullptr, PSTT2_EINVAL, "mode size too large");
+    N *= desc->n[q];
+    if (N > (int64_t(1) << 46)) return fail(nullptr, PSTT2_EINVAL, "tensor too large");
+  }
+  if (!tol)
+    for (int k = 0; k < d - 1; ++k)
+      if (desc->ranks[k] < 1) return fail(nullptr, PSTT2_EINVAL, "ranks must be >= 1");
+
+  pstt2_ctx* c = new pstt2_ctx();
+  c->desc = *desc;
+  c->stream = (hipStream_t)hip_stream;
+  c->d = d;
+  c->m = (d + 1) / 2;
+  c->ell = desc->ell;
+  c->lp = desc->ell <= 16 ? 16 : 32;
+  c->prec = desc->prec;
+  c->dtype = desc->dtype;
+  c->Rk[0] = 1;
+  for (int q = 0; q < d; ++q) {
+    c->n[q] = desc->n[q];
+    c->Rk[q + 1] = c->Rk[q] * desc->n[q];
+  }
+  c->N = N;
+  c->R = c->Rk[c->m];
+  c->C = N / c->R;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (c->ncu <= 0) c->ncu = 256;
+
+  // factors: psi_1..psi_{d-1}, omega_2..omega_d
+  int64_t off = 0;
+  for (int q = 1; q <= d - 1; ++q) {
+    c->psi_off[q - 1] = off;
+    off += c->n[q - 1] * c->ell;
+  }
+  for (int q = 2; q <= d; ++q) {
+    c->omega_off[q - 1] = off;
+    off += c->n[q - 1] * c->ell;
+  }
+  auto bail = [&](hipError_t e, const char* w) {
+    pstt2_status st = hfail(c, e, w);
+    pstt2_destroy(c);
+    return st;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&c->fac, sizeof(double) * off)) != hipSuccess) return bail(e, "hipMalloc(factors)");
+  if ((e = hipMemcpy(c->fac, desc->drm_factors, sizeof(double) * off, hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(e, "hipMemcpy(factors)");
+  if ((e = hipMalloc(&c->Y, sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Y)");
+  if ((e = hipMalloc(&c->Tt, sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(T)");
+  if ((e = hipMalloc(&c->flag, sizeof(int))) != hipSuccess) return bail(e, "hipMalloc(flag)");
+  if ((e = hipMalloc(&c->piv_dev, sizeof(int) * (d + 1) * c->ell)) != hipSuccess) return bail(e, "hipMalloc(piv)");
+  if ((e = hipMalloc(&c->one, sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(one)");
+  const double one = 1.0;
+  if ((e = hipMemcpy(c->one, &one, sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "hipMemcpy");
+  int rows_per_block = 0, threads = 0;
+  sketch_geometry(c->prec, c->lp, &rows_per_block, &threads);
+  c->gi = (int)((c->R + rows_per_block - 1) / rows_per_block);
+  c->gj_max = std::max(1, c->ncu / c->gi);
+  const size_t psz = c->prec == PSTT2_P_F64 ? 8 : 4;
+  if ((e = hipMalloc(&c->ypart, psz * c->gj_max * c->ell * c->R)) != hipSuccess) return bail(e, "hipMalloc(ypart)");
+  if ((e = hipMalloc(&c->tpart, psz * c->gi * c->ell * c->C)) != hipSuccess) return bail(e, "hipMalloc(tpart)");
+  c->L4 = (c->ell + 3) / 4 * 4;
+  if ((e = hipMalloc(&c->om_tab, sizeof(double) * c->C * c->L4)) != hipSuccess) return bail(e, "hipMalloc(omega)");
+  if ((e = build_omega_table(base_args(c), c->L4, c->om_tab, c->stream)) != hipSuccess)
+    return bail(e, "omega table");
+  c->S.assign(d + 1, nullptr);
+  c->Tk.assign(d + 1, nullptr);
+  c->basis.assign(d + 1, nullptr);
+  pstt2_status st = pstt2_reset(c);
+  if (st != PSTT2_OK) {
+    pstt2_destroy(c);
+    return st;
+  }
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "create");
+  *out = c;
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_reset(pstt2_ctx* c) {
+  if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
+  free_recovery(c);
+  HIPCK(c, hipMemsetAsync(c->Y, 0, sizeof(double) * c->R * c->ell, c->stream));
+  HIPCK(c, hipMemsetAsync(c->Tt, 0, sizeof(double) * c->C * c->ell, c->stream));
+  HIPCK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+  c->cover.clear();
+  c->covered = 0;
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_profile(pstt2_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
+  c->profile = enable != 0;
+  if (!c->profile) {
+    for (auto& e : c->ev_used) c->ev_pool.push_back(e);
+    c->ev_used.clear();
+  }
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_profile_read(pstt2_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return fail(c, PSTT2_EINVAL, "null argument");
+  HIPCK(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (auto& e : c->ev_used) {
+    float ms = 0.0f;
+    HIPCK(c, hipEventElapsedTime(&ms, e.first, e.second));
+    tot += ms;
+    c->ev_pool.push_back(e);
+  }
+  *total_ms = tot;
+  *launches = (int64_t)c->ev_used.size();
+  c->ev_used.clear();
+  return PSTT2_OK;
+}
+
+void pstt2_destroy(pstt2_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev_used) c->ev_pool.push_back(e);
+  for (auto& e : c->ev_pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  free_recovery(c);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->fac);
+  (void)hipFree(c->Y);
+  (void)hipFree(c->Tt);
+  (void)hipFree(c->ypart);
+  (void)hipFree(c->tpart);
+  (void)hipFree(c->flag);
+  (void)hipFree(c->piv_dev);
+  (void)hipFree(c->one);
+  (void)hipFree(c->om_tab);
+  delete c;
+}
+
+pstt2_status pstt2_sketch(pstt2_ctx* c, const void* x_dev, int64_t first, int64_t count) {
+  if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
+  if (!x_dev && count > 0) return fail(c, PSTT2_EINVAL, "null slab pointer");
+  if (c->recovered) return fail(c, PSTT2_ESTATE, "sketch after recover: call pstt2_reset first");
+  pstt2_status st = check_range(c, first, count);
+  if (st != PSTT2_OK) return st;
+  st = run_slabs(c, {Piece{x_dev, first, count}});
+  if (st != PSTT2_OK) return st;
+  add_cover(c, first, count);
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_sketch_slabs(pstt2_ctx* c, int32_t nslabs, const void* const* xs, const int64_t* firsts,
+                                const int64_t* counts) {
+  if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
+  if (nslabs < 0 || (nslabs > 0 && (!xs || !firsts || !counts))) return fail(c, PSTT2_EINVAL, "bad slab arrays");
+  if (c->recovered) return fail(c, PSTT2_ESTATE, "sketch after recover: call pstt2_reset first");
+  // validate every slab (including overlaps among themselves) before launching
+  std::map<int64_t, int64_t> saved = c->cover;
+  int64_t saved_cov = c->covered;
+  std::vector<Piece> ps;
+  for (int s = 0; s < nslabs; ++s) {
+    pstt2_status st = (!xs[s] && counts[s] > 0) ? fail(c, PSTT2_EINVAL, "null slab pointer")
+                                                : check_range(c, firsts[s], counts[s]);
+    if (st != PSTT2_OK) {
+      c->cover = saved;
+      c->covered = saved_cov;
+      return st;
+    }
+    add_cover(c, firsts[s], counts[s]);
+    ps.push_back(Piece{xs[s], firsts[s], counts[s]});
+  }
+  pstt2_status st = run_slabs(c, ps);
+  if (st != PSTT2_OK) {
+    c->cover = saved;
+    c->covered = saved_cov;
+  }
+  return st;
+}
+
+pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
+  if (!c || !out) return fail(c, PSTT2_EINVAL, "null argument");
+  if (c->covered != c->N) return fail(c, PSTT2_ESTATE, "not every entry of X was streamed exactly once");
+  free_recovery(c);
+  const int d = c->d, m = c->m, ell = c->ell;
+  hipStream_t s = c->stream;
+  // (1) every split's sketch
+  c->S[m] = c->Y;
+  for (int k = m - 1; k >= 1; --k) {
+    HIPCK(c, hipMallocAsync((void**)&c->S[k], sizeof(double) * c->Rk[k] * ell, s));
+    HIPCK(c, derive_left(c->S[k + 1], c->S[k], c->Rk[k], (int)c->n[k], ell, c->fac + c->omega_off[k], s));
+  }
+  c->Tk[m] = c->Tt;
+  for (int k = m + 1; k <= d - 1; ++k) {
+    const int64_t Ck = c->N / c->Rk[k];
+    HIPCK(c, hipMallocAsync((void**)&c->Tk[k], sizeof(double) * Ck * ell, s));
+    HIPCK(c, derive_right(c->Tk[k - 1], c->Tk[k], Ck, (int)c->n[k - 1], ell, c->fac + c->psi_off[k - 1], s));
+  }
+  // (2) factor every sketch; the ranks come from the descriptor or, in
+  // tolerance mode, from the singular values (one host synchronisation)
+  std::vector<BasisWork*> work(d + 1, nullptr);
+  auto cleanup = [&]() {
+    for (auto w : work) basis_free(w);
+  };
+  const bool tol = c->desc.ranks[0] <= 0;
+  for (int k = 1; k <= d - 1; ++k) {
+    const int64_t Mk = k < m ? c->Rk[k] : c->N / c->Rk[k];
+    const double* A = k < m ? c->S[k] : c->Tk[k];
+    hipError_t e = basis_factor(A, Mk, ell, c->piv_dev + (int64_t)k * ell, tol, &work[k], s);
+    if (e != hipSuccess) {
+      cleanup();
+      return hfail(c, e, "basis_factor");
+    }
+  }
+  int r[PSTT2_MAX_D + 1];
+  r[0] = r[d] = 1;
+  std::vector<double> sv((size_t)(d + 1) * ell, 0.0);
+  if (tol) {
+    for (int k = 1; k <= d - 1; ++k) {
+      hipError_t e = hipMemcpyAsync(sv.data() + (size_t)k * ell, basis_sv(work[k]), sizeof(double) * ell,
+                                    hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) {
+        cleanup();
+        return hfail(c, e, "hipMemcpyAsync(sv)");
+      }
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      cleanup();
+      return hfail(c, e, "recover");
+    }
+  }
+  for (int k = 1; k <= d - 1; ++k) {
+    const int64_t cap = std::min<int64_t>({c->Rk[k], c->N / c->Rk[k], (int64_t)ell});
+    int rk;
+    if (!tol) {
+      rk = (int)std::min<int64_t>(c->desc.ranks[k - 1], cap);
+    } else {
+      int rmax = c->desc.rmax > 0 ? c->desc.rmax : ell;
+      rmax = std::min(rmax, std::max(1, ell - 2));
+      const int rr = tolerance_rank(sv.data() + (size_t)k * ell, ell, c->desc.eps, d);
+      rk = (int)std::min<int64_t>({(int64_t)rr, (int64_t)rmax, cap});
+    }
+    r[k] = rk;
+  }
+  // (3) bases
+  for (int k = 1; k <= d - 1; ++k) {
+    const int64_t Mk = k < m ? c->Rk[k] : c->N / c->Rk[k];
+    hipError_t e = hipMallocAsync((void**)&c->basis[k], sizeof(double) * Mk * r[k], s);
+    if (e == hipSuccess) e = basis_form_q(work[k], r[k], c->basis[k], s);
+    if (e != hipSuccess) {
+      cleanup();
+      return hfail(c, e, "basis_form_q");
+    }
+  }
+  cleanup();
+  for (int k = 0; k <= d; ++k) c->ranks[k] = r[k];
+  // (4) cores, one allocation based at core[0]
+  tt_cores tc;
+  std::memset(&tc, 0, sizeof(tc));
+  tc.d = d;
+  tc.owned = 1;
+  int64_t tot = 0;
+  for (int k = 0; k < d; ++k) {
+    tc.n[k] = c->n[k];
+    tot += (int64_t)r[k] * c->n[k] * r[k + 1];
+  }
+  for (int k = 0; k <= d; ++k) tc.r[k] = r[k];
+  double* base = nullptr;
+  HIPCK(c, hipMalloc(&base, sizeof(double) * tot));
+  int64_t o = 0;
+  for (int k = 0; k < d; ++k) {
+    tc.core[k] = base + o;
+    o += (int64_t)r[k] * c->n[k] * r[k + 1];
+  }
+  auto cfail = [&](hipError_t e, const char* w) {
+    tt_cores_free(&tc);
+    return hfail(c, e, w);
+  };
+  hipError_t e = hipSuccess;
+  for (int k = 1; k <= m - 1 && e == hipSuccess; ++k) {
+    if (k == 1)
+      e = hipMemcpyAsync(tc.core[0], c->basis[1], sizeof(double) * c->n[0] * r[1], hipMemcpyDeviceToDevice, s);
+    else
+      e = core_left(c->basis[k - 1], c->Rk[k - 1], r[k - 1], c->basis[k], (int)c->n[k - 1], r[k], tc.core[k - 1], s);
+  }
+  for (int k = m + 1; k <= d && e == hipSuccess; ++k) {
+    if (k == d) {
+      const int64_t rows = c->n[d - 1];
+      hipLaunchKernelGGL(k_transpose_last, dim3(64), dim3(256), 0, s, c->basis[d - 1], rows, r[d - 1], tc.core[d - 1]);
+      e = hipGetLastError();
+    } else {
+      const int64_t Cp = c->N / c->Rk[k - 1], Ck = c->N / c->Rk[k];
+      e = core_right(c->basis[k - 1], Cp, r[k - 1], c->basis[k], Ck, (int)c->n[k - 1], r[k], tc.core[k - 1], s);
+    }
+  }
+  if (e != hipSuccess) return cfail(e, "cores");
+  const double* Qprev = m >= 2 ? c->basis[m - 1] : c->one;
+  const int64_t Rprev = c->Rk[m - 1];
+  const int64_t nz = (int64_t)r[m - 1] * c->n[m - 1];
+  if (c->desc.mid == PSTT2_MID_ONEPASS) {
+    double *Z = nullptr, *A = nullptr;
+    e = hipMallocAsync((void**)&Z, sizeof(double) * nz * ell, s);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&A, sizeof(double) * r[m] * ell, s);
+    if (e == hipSuccess) e = middle_z(Qprev, Rprev, r[m - 1], c->Y, c->R, (int)c->n[m - 1], ell, Z, s);
+    SketchArgs geo = base_args(c);
+    if (e == hipSuccess) e = middle_a(c->basis[m], c->C, r[m], geo, c->prec, A, s);
+    if (e == hipSuccess) e = middle_ls(Z, nz, A, r[m], ell, tc.core[m - 1], c->flag, s);
+    (void)hipFreeAsync(Z, s);
+    (void)hipFreeAsync(A, s);
+  } else {
+    e = hipMemsetAsync(tc.core[m - 1], 0, sizeof(double) * nz * r[m], s);
+  }
+  if (e != hipSuccess) return cfail(e, "middle core");
+  // (5) the single completion point: non-finite sketches, singular LS
+  int hflag = 0;
+  e = hipMemcpyAsync(&hflag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cfail(e, "recover");
+  if (hflag & 1) {
+    tt_cores_free(&tc);
+    return fail(c, PSTT2_ENUMERIC, "non-finite values in the sketches (NaN/Inf in X)");
+  }
+  if (hflag & 2) {
+    tt_cores_free(&tc);
+    return fail(c, PSTT2_ENUMERIC, "rank-deficient least-squares system for the middle core");
+  }
+  *out = tc;
+  c->recovered = true;
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_middle_pass(pstt2_ctx* c, tt_cores* cores, const void* x_dev, int64_t first, int64_t count) {
+  if (!c || !cores) return fail(c, PSTT2_EINVAL, "null argument");
+  if (c->desc.mid != PSTT2_MID_TWOPASS || !c->recovered)
+    return fail(c, PSTT2_ESTATE, "middle pass needs a two-pass context after pstt2_recover");
+  if (first < 0 || count < 0 || first + count > c->N) return fail(c, PSTT2_EINVAL, "slab range outside the tensor");
+  if (first % c->n[0] != 0 || count % c->n[0] != 0) return fail(c, PSTT2_EINVAL, "slab must hold whole mode-1 fibres");
+  const int m = c->m;
+  const double* Qprev = m >= 2 ? c->basis[m - 1] : c->one;
+  HIPCK(c, middle_twopass(c->dtype, x_dev, first, count, c->Rk[m - 1], (int)c->n[m - 1], c->C, Qprev,
+                          c->ranks[m - 1], c->basis[m], c->ranks[m], cores->core[m - 1], c->stream));
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_get_sketch(pstt2_ctx* c, int32_t which, int32_t k, double* host_out, int64_t* rows,
+                              int64_t* cols) {
+  if (!c || !rows || !cols) return fail(c, PSTT2_EINVAL, "null argument");
+  if (!c->recovered) return fail(c, PSTT2_ESTATE, "sketches are available after pstt2_recover");
+  const double* p = nullptr;
+  if (which == 0 && k >= 1 && k <= c->m) {
+    p = c->S[k];
+    *rows = c->Rk[k];
+  } else if (which == 1 && k >= c->m && k <= c->d - 1) {
+    p = c->Tk[k];
+    *rows = c->N / c->Rk[k];
+  } else {
+    return fail(c, PSTT2_EINVAL, "no such sketch");
+  }
+  *cols = c->ell;
+  if (host_out) {
+    HIPCK(c, hipMemcpyAsync(host_out, p, sizeof(double) * (*rows) * c->ell, hipMemcpyDeviceToHost, c->stream));
+    HIPCK(c, hipStreamSynchronize(c->stream));
+  }
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_get_pivots(pstt2_ctx* c, int32_t k, int32_t* host_piv) {
+  if (!c || !host_piv) return fail(c, PSTT2_EINVAL, "null argument");
+  if (!c->recovered || k < 1 || k > c->d - 1) return fail(c, PSTT2_ESTATE, "no pivots for this split");
+  HIPCK(c, hipMemcpyAsync(host_piv, c->piv_dev + (int64_t)k * c->ell, sizeof(int) * c->ell, hipMemcpyDeviceToHost,
+                          c->stream));
+  HIPCK(c, hipStreamSynchronize(c->stream));
+  return PSTT2_OK;
+}
+
+pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream) {
+  if (!src || !dst || src->d != dst->d || src->d < 2 || src->d > PSTT2_MAX_D)
+    return fail(nullptr, PSTT2_EINVAL, "bad cores");
+  for (int k = 0; k < src->d; ++k)
+    if (src->n[k] != dst->n[k] || src->r[k] != dst->r[k] || src->r[k + 1] != dst->r[k + 1] || !src->core[k] ||
+        !dst->core[k])
+      return fail(nullptr, PSTT2_EINVAL, "core shapes differ");
+  hipStream_t s = (hipStream_t)hip_stream;
+  for (int k = 0; k < src->d; ++k) {
+    hipError_t e = hipMemcpyAsync(dst->core[k], src->core[k], sizeof(double) * src->r[k] * src->n[k] * src->r[k + 1],
+                                  hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hfail(nullptr, e, "tt_cores_copy");
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hfail(nullptr, e, "tt_cores_copy");
+  return PSTT2_OK;
+}
+
+void tt_cores_free(tt_cores* t) {
+  if (!t) return;
+  if (t->owned && t->d >= 1) (void)hipFree(t->core[0]);   // one allocation, based at core[0]
+  std::memset(t, 0, sizeof(*t));
+}
+
+static pstt2_status check_cores(const tt_cores* t) {
+  if (!t || t->d < 2 || t->d > PSTT2_MAX_D) return fail(nullptr, PSTT2_EINVAL, "bad cores");
+  if (t->r[0] != 1 || t->r[t->d] != 1) return fail(nullptr, PSTT2_EINVAL, "boundary ranks must be 1");
+  for (int k = 0; k < t->d; ++k) {
+    if (!t->core[k] || t->n[k] < 1 || t->r[k + 1] < 1) return fail(nullptr, PSTT2_EINVAL, "bad core");
+    if (t->r[k + 1] > PSTT2_MAX_ELL) return fail(nullptr, PSTT2_EINVAL, "rank above 32 not supported");
+  }
+  return PSTT2_OK;
+}
+
+pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* rel_err, void* hip_stream) {
+  pstt2_status st = check_cores(cores);
+  if (st != PSTT2_OK) return st;
+  if (!x_dev || !rel_err) return fail(nullptr, PSTT2_EINVAL, "null argument");
+  double e2x2[2] = {0, 0};
+  hipError_t e = tt_error_run(cores, x_dev, dtype, e2x2, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hfail(nullptr, e, "tt_error");
+  *rel_err = e2x2[1] > 0 ? std::sqrt(e2x2[0] / e2x2[1]) : (e2x2[0] > 0 ? INFINITY : 0.0);
+  if (!std::isfinite(*rel_err)) return fail(nullptr, PSTT2_ENUMERIC, "non-finite error");
+  return PSTT2_OK;
+}
+
+pstt2_status tt_reconstruct(const tt_cores* cores, void* x_out_dev, pstt2_dtype dtype, int64_t first, int64_t count,
+                            void* hip_stream) {
+  pstt2_status st = check_cores(cores);
+  if (st != PSTT2_OK) return st;
+  int64_t N = 1;
+  for (int k = 0; k < cores->d; ++k) N *= cores->n[k];
+  if (first < 0 || count < 0 || first + count > N) return fail(nullptr, PSTT2_EINVAL, "range outside the tensor");
+  if (!x_out_dev && count > 0) return fail(nullptr, PSTT2_EINVAL, "null output");
+  hipError_t e = tt_reconstruct_run(cores, x_out_dev, dtype, first, count, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hfail(nullptr, e, "tt_reconstruct");
+  return PSTT2_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal declarations shared by the translation units of libpstt2.
+// Not part of the public ABI (include/pstt2.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pstt2.h"
+
+namespace pstt2 {
+
+constexpr int kMaxSeg = 48;   // slabs per sketch launch
+
+// One run of whole columns of the middle unfolding X_m held in one buffer.
+struct Seg {
+  const void* ptr;   // first entry of the run (column gcol0, row 0)
+  int64_t gcol0;     // global column index of its first column
+  int64_t ncols;     // number of columns
+  int64_t chunk0;    // index of its first 16-column chunk in the launch's chunk list
+};
+
+// Everything a sketch launch needs; passed by value as the kernel argument.
+struct SketchArgs {
+  int64_t R;         // rows of X_m: n_1 ... n_m
+  int64_t nchunks;   // chunks in this launch
+  int32_t ell;       // sketch size
+  int32_t gi_count;  // row blocks
+  int32_t gj_count;  // column groups
+  int32_t d, m;
+  int32_t nseg;
+  int32_t n[PSTT2_MAX_D];
+  const double* fac;           // FP64 factors, device
+  int64_t psi_off[PSTT2_MAX_D];    // offset of psi_q (q = 1..d-1) at index q-1
+  int64_t omega_off[PSTT2_MAX_D];  // offset of omega_q (q = 2..d) at index q-1
+  void* ypart;       // [gj][c][row], ell columns
+  void* tpart;       // [gi][a][gcol], ell rows, indexed by global column
+  int64_t C;         // columns of X_m (for the tpart stride)
+  const double* om_tab;  // Omega_m(col, c) table, C x L4, FP64
+  int32_t L4;            // its row stride: ell rounded up to a multiple of 4
+  Seg seg[kMaxSeg];
+};
+
+// Launch the streaming dual-sketch kernel for the configured precision.
+hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s);
+// Build the Omega_m table (C x L4, FP64) from the factors.
+hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream_t s);
+// Per-precision launch geometry.
+void sketch_geometry(int prec, int lp, int* rows_per_block, int* threads);
+// Sum the tile partials of one launch into the FP64 accumulators (fixed order).
+hipError_t launch_reduce(int prec, const SketchArgs& a, double* Y, double* Tt, int* flag, hipStream_t s);
+// FP64 contribution of one partial column (rows [r0, r1) of global column gcol).
+hipError_t launch_partial_col(int dtype, const void* x, int64_t r0, int64_t r1, int64_t gcol,
+                              const SketchArgs& a, double* Y, double* Tt, hipStream_t s);
+
+// Recovery building blocks (recover.hip); all FP64, column-major.
+hipError_t derive_left(const double* Sin, double* Sout, int64_t Rk, int nk1, int ell, const double* omega,
+                       hipStream_t s);
+hipError_t derive_right(const double* Tin, double* Tout, int64_t Ck, int nk, int ell, const double* psi,
+                        hipStream_t s);
+
+// Orthonormal basis of range(A) for an M x ell matrix by TSQR + pivoted QR of R.
+struct BasisWork;
+// Phase 1 (async): factor A (TSQR, CPQR of the final R into piv_dev, singular
+// values of R when want_sv).
+hipError_t basis_factor(const double* A, int64_t M, int ell, int* piv_dev, bool want_sv, BasisWork** w,
+                        hipStream_t s);
+// Device pointer to the ell singular values (descending) of phase 1, or null.
+const double* basis_sv(BasisWork* w);
+// Phase 2 (async): Q (M x r) = first r columns of the sign-fixed pivoted factor.
+hipError_t basis_form_q(BasisWork* w, int r, double* Q, hipStream_t s);
+// Release (stream-ordered).
+void basis_free(BasisWork* w);
+
+hipError_t core_left(const double* Qprev, int64_t Rprev, int rprev, const double* Qk, int nk, int rk, double* G,
+                     hipStream_t s);
+hipError_t core_right(const double* Pprev, int64_t Cprev, int rprev, const double* Pk, int64_t Ck, int nk, int rk,
+                      double* G, hipStream_t s);
+hipError_t middle_z(const double* Qprev, int64_t Rprev, int rprev, const double* Y, int64_t Rm, int nm, int ell,
+                    double* Z, hipStream_t s);
+hipError_t middle_a(const double* Pm, int64_t Cm, int rm, const SketchArgs& geo, int prec, double* A,
+                    hipStream_t s);
+hipError_t middle_ls(const double* Z, int64_t nz, const double* A, int rm, int ell, double* G, int* flag,
+                     hipStream_t s);
+hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count, int64_t Rprev, int nm,
+                          int64_t Cm, const double* Qprev, int rprev, const double* Pm, int rm, double* G,
+                          hipStream_t s);
+
+// TT evaluation (tt_eval.hip).
+hipError_t tt_interfaces(const tt_cores* c, int split, double** L, double** Rt, hipStream_t s);
+}  // namespace pstt2
+
+// Thread-local error text for calls without a context.
+void pstt2_set_tls_error(const std::string& msg);

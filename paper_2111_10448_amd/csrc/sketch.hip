@@ -1,0 +1,762 @@
+// Streaming dual sketch of the middle unfolding (PSTT2-onepass, Section 3.2;
+// Algorithm "parsketch": every sketch from a single read of each sub-tensor).
+//
+// For a tile X(I, J) of the middle unfolding X_m (column-major, leading
+// dimension R = n_1...n_m) the kernel adds
+//     Y_R(I, :) += X(I, J) Omega_m(J, :)        (right sketch, ell columns)
+//     T_m(:, J) += Psi_m(I, :)^T X(I, J)         (left sketch, ell rows)
+// where the Khatri-Rao DRM rows are products of per-mode Gaussian factors
+// (equation "sketch_orig"): Omega_m(j, c) = prod_{q>m} omega_q(j_q, c),
+// Psi_m(i, a) = prod_{q<=m} psi_q(i_q, a).
+//
+// Work decomposition (one workgroup = 8 waves of 64 lanes):
+//   * a workgroup owns a block of 8*RW consecutive rows and a contiguous share of
+//     the launch's 16-column chunks; each wave owns RW of the rows;
+//   * per chunk a wave loads its RW x 16 tile with 16-byte coalesced loads,
+//     stages it in a wave-private LDS tile, and runs matrix-core (MFMA) tiles
+//       right sketch: Y(rows, ell) += X(rows, 16 cols) * Omega(16 cols, ell)
+//       left sketch : T(ell, 16 cols) = Psi(rows, ell)^T * X(rows, 16 cols);
+//   * Y accumulates in registers over the workgroup's whole column share and is
+//     written once as a partial; T of the 8 waves is summed through LDS and
+//     written per chunk as a partial (one per row block);
+//   * Psi rows are stationary (computed once per workgroup from the factors);
+//     Omega rows of a chunk are built cooperatively into LDS two chunks ahead.
+// A separate kernel sums the partials in a fixed order into the FP64 sketches,
+// so results are bitwise reproducible.
+#include "internal.h"
+
+namespace pstt2 {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
+
+constexpr int NW = 8;   // waves per workgroup
+constexpr int KC = 16;  // columns per chunk
+
+// Round-to-nearest-even FP32 -> BF16 (bit pattern in the low 16 bits).
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi); packed as hi | lo << 16.
+__device__ __forceinline__ uint32_t split_bf16(float f) {
+  uint32_t h = bf16_rne(f);
+  float hf = __uint_as_float(h << 16);
+  uint32_t l = bf16_rne(f - hf);
+  return h | (l << 16);
+}
+
+template <int PREC>
+struct Eng;
+template <>
+struct Eng<P_F64> {
+  using elem = double;   // X in HBM
+  using lds_t = double;  // X and Omega in LDS
+  using acc = double;
+  using accv = d4;
+  using part = double;   // partial sums written to HBM
+  static constexpr int KPL = 1, KSTEP = 4, RW = 64, VEC = 2, PAD = 2;
+};
+template <>
+struct Eng<P_F32> {
+  using elem = float;
+  using lds_t = float;
+  using acc = float;
+  using accv = f4;
+  using part = float;
+  static constexpr int KPL = 1, KSTEP = 4, RW = 128, VEC = 4, PAD = 4;
+};
+template <>
+struct Eng<P_BF16> {
+  using elem = float;
+  using lds_t = uint32_t;  // packed bf16 hi | lo << 16
+  using acc = float;
+  using accv = f4;
+  using part = float;
+  static constexpr int KPL = 4, KSTEP = 16, RW = 128, VEC = 4, PAD = 4;
+};
+template <>
+struct Eng<P_BF16X3> : Eng<P_BF16> {};
+
+template <int PREC>
+__device__ __forceinline__ typename Eng<PREC>::lds_t to_lds(typename Eng<PREC>::elem v);
+template <>
+__device__ __forceinline__ double to_lds<P_F64>(double v) { return v; }
+template <>
+__device__ __forceinline__ float to_lds<P_F32>(float v) { return v; }
+template <>
+__device__ __forceinline__ uint32_t to_lds<P_BF16>(float v) { return bf16_rne(v); }
+template <>
+__device__ __forceinline__ uint32_t to_lds<P_BF16X3>(float v) { return split_bf16(v); }
+
+// DRM value (FP64 product of factors) converted to the LDS representation.
+template <int PREC>
+__device__ __forceinline__ typename Eng<PREC>::lds_t drm_to_lds(double v) {
+  if constexpr (PREC == P_F64) return v;
+  else if constexpr (PREC == P_F32) return (float)v;
+  else if constexpr (PREC == P_BF16) return bf16_rne((float)v);
+  else return split_bf16((float)v);
+}
+
+// Row of element v of a lane's 16x16 MFMA accumulator tile (column = lane % 16).
+// FP64 16x16x4 places element v at row 4*v + lane/16; the FP32-accumulating
+// 16x16 instructions at row 4*(lane/16) + v.
+template <int PREC>
+__device__ __forceinline__ int acc_row(int g4, int v) {
+  return PREC == P_F64 ? 4 * v + g4 : 4 * g4 + v;
+}
+
+__device__ __forceinline__ void unpack4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, s4& hi, s4& lo) {
+  hi = s4{(short)(a & 0xffff), (short)(b & 0xffff), (short)(c & 0xffff), (short)(d & 0xffff)};
+  lo = s4{(short)(a >> 16), (short)(b >> 16), (short)(c >> 16), (short)(d >> 16)};
+}
+
+// Psi_m(row, a) for a global row of X_m (0 outside the matrix / sketch).
+__device__ __forceinline__ double psi_row(const SketchArgs& A, int64_t row, int a) {
+  if (row >= A.R || a >= A.ell) return 0.0;
+  double v = 1.0;
+  int64_t r = row;
+  for (int q = 1; q <= A.m; ++q) {
+    int64_t nq = A.n[q - 1];
+    int64_t iq = r % nq;
+    r /= nq;
+    v *= A.fac[A.psi_off[q - 1] + iq * A.ell + a];
+  }
+  return v;
+}
+
+// Omega_m(gcol, c) for a global column of X_m.
+__device__ __forceinline__ double omega_col(const SketchArgs& A, int64_t gcol, int c) {
+  double v = 1.0;
+  int64_t r = gcol;
+  for (int q = A.m + 1; q <= A.d; ++q) {
+    int64_t nq = A.n[q - 1];
+    int64_t iq = r % nq;
+    r /= nq;
+    v *= A.fac[A.omega_off[q - 1] + iq * A.ell + c];
+  }
+  return v;
+}
+
+struct ChunkInfo {
+  const char* ptr;   // column 0 of the chunk's segment
+  int64_t lcol0;     // first column of the chunk within its segment
+  int64_t gcol0;     // global column of the chunk's first column
+  int ncols;         // valid columns (<= KC)
+};
+
+__device__ __forceinline__ ChunkInfo chunk_info(const SketchArgs& A, int64_t ci) {
+  int s = 0;
+  while (s + 1 < A.nseg && A.seg[s + 1].chunk0 <= ci) ++s;
+  ChunkInfo c;
+  c.ptr = (const char*)A.seg[s].ptr;
+  c.lcol0 = (ci - A.seg[s].chunk0) * KC;
+  c.gcol0 = A.seg[s].gcol0 + c.lcol0;
+  int64_t left = A.seg[s].ncols - c.lcol0;
+  c.ncols = (int)(left < KC ? left : KC);
+  return c;
+}
+
+template <int PREC, int LP, bool ALIGNED>
+__global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
+  using E = Eng<PREC>;
+  using elem = typename E::elem;
+  using lds_t = typename E::lds_t;
+  using acc = typename E::acc;
+  using accv = typename E::accv;
+  using part = typename E::part;
+  constexpr int RW = E::RW;
+  constexpr int ST = RW + E::PAD;   // LDS column stride of the X tile (elements)
+  constexpr int MT = RW / 16;       // row tiles per wave (right sketch)
+  constexpr int NT = LP / 16;       // ell tiles
+  constexpr int KT = RW / E::KSTEP; // K steps over rows (left sketch)
+  constexpr int VEC = E::VEC;       // elements per 16-byte load
+  constexpr int NLD = KC * RW / (64 * VEC);  // 16-byte loads per lane per chunk
+
+  __shared__ lds_t Xl[NW][KC * ST];
+  __shared__ acc Tred[2][NW][LP * KC];
+  __shared__ lds_t Om[3][KC * LP];
+
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int gi = blockIdx.x % A.gi_count;
+  const int gj = blockIdx.x / A.gi_count;
+  const int64_t row0w = (int64_t)gi * (NW * RW) + (int64_t)w * RW;
+  const int64_t cb = (int64_t)gj * A.nchunks / A.gj_count;
+  const int64_t ce = (int64_t)(gj + 1) * A.nchunks / A.gj_count;
+  const int l16 = lane & 15, g4 = lane >> 4;
+
+  // ---- stationary left-DRM operand (A operand of the left-sketch MFMA) ----
+  // element [a][row] with a = 16*mt + l16 and row = K index
+  typename std::conditional<E::KPL == 1, lds_t, s4>::type psiA[KT][NT];
+  s4 psiL[(E::KPL == 1) ? 1 : KT][(E::KPL == 1) ? 1 : NT];
+  (void)psiL;
+#pragma unroll
+  for (int ks = 0; ks < KT; ++ks) {
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      const int a = 16 * mt + l16;
+      if constexpr (E::KPL == 1) {
+        psiA[ks][mt] = drm_to_lds<PREC>(psi_row(A, row0w + E::KSTEP * ks + g4, a));
+      } else {
+        uint32_t p[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) p[v] = drm_to_lds<PREC>(psi_row(A, row0w + 16 * ks + 4 * g4 + v, a));
+        s4 hi, lo;
+        unpack4(p[0], p[1], p[2], p[3], hi, lo);
+        psiA[ks][mt] = hi;
+        psiL[ks][mt] = lo;
+      }
+    }
+  }
+
+  auto build_omega = [&](int buf, int64_t ci) {
+    const int t = threadIdx.x;
+    if (t < KC * LP) {
+      const int col = t / LP, c = t % LP;
+      lds_t v = drm_to_lds<PREC>(0.0);
+      if (ci < ce) {
+        ChunkInfo ch = chunk_info(A, ci);
+        if (col < ch.ncols && c < A.ell) v = drm_to_lds<PREC>(A.om_tab[(ch.gcol0 + col) * A.L4 + c]);
+      }
+      Om[buf][col * LP + c] = v;
+    }
+  };
+
+  // ---- global loads of one chunk (16-byte, coalesced along rows) ----
+  elem xr[NLD][VEC];
+  auto load_chunk = [&](int64_t ci) {
+    ChunkInfo ch = chunk_info(A, ci);
+    const elem* base = (const elem*)ch.ptr;
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int cc = i * (64 * VEC / RW) + lane / (RW / VEC);
+      const int r = (lane % (RW / VEC)) * VEC;
+      const int64_t row = row0w + r;
+      const bool colok = cc < ch.ncols;
+      const elem* p = base + (ch.lcol0 + cc) * A.R + row;
+      if constexpr (ALIGNED) {
+        if (colok && row < A.R) {
+          if constexpr (VEC == 2) {
+            const double2 v = *(const double2*)p;
+            xr[i][0] = v.x;
+            xr[i][1] = v.y;
+          } else {
+            const float4 v = *(const float4*)p;
+            xr[i][0] = v.x;
+            xr[i][1] = v.y;
+            xr[i][2] = v.z;
+            xr[i][3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) xr[i][v] = 0;
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) xr[i][v] = (colok && row + v < A.R) ? p[v] : (elem)0;
+      }
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int cc = i * (64 * VEC / RW) + lane / (RW / VEC);
+      const int r = (lane % (RW / VEC)) * VEC;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = to_lds<PREC>(xr[i][v]);
+    }
+  };
+
+  auto reduce_t = [&](int buf, int64_t ci) {
+    const int t = threadIdx.x;
+    if (t < LP * KC) {
+      const int a = t / KC, col = t % KC;
+      acc s = 0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) s += Tred[buf][ww][a * KC + col];
+      ChunkInfo ch = chunk_info(A, ci);
+      if (a < A.ell && col < ch.ncols)
+        ((part*)A.tpart)[((int64_t)gi * A.ell + a) * A.C + ch.gcol0 + col] = (part)s;
+    }
+  };
+
+  accv yacc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) yacc[mt][nt] = accv{0, 0, 0, 0};
+
+  if (cb < ce) {
+    build_omega(0, cb);
+    build_omega(1, cb + 1);
+    load_chunk(cb);
+  }
+
+  int it = 0;
+  for (int64_t ci = cb; ci < ce; ++ci, ++it) {
+    // (a) stage this chunk in the wave's LDS tile; prefetch the next one
+    store_chunk();
+    if (ci + 1 < ce) load_chunk(ci + 1);
+    // (b) one barrier per chunk
+    __syncthreads();
+    // (c) finish the previous chunk's left sketch; build Omega two chunks ahead
+    if (it >= 1) reduce_t((it - 1) & 1, ci - 1);
+    build_omega((it + 2) % 3, ci + 2);
+    // (d) matrix-core tiles
+    const lds_t* xw = Xl[w];
+    const lds_t* om = Om[it % 3];
+    // right sketch: Y(rows, ell) += X(rows, cols) Omega(cols, ell)
+    if constexpr (E::KPL == 1) {
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        lds_t b[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) b[nt] = om[(4 * ks + g4) * LP + 16 * nt + l16];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const lds_t a = xw[(4 * ks + g4) * ST + 16 * mt + l16];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            if constexpr (PREC == P_F64)
+              yacc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[nt], yacc[mt][nt], 0, 0, 0);
+            else
+              yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nt], yacc[mt][nt], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      s4 bh[NT], bl[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        unpack4(om[(4 * g4 + 0) * LP + 16 * nt + l16], om[(4 * g4 + 1) * LP + 16 * nt + l16],
+                om[(4 * g4 + 2) * LP + 16 * nt + l16], om[(4 * g4 + 3) * LP + 16 * nt + l16], bh[nt], bl[nt]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        s4 ah, al;
+        const int r = 16 * mt + l16;
+        unpack4(xw[(4 * g4 + 0) * ST + r], xw[(4 * g4 + 1) * ST + r], xw[(4 * g4 + 2) * ST + r],
+                xw[(4 * g4 + 3) * ST + r], ah, al);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          if constexpr (PREC == P_BF16X3) {
+            yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[nt], yacc[mt][nt], 0, 0, 0);
+            yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[nt], yacc[mt][nt], 0, 0, 0);
+          }
+          yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[nt], yacc[mt][nt], 0, 0, 0);
+        }
+      }
+    }
+    // left sketch: T(ell, cols) = Psi(rows, ell)^T X(rows, cols)
+    accv tacc[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) tacc[mt] = accv{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KT; ++ks) {
+      if constexpr (E::KPL == 1) {
+        const lds_t b = xw[l16 * ST + 4 * ks + g4];
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          if constexpr (PREC == P_F64)
+            tacc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
+          else
+            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
+        }
+      } else {
+        const u4 q = *(const u4*)&xw[l16 * ST + 16 * ks + 4 * g4];
+        s4 bh, bl;
+        unpack4(q.x, q.y, q.z, q.w, bh, bl);
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          if constexpr (PREC == P_BF16X3) {
+            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiL[ks][mt], bh, tacc[mt], 0, 0, 0);
+            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], bl, tacc[mt], 0, 0, 0);
+          }
+          tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], bh, tacc[mt], 0, 0, 0);
+        }
+      }
+    }
+    acc* tr = Tred[it & 1][w];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tr[(16 * mt + acc_row<PREC>(g4, v)) * KC + l16] = tacc[mt][v];
+  }
+  __syncthreads();
+  if (it >= 1) reduce_t((it - 1) & 1, ce - 1);
+
+  // ---- right-sketch partial of this workgroup ----
+  part* yp = (part*)A.ypart;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0w + 16 * mt + acc_row<PREC>(g4, v);
+        const int c = 16 * nt + l16;
+        if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = (part)yacc[mt][nt][v];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 kernel with the sketch size covered exactly: ell (rounded up to a
+// multiple of 4) = 16*NQ + 4*NS.  The 16-wide part of each side runs on
+// 16x16x4 FP64 MFMA tiles, the remaining 4-wide groups on the 4-block 4x4x4
+// FP64 MFMA, whose X operands have the same lane layout (A: row lane%16,
+// k lane/16; B: k lane/16, column lane%16), so one LDS read feeds both.
+// Output layouts: 16x16x4 element v of lane l at (4v + l/16, l%16); 4x4x4
+// block b = (l/4)%4 at (l/16, l%4) of that block.
+// ---------------------------------------------------------------------------
+template <int L4, bool ALIGNED>
+__global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
+  constexpr int RW = 64;
+  constexpr int ST = RW + 2;
+  constexpr int NQ = L4 / 16;          // 16-wide tiles
+  constexpr int NS = (L4 % 16) / 4;    // 4-wide groups
+  constexpr int KT = RW / 4;           // K steps over rows (left sketch)
+  constexpr int NLD = KC * RW / (64 * 2);
+  static_assert(L4 % 4 == 0 && L4 >= 4, "ell padded to a multiple of 4");
+
+  __shared__ double Xl[NW][KC * ST];
+  __shared__ double Tred[2][NW][L4 * KC];
+  __shared__ double Om[3][KC * L4];
+
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int gi = blockIdx.x % A.gi_count;
+  const int gj = blockIdx.x / A.gi_count;
+  const int64_t row0w = (int64_t)gi * (NW * RW) + (int64_t)w * RW;
+  const int64_t cb = (int64_t)gj * A.nchunks / A.gj_count;
+  const int64_t ce = (int64_t)(gj + 1) * A.nchunks / A.gj_count;
+  const int l16 = lane & 15, g4 = lane >> 4, l4 = lane & 3, blk = (lane >> 2) & 3;
+
+  // stationary left-DRM operands: Psi(row0w + 4 ks + g4, a)
+  double psiq[KT][NQ > 0 ? NQ : 1];
+  double psis[KT][NS > 0 ? NS : 1];
+#pragma unroll
+  for (int ks = 0; ks < KT; ++ks) {
+    const int64_t row = row0w + 4 * ks + g4;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) psiq[ks][q] = psi_row(A, row, 16 * q + l16);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) psis[ks][s] = psi_row(A, row, 16 * NQ + 4 * s + l4);
+  }
+
+  auto build_omega = [&](int buf, int64_t ci) {
+    const int t = threadIdx.x;
+    if (t < KC * L4) {
+      const int col = t / L4, c = t % L4;
+      double v = 0.0;
+      if (ci < ce) {
+        ChunkInfo ch = chunk_info(A, ci);
+        if (col < ch.ncols && c < A.ell) v = A.om_tab[(ch.gcol0 + col) * A.L4 + c];
+      }
+      Om[buf][col * L4 + c] = v;
+    }
+  };
+
+  double xr[NLD][2];
+  auto load_chunk = [&](int64_t ci) {
+    ChunkInfo ch = chunk_info(A, ci);
+    const double* base = (const double*)ch.ptr;
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int cc = 2 * i + (lane >> 5);
+      const int r = (lane & 31) * 2;
+      const int64_t row = row0w + r;
+      const bool colok = cc < ch.ncols;
+      const double* p = base + (ch.lcol0 + cc) * A.R + row;
+      if constexpr (ALIGNED) {
+        if (colok && row < A.R) {
+          const double2 v = *(const double2*)p;
+          xr[i][0] = v.x;
+          xr[i][1] = v.y;
+        } else {
+          xr[i][0] = xr[i][1] = 0.0;
+        }
+      } else {
+        xr[i][0] = (colok && row < A.R) ? p[0] : 0.0;
+        xr[i][1] = (colok && row + 1 < A.R) ? p[1] : 0.0;
+      }
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int cc = 2 * i + (lane >> 5);
+      const int r = (lane & 31) * 2;
+      Xl[w][cc * ST + r] = xr[i][0];
+      Xl[w][cc * ST + r + 1] = xr[i][1];
+    }
+  };
+  auto reduce_t = [&](int buf, int64_t ci) {
+    const int t = threadIdx.x;
+    if (t < L4 * KC) {
+      const int a = t / KC, col = t % KC;
+      double s = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) s += Tred[buf][ww][a * KC + col];
+      ChunkInfo ch = chunk_info(A, ci);
+      if (a < A.ell && col < ch.ncols)
+        ((double*)A.tpart)[((int64_t)gi * A.ell + a) * A.C + ch.gcol0 + col] = s;
+    }
+  };
+
+  d4 yq[4][NQ > 0 ? NQ : 1];
+  double ys[4][NS > 0 ? NS : 1];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) yq[mt][q] = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) ys[mt][s] = 0.0;
+  }
+
+  if (cb < ce) {
+    build_omega(0, cb);
+    build_omega(1, cb + 1);
+    load_chunk(cb);
+  }
+  int it = 0;
+  for (int64_t ci = cb; ci < ce; ++ci, ++it) {
+    store_chunk();
+    if (ci + 1 < ce) load_chunk(ci + 1);
+    __syncthreads();
+    if (it >= 1) reduce_t((it - 1) & 1, ci - 1);
+    build_omega((it + 2) % 3, ci + 2);
+    const double* xw = Xl[w];
+    const double* om = Om[it % 3];
+    // right sketch
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int col = 4 * ks + g4;
+      double bq[NQ > 0 ? NQ : 1], bs[NS > 0 ? NS : 1];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) bq[q] = om[col * L4 + 16 * q + l16];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) bs[s] = om[col * L4 + 16 * NQ + 4 * s + l4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const double a = xw[col * ST + 16 * mt + l16];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) yq[mt][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq[q], yq[mt][q], 0, 0, 0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) ys[mt][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, bs[s], ys[mt][s], 0, 0, 0);
+      }
+    }
+    // left sketch
+    d4 tq[NQ > 0 ? NQ : 1];
+    double ts[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tq[q] = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) ts[s] = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < KT; ++ks) {
+      const double b = xw[l16 * ST + 4 * ks + g4];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) tq[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(psiq[ks][q], b, tq[q], 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) ts[s] = __builtin_amdgcn_mfma_f64_4x4x4f64(psis[ks][s], b, ts[s], 0, 0, 0);
+    }
+    double* tr = Tred[it & 1][w];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tr[(16 * q + 4 * v + g4) * KC + l16] = tq[q][v];
+    // 4x4x4: block blk holds columns 4*blk + l4, rows (a) 16*NQ + 4s + g4
+#pragma unroll
+    for (int s = 0; s < NS; ++s) tr[(16 * NQ + 4 * s + g4) * KC + 4 * blk + l4] = ts[s];
+  }
+  __syncthreads();
+  if (it >= 1) reduce_t((it - 1) & 1, ce - 1);
+
+  double* yp = (double*)A.ypart;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0w + 16 * mt + 4 * v + g4;
+        const int c = 16 * q + l16;
+        if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = yq[mt][q][v];
+      }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int64_t row = row0w + 16 * mt + 4 * blk + g4;
+      const int c = 16 * NQ + 4 * s + l4;
+      if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = ys[mt][s];
+    }
+  }
+}
+
+template <int L4>
+static hipError_t launch_f64(const SketchArgs& a, bool aligned, hipStream_t s) {
+  dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(NW * 64);
+  if (aligned)
+    hipLaunchKernelGGL((k_sketch_f64<L4, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_sketch_f64<L4, false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+// Table of the right DRM of the middle unfolding, Omega_m(col, c), FP64, C x L4
+// (columns c >= ell are zero).  Built once per context; the sketch kernels
+// stream 16-row blocks of it per chunk instead of re-forming the products.
+__global__ void k_omega_table(const SketchArgs A, int L4, double* __restrict__ tab) {
+  const int64_t tot = A.C * L4;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t col = t / L4;
+    const int c = (int)(t % L4);
+    tab[t] = c < A.ell ? omega_col(A, col, c) : 0.0;
+  }
+}
+
+hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream_t s) {
+  const int64_t tot = a.C * L4;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 16384));
+  hipLaunchKernelGGL(k_omega_table, dim3(g), dim3(256), 0, s, a, L4, tab);
+  return hipGetLastError();
+}
+
+void sketch_geometry(int prec, int lp, int* rows_per_block, int* threads) {
+  (void)lp;
+  *threads = NW * 64;
+  *rows_per_block = NW * (prec == P_F64 ? Eng<P_F64>::RW : Eng<P_F32>::RW);
+}
+
+template <int PREC, int LP>
+static hipError_t launch_t(const SketchArgs& a, bool aligned, hipStream_t s) {
+  dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(NW * 64);
+  if (aligned)
+    hipLaunchKernelGGL((k_sketch<PREC, LP, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_sketch<PREC, LP, false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s) {
+  // 16-byte loads need every column (and segment start) 16-byte aligned.
+  const int esz = prec == P_F64 ? 8 : 4;
+  bool aligned = ((a.R * esz) % 16) == 0;
+  for (int i = 0; i < a.nseg; ++i) aligned = aligned && (((uintptr_t)a.seg[i].ptr) % 16 == 0);
+  if (prec == P_F64) {
+    switch ((a.ell + 3) / 4 * 4) {
+      case 4: return launch_f64<4>(a, aligned, s);
+      case 8: return launch_f64<8>(a, aligned, s);
+      case 12: return launch_f64<12>(a, aligned, s);
+      case 16: return launch_f64<16>(a, aligned, s);
+      case 20: return launch_f64<20>(a, aligned, s);
+      case 24: return launch_f64<24>(a, aligned, s);
+      case 28: return launch_f64<28>(a, aligned, s);
+      case 32: return launch_f64<32>(a, aligned, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (prec * 100 + lp) {
+    case P_F32 * 100 + 16: return launch_t<P_F32, 16>(a, aligned, s);
+    case P_F32 * 100 + 32: return launch_t<P_F32, 32>(a, aligned, s);
+    case P_BF16 * 100 + 16: return launch_t<P_BF16, 16>(a, aligned, s);
+    case P_BF16 * 100 + 32: return launch_t<P_BF16, 32>(a, aligned, s);
+    case P_BF16X3 * 100 + 16: return launch_t<P_BF16X3, 16>(a, aligned, s);
+    case P_BF16X3 * 100 + 32: return launch_t<P_BF16X3, 32>(a, aligned, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---- fixed-order reduction of the tile partials into the FP64 sketches ----
+template <typename P>
+__global__ void k_reduce_y(const P* __restrict__ yp, int gj_count, int64_t R, int ell, double* __restrict__ Y,
+                           int* flag) {
+  const int64_t tot = R * ell;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = Y[i];
+    for (int g = 0; g < gj_count; ++g) s += (double)yp[(int64_t)g * tot + i];
+    Y[i] = s;
+    if (!isfinite(s)) atomicOr(flag, 1);
+  }
+}
+
+// Tt is C x ell column-major (the transposed left sketch); tpart is [gi][a][gcol].
+template <typename P>
+__global__ void k_reduce_t(const P* __restrict__ tp, int gi_count, int64_t C, int ell, int64_t gc0, int64_t ncols,
+                           double* __restrict__ Tt, int* flag) {
+  const int64_t tot = ncols * ell;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(i / ncols);
+    const int64_t col = gc0 + i % ncols;
+    double s = Tt[(int64_t)a * C + col];
+    for (int g = 0; g < gi_count; ++g) s += (double)tp[((int64_t)g * ell + a) * C + col];
+    Tt[(int64_t)a * C + col] = s;
+    if (!isfinite(s)) atomicOr(flag, 1);
+  }
+}
+
+hipError_t launch_reduce(int prec, const SketchArgs& a, double* Y, double* Tt, int* flag, hipStream_t s) {
+  const int bs = 256;
+  const int64_t ny = a.R * a.ell;
+  const unsigned gy = (unsigned)std::min<int64_t>((ny + bs - 1) / bs, 4096);
+  if (prec == P_F64)
+    hipLaunchKernelGGL(k_reduce_y<double>, dim3(gy), dim3(bs), 0, s, (const double*)a.ypart, a.gj_count, a.R,
+                       a.ell, Y, flag);
+  else
+    hipLaunchKernelGGL(k_reduce_y<float>, dim3(gy), dim3(bs), 0, s, (const float*)a.ypart, a.gj_count, a.R,
+                       a.ell, Y, flag);
+  for (int i = 0; i < a.nseg; ++i) {
+    const int64_t nt = a.seg[i].ncols * a.ell;
+    const unsigned gt = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nt + bs - 1) / bs, 4096));
+    if (prec == P_F64)
+      hipLaunchKernelGGL(k_reduce_t<double>, dim3(gt), dim3(bs), 0, s, (const double*)a.tpart, a.gi_count, a.C,
+                         a.ell, a.seg[i].gcol0, a.seg[i].ncols, Tt, flag);
+    else
+      hipLaunchKernelGGL(k_reduce_t<float>, dim3(gt), dim3(bs), 0, s, (const float*)a.tpart, a.gi_count, a.C,
+                         a.ell, a.seg[i].gcol0, a.seg[i].ncols, Tt, flag);
+  }
+  return hipGetLastError();
+}
+
+// ---- one partial column (slab edges that cut a column of X_m), FP64 ----
+template <typename T>
+__global__ void k_partial_col(const T* __restrict__ x, int64_t r0, int64_t r1, int64_t gcol, const SketchArgs A,
+                              double* __restrict__ Y, double* __restrict__ Tt) {
+  __shared__ double red[PSTT2_MAX_ELL][8];
+  double om[PSTT2_MAX_ELL];
+  for (int c = 0; c < A.ell; ++c) om[c] = omega_col(A, gcol, c);
+  double t[PSTT2_MAX_ELL];
+  for (int a = 0; a < A.ell; ++a) t[a] = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const double xv = (double)x[r - r0];
+    for (int c = 0; c < A.ell; ++c) Y[(int64_t)c * A.R + r] += xv * om[c];
+    for (int a = 0; a < A.ell; ++a) t[a] += psi_row(A, r, a) * xv;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int a = 0; a < A.ell; ++a) {
+    double v = t[a];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[a][w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < A.ell) {
+    double s = 0.0;
+    for (int ww = 0; ww < (int)(blockDim.x >> 6); ++ww) s += red[threadIdx.x][ww];
+    Tt[(int64_t)threadIdx.x * A.C + gcol] += s;
+  }
+}
+
+hipError_t launch_partial_col(int dtype, const void* x, int64_t r0, int64_t r1, int64_t gcol, const SketchArgs& a,
+                              double* Y, double* Tt, hipStream_t s) {
+  if (dtype == PSTT2_F64)
+    hipLaunchKernelGGL(k_partial_col<double>, dim3(1), dim3(512), 0, s, (const double*)x, r0, r1, gcol, a, Y, Tt);
+  else
+    hipLaunchKernelGGL(k_partial_col<float>, dim3(1), dim3(512), 0, s, (const float*)x, r0, r1, gcol, a, Y, Tt);
+  return hipGetLastError();
+}
+
+}  // namespace pstt2

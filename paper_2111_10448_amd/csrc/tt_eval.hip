@@ -1,0 +1,264 @@
+// Evaluation of a tensor train against a dense tensor (Section 2.2 entry
+// formula; relative Frobenius error of equation "FrobeniusNorm").
+//
+// The train is split at mode m: the left interface L (R_m x r_m) holds the
+// products G_1(i_1) ... G_m(i_m) for every row of X_m and the right interface
+// Rt (r_m x C_m) the products G_{m+1}(i_{m+1}) ... G_d(i_d) for every column, so
+// that X~_m = L Rt.  tt_error streams X once: lanes run along rows with 8- or
+// 16-byte loads (each column of X_m is contiguous), every lane keeps its rows
+// of L in registers, and the column's Rt(:, col) is wave-uniform (scalar
+// loads).  Squared differences are summed in FP64, never through
+// ||X||^2 - 2<X, X~> + ||X~||^2, which cancels.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace pstt2 {
+
+static unsigned grid_for(int64_t n, int bs) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + bs - 1) / bs, 8192));
+}
+
+// L_k(row + R_{k-1} i, b) = sum_a L_{k-1}(row, a) G_k(a, i, b)
+__global__ void k_left_iface(const double* __restrict__ Lp, int64_t Rp, int rp, const double* __restrict__ G, int nk,
+                             int rk, double* __restrict__ L) {
+  const int64_t Rk = Rp * nk;
+  const int64_t tot = Rk * rk;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rr = t % Rk;
+    const int b = (int)(t / Rk);
+    const int64_t row = rr % Rp;
+    const int i = (int)(rr / Rp);
+    double s = 0.0;
+    for (int a = 0; a < rp; ++a) s += Lp[(int64_t)a * Rp + row] * G[a + (int64_t)rp * (i + (int64_t)nk * b)];
+    L[t] = s;
+  }
+}
+
+// Rt_k(a, i + n_k col) = sum_b G_k(a, i, b) Rt_{k+1}(b, col); Rt_{k+1} is r_k x C_k.
+__global__ void k_right_iface(const double* __restrict__ G, int rp, int nk, int rk, const double* __restrict__ Rn,
+                              int64_t Ck, double* __restrict__ Rt) {
+  const int64_t Cp = Ck * nk;
+  const int64_t tot = (int64_t)rp * Cp;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(t % rp);
+    const int64_t cc = t / rp;
+    const int i = (int)(cc % nk);
+    const int64_t col = cc / nk;
+    double s = 0.0;
+    for (int b = 0; b < rk; ++b) s += G[a + (int64_t)rp * (i + (int64_t)nk * b)] * Rn[b + (int64_t)rk * col];
+    Rt[t] = s;
+  }
+}
+
+// Interfaces in stream-ordered memory (release with hipFreeAsync on the same stream).
+hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** Rout, hipStream_t s) {
+  const int d = c->d;
+  int64_t Rp = c->n[0];
+  double* L = nullptr;
+  hipError_t e = hipMallocAsync((void**)&L, sizeof(double) * Rp * c->r[1], s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(L, c->core[0], sizeof(double) * Rp * c->r[1], hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  for (int k = 1; k < split; ++k) {
+    const int nk = (int)c->n[k];
+    double* Ln = nullptr;
+    e = hipMallocAsync((void**)&Ln, sizeof(double) * Rp * nk * c->r[k + 1], s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_left_iface, dim3(grid_for(Rp * nk * c->r[k + 1], 256)), dim3(256), 0, s, L, Rp, c->r[k],
+                       c->core[k], nk, c->r[k + 1], Ln);
+    e = hipFreeAsync(L, s);
+    if (e != hipSuccess) return e;
+    L = Ln;
+    Rp *= nk;
+  }
+  int64_t Ck = c->n[d - 1];
+  double* R = nullptr;
+  e = hipMallocAsync((void**)&R, sizeof(double) * Ck * c->r[d - 1], s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(R, c->core[d - 1], sizeof(double) * Ck * c->r[d - 1], hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  for (int k = d - 2; k >= split; --k) {
+    const int nk = (int)c->n[k];
+    double* Rn = nullptr;
+    e = hipMallocAsync((void**)&Rn, sizeof(double) * Ck * nk * c->r[k], s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_right_iface, dim3(grid_for(Ck * nk * c->r[k], 256)), dim3(256), 0, s, c->core[k], c->r[k],
+                       nk, c->r[k + 1], R, Ck, Rn);
+    e = hipFreeAsync(R, s);
+    if (e != hipSuccess) return e;
+    R = Rn;
+    Ck *= nk;
+  }
+  *Lout = L;
+  *Rout = R;
+  return hipGetLastError();
+}
+
+// ---- tt_error: one streaming pass over X ----
+// Block = 4 waves; a wave owns 128 consecutive rows (2 per lane) of X_m and
+// walks the block's column range one column at a time.
+template <typename T, int RK>
+__global__ __launch_bounds__(256) void k_tt_error(const T* __restrict__ x, int64_t R, int64_t C, int r,
+                                                  const double* __restrict__ L, const double* __restrict__ Rt,
+                                                  int gi_count, int gj_count, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int gi = blockIdx.x % gi_count, gj = blockIdx.x / gi_count;
+  const int64_t row = (int64_t)gi * 512 + w * 128 + 2 * lane;
+  const int64_t cb = gj * C / gj_count, ce = (gj + 1) * C / gj_count;
+  const bool ok0 = row < R, ok1 = row + 1 < R;
+  double l0[RK], l1[RK];
+#pragma unroll
+  for (int k = 0; k < RK; ++k) {
+    l0[k] = (ok0 && k < r) ? L[(int64_t)k * R + row] : 0.0;
+    l1[k] = (ok1 && k < r) ? L[(int64_t)k * R + row + 1] : 0.0;
+  }
+  const bool pair = ok1 && ((R & 1) == 0);   // aligned 2-element loads
+  double e2 = 0.0, x2 = 0.0;
+  for (int64_t col = cb; col < ce; ++col) {
+    const T* p = x + col * R + row;
+    double x0 = 0.0, x1 = 0.0;
+    if (pair) {
+      if constexpr (sizeof(T) == 8) {
+        const double2 v = *(const double2*)p;
+        x0 = v.x;
+        x1 = v.y;
+      } else {
+        const float2 v = *(const float2*)p;
+        x0 = v.x;
+        x1 = v.y;
+      }
+    } else {
+      if (ok0) x0 = (double)p[0];
+      if (ok1) x1 = (double)p[1];
+    }
+    const double* rc = Rt + (int64_t)r * col;
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < RK; ++k) {
+      const double rv = k < r ? rc[k] : 0.0;
+      t0 += l0[k] * rv;
+      t1 += l1[k] * rv;
+    }
+    const double d0 = x0 - t0, d1 = x1 - t1;
+    e2 += d0 * d0 + d1 * d1;
+    x2 += x0 * x0 + x1 * x1;
+  }
+  __shared__ double red[2][4];
+  for (int o = 32; o > 0; o >>= 1) {
+    e2 += __shfl_xor(e2, o);
+    x2 += __shfl_xor(x2, o);
+  }
+  if (lane == 0) {
+    red[0][w] = e2;
+    red[1][w] = x2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    part[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// Fixed-order sum of nb (e2, x2) pairs: strided per thread, then a tree.
+__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sa[256], sb[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sa[threadIdx.x] += sa[threadIdx.x + o];
+      sb[threadIdx.x] += sb[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sa[0];
+    out[1] = sb[0];
+  }
+}
+
+template <typename T>
+static hipError_t launch_err(const T* x, int64_t R, int64_t C, int r, const double* L, const double* Rt, int gi,
+                             int gj, double* part, hipStream_t s) {
+  dim3 g((unsigned)(gi * gj)), b(256);
+  if (r <= 4) hipLaunchKernelGGL((k_tt_error<T, 4>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else if (r <= 8) hipLaunchKernelGGL((k_tt_error<T, 8>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else if (r <= 12) hipLaunchKernelGGL((k_tt_error<T, 12>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else if (r <= 16) hipLaunchKernelGGL((k_tt_error<T, 16>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else if (r <= 24) hipLaunchKernelGGL((k_tt_error<T, 24>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else hipLaunchKernelGGL((k_tt_error<T, 32>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  return hipGetLastError();
+}
+
+hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s) {
+  const int d = c->d;
+  const int split = (d + 1) / 2;
+  double *L = nullptr, *Rt = nullptr;
+  hipError_t e = tt_interfaces(c, split, &L, &Rt, s);
+  if (e != hipSuccess) return e;
+  int64_t R = 1, C = 1;
+  for (int k = 0; k < split; ++k) R *= c->n[k];
+  for (int k = split; k < d; ++k) C *= c->n[k];
+  const int r = c->r[split];
+  const int gi = (int)((R + 511) / 512);
+  const int gj = (int)std::max<int64_t>(1, std::min<int64_t>(C, (4096 + gi - 1) / gi));
+  double* part = nullptr;
+  e = hipMallocAsync((void**)&part, sizeof(double) * 2 * ((int64_t)gi * gj + 1), s);
+  if (e != hipSuccess) return e;
+  if (dtype == PSTT2_F64) e = launch_err((const double*)x, R, C, r, L, Rt, gi, gj, part, s);
+  else e = launch_err((const float*)x, R, C, r, L, Rt, gi, gj, part, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, gi * gj, part + 2 * (int64_t)gi * gj);
+    e = hipMemcpyAsync(e2x2, part + 2 * (int64_t)gi * gj, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  }
+  hipFreeAsync(part, s);
+  hipFreeAsync(L, s);
+  hipFreeAsync(Rt, s);
+  hipError_t e2 = hipStreamSynchronize(s);
+  return e != hipSuccess ? e : e2;
+}
+
+template <typename T>
+__global__ void k_reconstruct(T* __restrict__ out, int64_t first, int64_t count, int64_t R, int r,
+                              const double* __restrict__ L, const double* __restrict__ Rt) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = first + t;
+    const int64_t row = f % R, col = f / R;
+    double s = 0.0;
+    for (int b = 0; b < r; ++b) s += L[(int64_t)b * R + row] * Rt[b + (int64_t)r * col];
+    out[t] = (T)s;
+  }
+}
+
+hipError_t tt_reconstruct_run(const tt_cores* c, void* out, int dtype, int64_t first, int64_t count, hipStream_t s) {
+  const int d = c->d;
+  const int split = (d + 1) / 2;
+  double *L = nullptr, *Rt = nullptr;
+  hipError_t e = tt_interfaces(c, split, &L, &Rt, s);
+  if (e != hipSuccess) return e;
+  int64_t R = 1;
+  for (int k = 0; k < split; ++k) R *= c->n[k];
+  const int r = c->r[split];
+  if (count > 0) {
+    if (dtype == PSTT2_F64)
+      hipLaunchKernelGGL(k_reconstruct<double>, dim3(grid_for(count, 256)), dim3(256), 0, s, (double*)out, first,
+                         count, R, r, L, Rt);
+    else
+      hipLaunchKernelGGL(k_reconstruct<float>, dim3(grid_for(count, 256)), dim3(256), 0, s, (float*)out, first,
+                         count, R, r, L, Rt);
+    e = hipGetLastError();
+  }
+  hipFreeAsync(L, s);
+  hipFreeAsync(Rt, s);
+  hipError_t e2 = hipStreamSynchronize(s);
+  return e != hipSuccess ? e : e2;
+}
+
+}  // namespace pstt2

@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every symbol include/pstt2.h declares (CPU only).
+
+No compute call is made here: this container has no GPU.  Host-side argument
+validation that fails before touching the device is exercised too.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "pstt2.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:pstt2_status|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_and_binding_agree():
+    from paper_2111_10448_amd import _lib as L
+    assert _header_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    from paper_2111_10448_amd import _lib as L
+    lib = L.lib()
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+    assert b"gfx950" in lib.pstt2_version()
+
+
+def test_struct_layouts_match_header():
+    """ctypes layouts mirror the C structs (natural alignment, x86-64)."""
+    from paper_2111_10448_amd import _lib as L
+    assert ctypes.sizeof(L.Desc) == 432
+    assert L.Desc.eps.offset == 408 and L.Desc.drm_factors.offset == 424
+    assert ctypes.sizeof(L.TTCores) == 4 + 4 + 256 + 132 + 4 + 256 + 4 + 4
+    assert L.TTCores.core.offset == 400
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("d", 1, "d must be"),
+    ("ell", 0, "ell must be"),
+    ("ell", 33, "ell must be"),
+    ("dtype", 7, "bad dtype"),
+])
+def test_create_rejects_bad_descriptors(field, value, msg):
+    from paper_2111_10448_amd import _lib as L
+    lib = L.lib()
+    d = L.Desc()
+    d.d = 3
+    for k in range(3):
+        d.n[k] = 4
+    d.ell = 4
+    d.ranks[0] = 2
+    d.ranks[1] = 2
+    fac = np.zeros(64)
+    d.drm_factors = fac.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    setattr(d, field, value)
+    ctx = ctypes.c_void_p()
+    st = lib.pstt2_create(ctypes.byref(d), None, ctypes.byref(ctx))
+    assert st == L.EINVAL
+    assert msg in lib.pstt2_last_error(None).decode()
+    assert not ctx
+
+
+def test_null_arguments_are_rejected():
+    from paper_2111_10448_amd import _lib as L
+    lib = L.lib()
+    assert lib.pstt2_sketch(None, None, 0, 0) == L.EINVAL
+    assert lib.pstt2_reset(None) == L.EINVAL
+    out = ctypes.c_double()
+    assert lib.tt_error(None, None, 0, ctypes.byref(out), None) == L.EINVAL
+    lib.pstt2_destroy(None)
+    lib.tt_cores_free(None)
+
+
+def test_missing_factors_rejected():
+    from paper_2111_10448_amd import _lib as L
+    lib = L.lib()
+    d = L.Desc()
+    d.d = 2
+    d.n[0] = d.n[1] = 4
+    d.ell = 3
+    d.ranks[0] = 1
+    ctx = ctypes.c_void_p()
+    assert lib.pstt2_create(ctypes.byref(d), None, ctypes.byref(ctx)) == L.EINVAL
+    assert "drm_factors" in lib.pstt2_last_error(None).decode()

@@ -1,0 +1,180 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Same seeded inputs on both sides; compared element by element: the sketches
+(Y_R, T_m and every derived split), CPQR pivots, ranks, the reconstructed
+tensor X~ and the relative error.  Tolerances: 1e-10 (FP64), 1e-5 (FP32,
+split-BF16), 5e-3 (BF16) on X~.
+"""
+import numpy as np
+import pytest
+
+import inputs
+from oracle import tt_sketch as O
+
+from gpu_common import TOL_XT, compare, gpu_run, oracle_run, rel, say, setup
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", ["c1", "c1_exact", "c2_small", "c5_small", "c5_fd"])
+def test_fp64_and_fp32_workloads(name):
+    w = inputs.WORKLOADS[name]
+    say(f"[gpu] parity {name} n={w.n} ell={w.ell} dtype={w.dtype}")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    prec = "f64" if w.dtype == "f64" else "f32"
+    ctx, tt, xg = gpu_run(x, w, fac, prec)
+    out = compare(ctx, tt, xg, x, w, ref, prec, check_cores=(prec == "f64"))
+    say(f"    {out}")
+    if name == "c1_exact":
+        assert out["err_gpu"] < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16"])
+def test_mixed_precision_invsum(prec):
+    w = inputs.WORKLOADS["c3_small"]
+    say(f"[gpu] parity c3_small prec={prec}")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    # plain BF16 sketches sit ~1e-3 above the 1e-5 tolerance rule, so that run
+    # uses the oracle's ranks (fixed-rank mode); the others choose their own.
+    ranks = ref["ranks"] if prec == "bf16" else None
+    ctx, tt, xg = gpu_run(x, w, fac, prec, ranks=ranks)
+    out = compare(ctx, tt, xg, x, w, ref, prec, check_pivots=(prec != "bf16"))
+    say(f"    {out}")
+    assert out["err_gpu"] <= 1e-5 or prec == "bf16"
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("batched", [False, True])
+def test_slab_streaming(prec, batched):
+    """Slabs of whole mode-1 fibres (edges cut columns of X_m) in scrambled order."""
+    w = inputs.WORKLOADS["c4_small"]
+    say(f"[gpu] slabs c4_small prec={prec} batched={batched}")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    slabs = inputs.slab_bounds(x.size, w.n[0], w.nslabs)
+    order = np.random.default_rng(5).permutation(len(slabs))
+    slabs = [slabs[i] for i in order]
+    ctx, tt, xg = gpu_run(x, w, fac, prec, slabs=slabs, batched=batched)
+    out = compare(ctx, tt, xg, x, w, ref, prec)
+    say(f"    {out}")
+    ctx.close()
+
+
+def test_twopass_middle_core():
+    w = inputs.WORKLOADS["c2_small"]
+    say("[gpu] two-pass middle core c2_small")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega, middle="twopass")
+    ctx, tt, xg = gpu_run(x, w, fac, "f64", middle="twopass")
+    out = compare(ctx, tt, xg, x, w, ref, "f64", check_cores=True)
+    say(f"    {out}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,rank,ell", [((37, 41), 4, 7), ((5, 6, 7), 3, 6), ((3, 4, 5, 4, 3, 2, 3), 2, 5),
+                                         ((2, 2, 2, 2, 2, 2, 2, 2, 2), 2, 4)])
+def test_exact_recovery_shapes(n, rank, ell):
+    """d = 2, 3, 7, 9; exact-rank TT, noise 0: both sides recover X to ~1e-12."""
+    import dataclasses
+    w = dataclasses.replace(inputs.WORKLOADS["c1_exact"], name="shape", index=90 + len(n), n=tuple(n),
+                            tt_rank=rank, ell=ell, rank=rank)
+    say(f"[gpu] exact recovery n={n}")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    ctx, tt, xg = gpu_run(x, w, fac, "f64")
+    out = compare(ctx, tt, xg, x, w, ref, "f64", check_cores=True)
+    assert out["err_gpu"] < 1e-11
+    say(f"    {out}")
+    ctx.close()
+
+
+def test_repeatable_bitwise_and_slab_order():
+    """Same call sequence -> bitwise-identical sketches; another slab order -> equal to rounding."""
+    import torch
+    w = inputs.WORKLOADS["c2_small"]
+    say("[gpu] determinism c2_small")
+    x, psi, omega, fac = setup(w)
+    import paper_2111_10448_amd as P
+    xg = torch.from_numpy(x).cuda()
+    m = O.middle_index(w.d)
+    ys = []
+    for rep in range(2):
+        with P.PSTT2(w.n, w.ell, fac, ranks=w.ranks()) as ctx:
+            ctx.sketch(xg)
+            ctx.recover()
+            ys.append((ctx.get_sketch(0, m), ctx.get_sketch(1, m)))
+    assert np.array_equal(ys[0][0], ys[1][0]) and np.array_equal(ys[0][1], ys[1][1])
+    slabs = inputs.slab_bounds(x.size, w.n[0], 9)[::-1]
+    with P.PSTT2(w.n, w.ell, fac, ranks=w.ranks()) as ctx:
+        for f, c in slabs:
+            ctx.sketch(xg[f:f + c], f)
+        ctx.recover()
+        assert rel(ctx.get_sketch(0, m), ys[0][0]) < 1e-13
+        assert rel(ctx.get_sketch(1, m), ys[0][1]) < 1e-13
+
+
+def test_error_paths():
+    """Overlap / missing coverage / misalignment / NaN are reported, not run."""
+    import torch
+    import paper_2111_10448_amd as P
+    from paper_2111_10448_amd import _lib as L
+    w = inputs.WORKLOADS["c1"]
+    say("[gpu] error paths")
+    x, psi, omega, fac = setup(w)
+    xg = torch.from_numpy(x).cuda()
+    with P.PSTT2(w.n, w.ell, fac, ranks=w.ranks()) as ctx:
+        ctx.sketch(xg[:1024], 0)
+        with pytest.raises(P.PSTT2Error) as e:
+            ctx.sketch(xg[512:2048], 512)
+        assert e.value.status == L.ESTATE
+        with pytest.raises(P.PSTT2Error) as e:
+            ctx.sketch(xg[1030:1040], 1030)    # not a multiple of n_1 = 16
+        assert e.value.status == L.EINVAL
+        with pytest.raises(P.PSTT2Error) as e:
+            ctx.recover()                      # entries 1024.. never streamed
+        assert e.value.status == L.ESTATE
+        ctx.sketch(xg[1024:1024], 1024)        # empty slab is a no-op
+        ctx.sketch(xg[1024:], 1024)
+        tt = ctx.recover()
+        assert tt.ranks[1] == 3
+    xn = x.copy()
+    xn[777] = np.nan
+    with P.PSTT2(w.n, w.ell, fac, ranks=w.ranks()) as ctx:
+        ctx.sketch(torch.from_numpy(xn).cuda())
+        with pytest.raises(P.PSTT2Error) as e:
+            ctx.recover()
+        assert e.value.status == L.ENUMERIC
+        ctx.reset()
+        ctx.sketch(xg)
+        ctx.recover()
+
+
+def test_tt_error_and_reconstruct_on_given_cores():
+    """tt_error / tt_reconstruct of caller-provided cores vs the entry formula."""
+    import torch
+    import paper_2111_10448_amd as P
+    say("[gpu] tt_error on given cores")
+    n = (7, 6, 5, 8, 3)
+    rng = np.random.default_rng(3)
+    cores = inputs.random_tt_cores(rng, n, 4)
+    ranks = [1] + [c.shape[2] for c in cores[:-1]]
+    tc = [torch.from_numpy(np.ascontiguousarray(c.reshape(-1, order="F"))).cuda() for c in cores]
+    cs = P.cores_struct(tc, n, ranks + [1])
+    xt = O.tt_full(cores)
+    got = P.tt_reconstruct(cs).cpu().numpy()
+    assert rel(got, xt) < 1e-14
+    part = P.tt_reconstruct(cs, 35, 700, dtype=torch.float32).cpu().numpy()
+    assert rel(part, xt[35:735]) < 1e-6
+    noise = 1e-3 * rng.standard_normal(xt.size)
+    xg = torch.from_numpy(xt + noise).cuda()
+    e = P.tt_error(cs, xg)
+    ref = np.linalg.norm(noise) / np.linalg.norm(xt + noise)
+    assert abs(e - ref) < 1e-9 * ref
+    e32 = P.tt_error(cs, xg.float())
+    ref32 = np.linalg.norm((xt + noise).astype(np.float32).astype(np.float64) - xt) / \
+        np.linalg.norm((xt + noise).astype(np.float32).astype(np.float64))
+    assert abs(e32 - ref32) < 1e-6 * ref32
