@@ -75,6 +75,9 @@ WORKLOADS = {
     "c1_exact": Workload("c1_exact", 0, (16,) * 4, "f64", "tt", tt_rank=3, noise=0.0, ell=6, rank=3),
     # d=6, n=32 (1.07e9 entries, 8.6 GB), TT ranks 10, ||X||_F = 1, noise 1e-8, rank 10, sketch size 20, FP64
     "c2": Workload("c2", 1, (32,) * 6, "f64", "tt", tt_rank=10, noise=1e-8, unit_norm=True, ell=20, rank=10),
+    # the same tensor without noise: exact-rank, recovered to rounding at full size
+    "c2_exact": Workload("c2_exact", 1, (32,) * 6, "f64", "tt", tt_rank=10, noise=0.0, unit_norm=True, ell=20,
+                         rank=10),
     # d=5, n=64 FP32 samples of 1/(x1+..+x5) on a Chebyshev grid over [1,2]^5, eps=1e-5, ranks <= 16, sketch size 32
     "c3": Workload("c3", 2, (64,) * 5, "f32", "invsum", ell=32, eps=1e-5, rmax=16),
     # the same samples kept in FP64 (the plain-FP64 comparator of the precision study)

@@ -83,13 +83,50 @@ hipError_t derive_right(const double* Tin, double* Tout, int64_t Ck, int nk, int
 // when the column below the diagonal is already zero).  Lane t holds rows t
 // and t + 64 of the block.  Rows past M are zero.
 // ---------------------------------------------------------------------------
+// Wave-local batched reduction: every lane holds p[c] for the columns c in
+// (j, ell); returns, in every lane, the wave sums W[c] (read back from LDS).
+// P is this wave's LDS scratch with row stride 65 (conflict-free transposes).
+template <int LP>
+__device__ __forceinline__ void wave_colsum(const double (&p)[LP], int j, int ell, double* P, double* W) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < LP; ++c)
+    if (c > j && c < ell) P[c * 65 + lane] = p[c];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // lane (c, h): c = lane % 32 sums half h = lane / 32 of column c's 64 entries
+  const int c = lane & 31, h = lane >> 5;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (c > j && c < ell) {
+    const double* q = P + c * 65 + 32 * h;
+#pragma unroll
+    for (int i = 0; i < 32; i += 4) {
+      s0 += q[i];
+      s1 += q[i + 1];
+      s2 += q[i + 2];
+      s3 += q[i + 3];
+    }
+  }
+  double s = (s0 + s1) + (s2 + s3);
+  s += __shfl_xor(s, 32);
+  if (h == 0 && c > j && c < ell) W[c] = s;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int LP>
 __global__ __launch_bounds__(256) void k_hh_block(const double* __restrict__ A, int64_t M, int64_t lda, int ell,
                                                   int64_t nb, double* __restrict__ V, double* __restrict__ tau,
                                                   double* __restrict__ Rout, int64_t ldr) {
-  const int lane = threadIdx.x & 63;
-  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  __shared__ double Pbuf[4][LP * 65];
+  __shared__ double Wbuf[4][LP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * 4 + wv;
   if (b >= nb) return;
+  double* P = Pbuf[wv];
+  double* W = Wbuf[wv];
   const int64_t r0 = b * BRW + lane, r1 = r0 + 64;
   double a0[LP], a1[LP];
 #pragma unroll
@@ -121,10 +158,14 @@ __global__ __launch_bounds__(256) void k_hh_block(const double* __restrict__ A, 
     }
     const double v0 = (t0 == j) ? 1.0 : (t0 > j ? x0 * scal : 0.0);
     const double v1 = x1 * scal;
+    double p[LP];
+#pragma unroll
+    for (int c = 0; c < LP; ++c) p[c] = v0 * a0[c] + v1 * a1[c];
+    wave_colsum<LP>(p, j, ell, P, W);
 #pragma unroll
     for (int c = 0; c < LP; ++c) {
       if (c > j && c < ell) {
-        const double wc = wave_sum(v0 * a0[c] + v1 * a1[c]) * tj;
+        const double wc = W[c] * tj;
         a0[c] -= wc * v0;
         a1[c] -= wc * v1;
       }
@@ -153,9 +194,13 @@ template <int RP>
 __global__ __launch_bounds__(256) void k_hh_apply(const double* __restrict__ V, const double* __restrict__ tau,
                                                   int ell, int64_t nb, const double* __restrict__ Zin, int64_t ldzi,
                                                   int r, double* __restrict__ Zout, int64_t ldzo, int64_t Mout) {
-  const int lane = threadIdx.x & 63;
-  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  __shared__ double Pbuf[4][RP * 65];
+  __shared__ double Wbuf[4][RP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * 4 + wv;
   if (b >= nb) return;
+  double* P = Pbuf[wv];
+  double* W = Wbuf[wv];
   double c0[RP], c1[RP];
 #pragma unroll
   for (int c = 0; c < RP; ++c) {
@@ -166,10 +211,14 @@ __global__ __launch_bounds__(256) void k_hh_apply(const double* __restrict__ V, 
     const double tj = tau[b * ell + j];
     const double v0 = V[(b * ell + j) * BRW + lane];
     const double v1 = V[(b * ell + j) * BRW + lane + 64];
+    double p[RP];
+#pragma unroll
+    for (int c = 0; c < RP; ++c) p[c] = v0 * c0[c] + v1 * c1[c];
+    wave_colsum<RP>(p, -1, r, P, W);
 #pragma unroll
     for (int c = 0; c < RP; ++c) {
       if (c < r) {
-        const double wc = wave_sum(v0 * c0[c] + v1 * c1[c]) * tj;
+        const double wc = W[c] * tj;
         c0[c] -= wc * v0;
         c1[c] -= wc * v1;
       }
@@ -261,18 +310,17 @@ __global__ __launch_bounds__(64) void k_cpqr(const double* __restrict__ R, int64
     }
     __syncthreads();
   }
-  // Qc = H_0 ... H_{ell-1} I, column t by lane t, sign-fixed
+  // Qc = H_0 ... H_{ell-1} I, column t by lane t (in LDS, reusing As), sign-fixed
   if (t < ell) {
-    double q[PSTT2_MAX_ELL];
-    for (int i = 0; i < ell; ++i) q[i] = (i == t) ? 1.0 : 0.0;
+    for (int i = 0; i < ell; ++i) As[t][i] = (i == t) ? 1.0 : 0.0;
     for (int j = ell - 1; j >= 0; --j) {
       double p = 0.0;
-      for (int i = j; i < ell; ++i) p += Vs[j][i] * q[i];
+      for (int i = j; i < ell; ++i) p += Vs[j][i] * As[t][i];
       p *= taus[j];
-      for (int i = j; i < ell; ++i) q[i] -= p * Vs[j][i];
+      for (int i = j; i < ell; ++i) As[t][i] -= p * Vs[j][i];
     }
     const double sg = diag[t] < 0.0 ? -1.0 : 1.0;
-    for (int i = 0; i < ell; ++i) Qc[(int64_t)t * ell + i] = sg * q[i];
+    for (int i = 0; i < ell; ++i) Qc[(int64_t)t * ell + i] = sg * As[t][i];
     piv[t] = pv[t];
   }
 }

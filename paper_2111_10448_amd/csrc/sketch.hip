@@ -180,7 +180,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
 
   __shared__ lds_t Xl[NW][KC * ST];
   __shared__ acc Tred[2][NW][LP * KC];
-  __shared__ lds_t Om[3][KC * LP];
+  __shared__ lds_t Om[4][KC * LP];   // 4 buffers: each write is a barrier past the last read
 
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -215,17 +215,18 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
     }
   }
 
-  auto build_omega = [&](int buf, int64_t ci) {
+  // Omega_m rows of a chunk (thread t < KC*LP holds entry (t / LP, t % LP)),
+  // loaded one iteration before they are written to LDS so that waiting for
+  // them never waits for the X prefetch (loads retire in order).
+  auto load_omega = [&](int64_t ci) -> double {
     const int t = threadIdx.x;
-    if (t < KC * LP) {
+    double v = 0.0;
+    if (t < KC * LP && ci < ce) {
       const int col = t / LP, c = t % LP;
-      lds_t v = drm_to_lds<PREC>(0.0);
-      if (ci < ce) {
-        ChunkInfo ch = chunk_info(A, ci);
-        if (col < ch.ncols && c < A.ell) v = drm_to_lds<PREC>(A.om_tab[(ch.gcol0 + col) * A.L4 + c]);
-      }
-      Om[buf][col * LP + c] = v;
+      ChunkInfo ch = chunk_info(A, ci);
+      if (col < ch.ncols && c < A.ell) v = A.om_tab[(ch.gcol0 + col) * A.L4 + c];
     }
+    return v;
   };
 
   // ---- global loads of one chunk (16-byte, coalesced along rows) ----
@@ -292,25 +293,31 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) yacc[mt][nt] = accv{0, 0, 0, 0};
 
+  double omv = 0.0;
   if (cb < ce) {
-    build_omega(0, cb);
-    build_omega(1, cb + 1);
+    if (threadIdx.x < KC * LP) {
+      Om[0][threadIdx.x] = drm_to_lds<PREC>(load_omega(cb));
+      Om[1][threadIdx.x] = drm_to_lds<PREC>(load_omega(cb + 1));
+    }
     load_chunk(cb);
+    omv = load_omega(cb + 2);
   }
 
   int it = 0;
   for (int64_t ci = cb; ci < ce; ++ci, ++it) {
-    // (a) stage this chunk in the wave's LDS tile; prefetch the next one
+    // (a) stage this chunk in the wave's LDS tile and the Omega rows of chunk
+    //     ci + 2 (both loaded one iteration ago); one barrier per chunk
     store_chunk();
-    if (ci + 1 < ce) load_chunk(ci + 1);
-    // (b) one barrier per chunk
+    if (threadIdx.x < KC * LP) Om[(it + 2) % 4][threadIdx.x] = drm_to_lds<PREC>(omv);
     __syncthreads();
-    // (c) finish the previous chunk's left sketch; build Omega two chunks ahead
+    // (b) prefetch the next chunk and Omega three chunks ahead
+    if (ci + 1 < ce) load_chunk(ci + 1);
+    omv = load_omega(ci + 3);
+    // (c) finish the previous chunk's left sketch
     if (it >= 1) reduce_t((it - 1) & 1, ci - 1);
-    build_omega((it + 2) % 3, ci + 2);
     // (d) matrix-core tiles
     const lds_t* xw = Xl[w];
-    const lds_t* om = Om[it % 3];
+    const lds_t* om = Om[it % 4];
     // right sketch: Y(rows, ell) += X(rows, cols) Omega(cols, ell)
     if constexpr (E::KPL == 1) {
 #pragma unroll
@@ -425,7 +432,7 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
 
   __shared__ double Xl[NW][KC * ST];
   __shared__ double Tred[2][NW][L4 * KC];
-  __shared__ double Om[3][KC * L4];
+  __shared__ double Om[4][KC * L4];  // 4 buffers: each write is a barrier past the last read
 
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -448,17 +455,18 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
     for (int s = 0; s < NS; ++s) psis[ks][s] = psi_row(A, row, 16 * NQ + 4 * s + l4);
   }
 
-  auto build_omega = [&](int buf, int64_t ci) {
+  // Omega_m rows of a chunk: thread t < KC*L4 loads entry (t / L4, t % L4).
+  // The load is issued one iteration before its value is written to LDS, so
+  // waiting for it never waits for the X prefetch (loads retire in order).
+  auto load_omega = [&](int64_t ci) -> double {
     const int t = threadIdx.x;
-    if (t < KC * L4) {
+    double v = 0.0;
+    if (t < KC * L4 && ci < ce) {
       const int col = t / L4, c = t % L4;
-      double v = 0.0;
-      if (ci < ce) {
-        ChunkInfo ch = chunk_info(A, ci);
-        if (col < ch.ncols && c < A.ell) v = A.om_tab[(ch.gcol0 + col) * A.L4 + c];
-      }
-      Om[buf][col * L4 + c] = v;
+      ChunkInfo ch = chunk_info(A, ci);
+      if (col < ch.ncols && c < A.ell) v = A.om_tab[(ch.gcol0 + col) * A.L4 + c];
     }
+    return v;
   };
 
   double xr[NLD][2];
@@ -518,21 +526,40 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
     for (int s = 0; s < NS; ++s) ys[mt][s] = 0.0;
   }
 
+  double omv = 0.0;
   if (cb < ce) {
-    build_omega(0, cb);
-    build_omega(1, cb + 1);
+    if (threadIdx.x < KC * L4) {
+      Om[0][threadIdx.x] = load_omega(cb);
+      Om[1][threadIdx.x] = load_omega(cb + 1);
+    }
     load_chunk(cb);
+    omv = load_omega(cb + 2);
   }
   int it = 0;
   for (int64_t ci = cb; ci < ce; ++ci, ++it) {
+    // (a) stage this chunk's X tile and the Omega rows of chunk ci + 2 (both
+    //     loaded one iteration ago) in LDS
     store_chunk();
-    if (ci + 1 < ce) load_chunk(ci + 1);
+    if (threadIdx.x < KC * L4) Om[(it + 2) % 4][threadIdx.x] = omv;
     __syncthreads();
+    // (b) prefetch the next chunk; Omega three chunks ahead
+    if (ci + 1 < ce) load_chunk(ci + 1);
+    omv = load_omega(ci + 3);
+    // (c) finish the previous chunk's left sketch
     if (it >= 1) reduce_t((it - 1) & 1, ci - 1);
-    build_omega((it + 2) % 3, ci + 2);
     const double* xw = Xl[w];
-    const double* om = Om[it % 3];
-    // right sketch
+    const double* om = Om[it % 4];
+    // (d) matrix-core tiles; the left sketch uses two accumulator chains
+    //     (even / odd K steps) interleaved with the right sketch
+    d4 tq[2][NQ > 0 ? NQ : 1];
+    double ts[2][NS > 0 ? NS : 1];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) tq[h][q] = d4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < NS; ++s) ts[h][s] = 0.0;
+    }
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       const int col = 4 * ks + g4;
@@ -549,30 +576,31 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) ys[mt][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, bs[s], ys[mt][s], 0, 0, 0);
       }
+      // left sketch, K steps 4*ks .. 4*ks + 3
+#pragma unroll
+      for (int kk = 0; kk < KT / (KC / 4); ++kk) {
+        const int k2 = ks * (KT / (KC / 4)) + kk;
+        const double b = xw[l16 * ST + 4 * k2 + g4];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          tq[kk & 1][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(psiq[k2][q], b, tq[kk & 1][q], 0, 0, 0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          ts[kk & 1][s] = __builtin_amdgcn_mfma_f64_4x4x4f64(psis[k2][s], b, ts[kk & 1][s], 0, 0, 0);
+      }
     }
-    // left sketch
-    d4 tq[NQ > 0 ? NQ : 1];
-    double ts[NS > 0 ? NS : 1];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) tq[q] = d4{0, 0, 0, 0};
+    for (int q = 0; q < NQ; ++q) tq[0][q] += tq[1][q];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) ts[s] = 0.0;
-#pragma unroll
-    for (int ks = 0; ks < KT; ++ks) {
-      const double b = xw[l16 * ST + 4 * ks + g4];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) tq[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(psiq[ks][q], b, tq[q], 0, 0, 0);
-#pragma unroll
-      for (int s = 0; s < NS; ++s) ts[s] = __builtin_amdgcn_mfma_f64_4x4x4f64(psis[ks][s], b, ts[s], 0, 0, 0);
-    }
+    for (int s = 0; s < NS; ++s) ts[0][s] += ts[1][s];
     double* tr = Tred[it & 1][w];
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) tr[(16 * q + 4 * v + g4) * KC + l16] = tq[q][v];
+      for (int v = 0; v < 4; ++v) tr[(16 * q + 4 * v + g4) * KC + l16] = tq[0][q][v];
     // 4x4x4: block blk holds columns 4*blk + l4, rows (a) 16*NQ + 4s + g4
 #pragma unroll
-    for (int s = 0; s < NS; ++s) tr[(16 * NQ + 4 * s + g4) * KC + 4 * blk + l4] = ts[s];
+    for (int s = 0; s < NS; ++s) tr[(16 * NQ + 4 * s + g4) * KC + 4 * blk + l4] = ts[0][s];
   }
   __syncthreads();
   if (it >= 1) reduce_t((it - 1) & 1, ce - 1);
