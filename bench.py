@@ -60,8 +60,13 @@ def traffic_from_profiles(workload: str, launches_per_step: int):
     return float(b.group(1))
 
 
-def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 15.0):
-    """Time the oracle (sketches + recovery + error) on a sub-tensor of the same tensor."""
+def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 30.0):
+    """Time the oracle (sketches + recovery + error) on a leading block of the same tensor.
+
+    The sample keeps modes 1..d-1 whole and the first s slices of mode d (a
+    contiguous prefix of the column-major array).  A short probe at s = 1
+    sizes s so that the timed oracle run takes about `target_s` seconds.
+    """
     from oracle import tt_sketch as O
     try:
         import threadpoolctl
@@ -69,25 +74,28 @@ def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 15.0):
     except Exception:
         threads = len(os.sched_getaffinity(0))
     n = list(w.n)
-    d = len(n)
-    # keep the first modes whole, cut the two slowest modes to s entries each
-    s = 8
-    sub = x.reshape(n[::-1])[:s, :s].reshape(-1)      # C-order view (i_d slowest)
-    ns = n[:-2] + [s, s]
-    sub = np.ascontiguousarray(sub)
-    psi_s = {q: psi[q][:ns[q - 1]] for q in psi}
-    om_s = {q: omega[q][:ns[q - 1]] for q in omega}
-    drm = O.NestedKR(psi_s, om_s)
-    t0 = time.perf_counter()
-    out = O.pstt2(sub, ns, drm, ranks=w.ranks())
-    t1 = time.perf_counter()
-    err = O.tt_error(sub, out["cores"])
-    t2 = time.perf_counter()
-    gbs = sub.nbytes / (t2 - t0) / 1e9
+    slab = int(np.prod(n[:-1]))
+
+    def run(s):
+        ns = n[:-1] + [s]
+        sub = np.asarray(x[:slab * s], dtype=np.float64)
+        psi_s = {q: psi[q][:ns[q - 1]] for q in psi}
+        om_s = {q: omega[q][:ns[q - 1]] for q in omega}
+        t0 = time.perf_counter()
+        out = O.pstt2(sub, ns, O.NestedKR(psi_s, om_s), ranks=w.ranks())
+        t1 = time.perf_counter()
+        err = O.tt_error(sub, out["cores"])
+        t2 = time.perf_counter()
+        return ns, sub.nbytes, t1 - t0, t2 - t1, err
+
+    _, nb1, a1, b1, _ = run(1)
+    per_byte = (a1 + b1) / nb1
+    s = int(max(1, min(n[-1], round(target_s / (per_byte * nb1)))))
+    ns, nb, ta, tb, err = run(s)
+    gbs = nb / (ta + tb) / 1e9
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"sub-tensor n={tuple(ns)} ({sub.size} entries, {sub.nbytes / 1e9:.2f} GB) of the same "
-                      f"tensor: oracle sketches+recovery {t1 - t0:.1f} s, error pass {t2 - t1:.1f} s, "
-                      f"rel. error {err:.3e}"}
+            "sample": f"leading block n={tuple(ns)} ({nb // 8} entries, {nb / 1e9:.2f} GB FP64) of the same "
+                      f"tensor: oracle sketches+recovery {ta:.1f} s, error pass {tb:.1f} s, rel. error {err:.3e}"}
 
 
 def run_workload(name, prec, steps, warmup, ranks_from=None):

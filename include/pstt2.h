@@ -62,8 +62,10 @@ typedef enum { PSTT2_F64 = 0, PSTT2_F32 = 1 } pstt2_dtype;
  *   F64     FP64 products and sums (FP64 matrix cores)
  *   F32     FP32 products, FP32 accumulation within a tile, FP64 across tiles
  *   BF16    X and the DRM rounded to bfloat16, FP32 accumulation
- *   BF16X3  X = hi + lo and DRM = hi + lo in bfloat16, hi*hi + hi*lo + lo*hi,
- *           FP32 accumulation (split precision)
+ *   BF16X3  split precision: X and the DRM each split into three bfloat16
+ *           terms t0 + t1 + t2 (exact for FP32 values), the six products
+ *           t_i * t_j with i + j <= 2 on bfloat16 matrix cores, FP32
+ *           accumulation; about FP32 accuracy
  * F32 / BF16 / BF16X3 need dtype F32. */
 typedef enum { PSTT2_P_F64 = 0, PSTT2_P_F32 = 1, PSTT2_P_BF16 = 2, PSTT2_P_BF16X3 = 3 } pstt2_prec;
 

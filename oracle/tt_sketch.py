@@ -20,7 +20,8 @@ split draws its own.
 PSTT2 (Section 3.2, end; equation "PSTT2_final_core"), m = ceil(d/2):
   * column bases Q_k of X_k for k = 1..m-1 from CPQR of S_k = X_k Omega_k;
   * row bases P_k of X_k for k = m..d-1 from CPQR of T_k^T, T_k = Psi_k^T X_k
-    (the paper's "P_j" is the row basis of X_{j-1}; see the reading in DESIGN);
+    (the paper's "P_j" read as the row basis of X_{j-1}, the only index
+    reading consistent with the three-way reshape of its middle-core formula);
   * outer cores from neighbouring bases (equation "core" and its row mirror);
   * the middle core either from a second pass over X (two-pass PSTT2) or from
     the extra sketch Y_R = X_m Omega_m and a least-squares solve (PSTT2-onepass,

@@ -599,21 +599,18 @@ hipError_t middle_z(const double* Qprev, int64_t Rprev, int rprev, const double*
 }
 
 // The value of a DRM entry as the sketch kernel used it: the FP64 product of
-// factors rounded to the sketch arithmetic (FP32, BF16, or BF16 hi + lo).  The
+// factors rounded to the sketch arithmetic (FP32 for FP32 and split BF16, or
+// BF16).  The
 // one-pass middle core pairs Y_R with A = P_m^T Omega_m, so both must see the
 // same Omega_m.
 __device__ __forceinline__ double drm_effective(double v, int prec) {
   if (prec == PSTT2_P_F64) return v;
   const float f = (float)v;
-  if (prec == PSTT2_P_F32) return (double)f;
+  // split BF16 carries all 24 bits of the FP32 value in its three terms
+  if (prec != PSTT2_P_BF16) return (double)f;
   uint32_t u = __float_as_uint(f);
   const uint32_t h = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-  const float hf = __uint_as_float(h << 16);
-  if (prec == PSTT2_P_BF16) return (double)hf;
-  const float rem = f - hf;
-  uint32_t ur = __float_as_uint(rem);
-  const uint32_t l = (ur + 0x7fffu + ((ur >> 16) & 1u)) >> 16;
-  return (double)hf + (double)__uint_as_float(l << 16);
+  return (double)__uint_as_float(h << 16);
 }
 
 // A(b, c) = sum_col Pm(col, b) Omega_m(col, c): one block per c; every thread

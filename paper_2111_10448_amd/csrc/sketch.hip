@@ -43,12 +43,26 @@ __device__ __forceinline__ uint32_t bf16_rne(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return u >> 16;
 }
-// x = hi + lo with hi = bf16(x), lo = bf16(x - hi); packed as hi | lo << 16.
-__device__ __forceinline__ uint32_t split_bf16(float f) {
-  uint32_t h = bf16_rne(f);
-  float hf = __uint_as_float(h << 16);
-  uint32_t l = bf16_rne(f - hf);
-  return h | (l << 16);
+// x = t0 + t1 + t2 with t0 = bf16(x), t1 = bf16(x - t0), t2 = bf16(x - t0 - t1).
+// Each subtraction is exact in FP32 and the three terms hold the whole 24-bit
+// significand, so the split of an FP32 value is exact (barring underflow).
+struct Split3 {
+  short t0, t1, t2;
+};
+__device__ __forceinline__ Split3 split3(float f) {
+  const uint32_t h = bf16_rne(f);
+  const float r1 = f - __uint_as_float(h << 16);
+  const uint32_t m = bf16_rne(r1);
+  const float r2 = r1 - __uint_as_float(m << 16);
+  const uint32_t l = bf16_rne(r2);
+  return Split3{(short)h, (short)m, (short)l};
+}
+// Three-term splits of four FP32 values (one MFMA operand per term).
+__device__ __forceinline__ void split3x4(float a, float b, float c, float d, s4& t0, s4& t1, s4& t2) {
+  const Split3 sa = split3(a), sb = split3(b), sc = split3(c), sd = split3(d);
+  t0 = s4{sa.t0, sb.t0, sc.t0, sd.t0};
+  t1 = s4{sa.t1, sb.t1, sc.t1, sd.t1};
+  t2 = s4{sa.t2, sb.t2, sc.t2, sd.t2};
 }
 
 template <int PREC>
@@ -74,14 +88,23 @@ struct Eng<P_F32> {
 template <>
 struct Eng<P_BF16> {
   using elem = float;
-  using lds_t = uint32_t;  // packed bf16 hi | lo << 16
+  using lds_t = uint32_t;  // bf16 in the low half
   using acc = float;
   using accv = f4;
   using part = float;
-  static constexpr int KPL = 4, KSTEP = 16, RW = 128, VEC = 4, PAD = 4;
+  static constexpr int KPL = 4, KSTEP = 16, RW = 64, VEC = 4, PAD = 4;
 };
+// Split BF16: X and the DRM stay FP32 in LDS and are split into three bf16
+// terms when an operand is formed; the six products of order <= 2 are summed.
 template <>
-struct Eng<P_BF16X3> : Eng<P_BF16> {};
+struct Eng<P_BF16X3> {
+  using elem = float;
+  using lds_t = float;
+  using acc = float;
+  using accv = f4;
+  using part = float;
+  static constexpr int KPL = 4, KSTEP = 16, RW = 64, VEC = 4, PAD = 4;
+};
 
 template <int PREC>
 __device__ __forceinline__ typename Eng<PREC>::lds_t to_lds(typename Eng<PREC>::elem v);
@@ -92,7 +115,7 @@ __device__ __forceinline__ float to_lds<P_F32>(float v) { return v; }
 template <>
 __device__ __forceinline__ uint32_t to_lds<P_BF16>(float v) { return bf16_rne(v); }
 template <>
-__device__ __forceinline__ uint32_t to_lds<P_BF16X3>(float v) { return split_bf16(v); }
+__device__ __forceinline__ float to_lds<P_BF16X3>(float v) { return v; }
 
 // DRM value (FP64 product of factors) converted to the LDS representation.
 template <int PREC>
@@ -100,7 +123,7 @@ __device__ __forceinline__ typename Eng<PREC>::lds_t drm_to_lds(double v) {
   if constexpr (PREC == P_F64) return v;
   else if constexpr (PREC == P_F32) return (float)v;
   else if constexpr (PREC == P_BF16) return bf16_rne((float)v);
-  else return split_bf16((float)v);
+  else return (float)v;
 }
 
 // Row of element v of a lane's 16x16 MFMA accumulator tile (column = lane % 16).
@@ -193,8 +216,12 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
 
   // ---- stationary left-DRM operand (A operand of the left-sketch MFMA) ----
   // element [a][row] with a = 16*mt + l16 and row = K index
+  // (BF16X3: psiA, psiM, psiL are the three split terms)
+  constexpr bool X3 = PREC == P_BF16X3;
   typename std::conditional<E::KPL == 1, lds_t, s4>::type psiA[KT][NT];
-  s4 psiL[(E::KPL == 1) ? 1 : KT][(E::KPL == 1) ? 1 : NT];
+  s4 psiM[X3 ? KT : 1][X3 ? NT : 1];
+  s4 psiL[X3 ? KT : 1][X3 ? NT : 1];
+  (void)psiM;
   (void)psiL;
 #pragma unroll
   for (int ks = 0; ks < KT; ++ks) {
@@ -203,6 +230,11 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
       const int a = 16 * mt + l16;
       if constexpr (E::KPL == 1) {
         psiA[ks][mt] = drm_to_lds<PREC>(psi_row(A, row0w + E::KSTEP * ks + g4, a));
+      } else if constexpr (X3) {
+        float p[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) p[v] = (float)psi_row(A, row0w + 16 * ks + 4 * g4 + v, a);
+        split3x4(p[0], p[1], p[2], p[3], psiA[ks][mt], psiM[ks][mt], psiL[ks][mt]);
       } else {
         uint32_t p[4];
 #pragma unroll
@@ -210,7 +242,6 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
         s4 hi, lo;
         unpack4(p[0], p[1], p[2], p[3], hi, lo);
         psiA[ks][mt] = hi;
-        psiL[ks][mt] = lo;
       }
     }
   }
@@ -337,6 +368,31 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
           }
         }
       }
+    } else if constexpr (X3) {
+      // six products t_i * t_j with i + j <= 2, smallest first
+      s4 b0[NT], b1[NT], b2[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        split3x4(om[(4 * g4 + 0) * LP + 16 * nt + l16], om[(4 * g4 + 1) * LP + 16 * nt + l16],
+                 om[(4 * g4 + 2) * LP + 16 * nt + l16], om[(4 * g4 + 3) * LP + 16 * nt + l16], b0[nt], b1[nt],
+                 b2[nt]);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        s4 a0, a1, a2;
+        const int r = 16 * mt + l16;
+        split3x4(xw[(4 * g4 + 0) * ST + r], xw[(4 * g4 + 1) * ST + r], xw[(4 * g4 + 2) * ST + r],
+                 xw[(4 * g4 + 3) * ST + r], a0, a1, a2);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          accv y = yacc[mt][nt];
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, b0[nt], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1[nt], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b2[nt], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0[nt], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1[nt], y, 0, 0, 0);
+          yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0[nt], y, 0, 0, 0);
+        }
+      }
     } else {
       s4 bh[NT], bl[NT];
 #pragma unroll
@@ -350,13 +406,8 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
         unpack4(xw[(4 * g4 + 0) * ST + r], xw[(4 * g4 + 1) * ST + r], xw[(4 * g4 + 2) * ST + r],
                 xw[(4 * g4 + 3) * ST + r], ah, al);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          if constexpr (PREC == P_BF16X3) {
-            yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[nt], yacc[mt][nt], 0, 0, 0);
-            yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[nt], yacc[mt][nt], 0, 0, 0);
-          }
+        for (int nt = 0; nt < NT; ++nt)
           yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[nt], yacc[mt][nt], 0, 0, 0);
-        }
       }
     }
     // left sketch: T(ell, cols) = Psi(rows, ell)^T X(rows, cols)
@@ -374,18 +425,27 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
           else
             tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
         }
+      } else if constexpr (X3) {
+        const f4 q = *(const f4*)&xw[l16 * ST + 16 * ks + 4 * g4];
+        s4 b0, b1, b2;
+        split3x4(q.x, q.y, q.z, q.w, b0, b1, b2);
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          accv t = tacc[mt];
+          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiL[ks][mt], b0, t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiM[ks][mt], b1, t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], b2, t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiM[ks][mt], b0, t, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], b1, t, 0, 0, 0);
+          tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], b0, t, 0, 0, 0);
+        }
       } else {
         const u4 q = *(const u4*)&xw[l16 * ST + 16 * ks + 4 * g4];
         s4 bh, bl;
         unpack4(q.x, q.y, q.z, q.w, bh, bl);
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) {
-          if constexpr (PREC == P_BF16X3) {
-            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiL[ks][mt], bh, tacc[mt], 0, 0, 0);
-            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], bl, tacc[mt], 0, 0, 0);
-          }
+        for (int mt = 0; mt < NT; ++mt)
           tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], bh, tacc[mt], 0, 0, 0);
-        }
       }
     }
     acc* tr = Tred[it & 1][w];
@@ -657,7 +717,12 @@ hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream
 void sketch_geometry(int prec, int lp, int* rows_per_block, int* threads) {
   (void)lp;
   *threads = NW * 64;
-  *rows_per_block = NW * (prec == P_F64 ? Eng<P_F64>::RW : Eng<P_F32>::RW);
+  switch (prec) {
+    case P_F64: *rows_per_block = NW * Eng<P_F64>::RW; break;
+    case P_F32: *rows_per_block = NW * Eng<P_F32>::RW; break;
+    case P_BF16: *rows_per_block = NW * Eng<P_BF16>::RW; break;
+    default: *rows_per_block = NW * Eng<P_BF16X3>::RW; break;
+  }
 }
 
 template <int PREC, int LP>

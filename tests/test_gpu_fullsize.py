@@ -126,7 +126,7 @@ def test_c2_noisy_full_size():
     assert noise_rel * 0.5 < err < 10 * noise_rel
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 2e-6), ("bf16x3", 1e-4), ("bf16", 2e-2)])
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-6), ("bf16x3", 2e-6), ("bf16", 2e-2)])
 def test_c3_precisions_full_size(prec, tol):
     """d=5, n=64 FP32 1/sum on a Chebyshev grid (1.07e9 entries): sampled sketches, error."""
     w = inputs.WORKLOADS["c3"]
@@ -134,7 +134,7 @@ def test_c3_precisions_full_size(prec, tol):
     x, psi, omega, y, t, err, ranks = _run(w, prec)
     worst = _check_sampled(x, w, psi, omega, y, t, 8, tol, 3)
     say(f"    sampled sketch max rel {worst:.2e}, tt_error {err:.3e}, ranks {ranks}")
-    if prec == "f32":
+    if prec != "bf16":
         assert err <= 1e-5
 
 
