@@ -140,6 +140,26 @@ pstt2_status pstt2_recover(pstt2_ctx* ctx, tt_cores* out);
 pstt2_status pstt2_middle_pass(pstt2_ctx* ctx, tt_cores* cores, const void* x_dev, int64_t first,
                                int64_t count);
 
+/* Vector-Jacobian product of the one-pass map X -> X~ (the cores returned by
+ * the last pstt2_recover of this context, reconstructed by the entry formula
+ * of Section 2.2), with the pivots and ranks of that recovery held fixed.
+ * X~ depends on X only through the two sketches of the middle unfolding, so
+ *   J^T gbar = Ybar Omega_m^T + Psi_m Tbar_m,
+ * where (Ybar, Tbar_m) are the cotangents of Y_R and T_m obtained by running
+ * the recovery (least squares, outer cores, QR of the pivoted sketch columns,
+ * derived sketches) backwards in FP64 on the GPU.
+ *   gbar_dev != NULL: gx_dev = J^T gbar (gbar and gx have X's shape and dtype);
+ *                     x_dev is not read and may be NULL.
+ *   gbar_dev == NULL: gx_dev = gradient of ||X - X~||_F^2 with respect to X,
+ *                     i.e. 2 (X - X~) + J^T (-2 (X - X~)); x_dev must be the
+ *                     tensor that was sketched.
+ * gx_dev is caller-owned device memory of N entries of the context's dtype.
+ * Uses stream-ordered device workspace (about 8 N bytes).  sync.
+ * Errors: ESTATE (no successful pstt2_recover, or two-pass middle core),
+ * EINVAL (null pointers, cores not from this context), ENOMEM, EDEVICE. */
+pstt2_status pstt2_vjp(pstt2_ctx* ctx, const tt_cores* cores, const void* x_dev, const void* gbar_dev,
+                       void* gx_dev);
+
 /* Copy an accumulated or derived sketch to host memory (FP64, column-major).
  * which = 0: the right sketch of split k (1 <= k <= m; k = m is Y_R), R_k x ell.
  * which = 1: the transposed left sketch T_k^T of split k (m <= k <= d-1), C_k x ell.

@@ -21,7 +21,8 @@ import numpy as np
 from . import _lib as L
 from ._lib import PSTT2Error  # noqa: F401
 
-__all__ = ["PSTT2", "TT", "PSTT2Error", "decompose", "tt_error", "tt_reconstruct", "version", "cores_struct"]
+__all__ = ["PSTT2", "TT", "PSTT2Error", "decompose", "tt_error", "tt_reconstruct", "version", "cores_struct",
+           "PSTT2Reconstruct", "pstt2_reconstruct"]
 
 
 def _torch():
@@ -219,6 +220,24 @@ class PSTT2:
                                           int(first), int(x.numel())), self._ctx)
         self._keep.append(x)
 
+    def vjp(self, tt: "TT", x=None, gbar=None):
+        """J^T gbar for X~ = the one-pass approximation (pivots and ranks of the last
+        recover held fixed); with gbar None, the gradient of ||X - X~||_F^2 (needs x).
+        Returns a flat CUDA tensor of the context's dtype."""
+        torch = _torch()
+        ref = gbar if gbar is not None else x
+        if ref is None:
+            raise ValueError("give gbar, or x for the Frobenius-loss gradient")
+        for t in (x, gbar):
+            if t is not None:
+                _check_dev(t)
+        gx = torch.empty(ref.numel(), dtype=ref.dtype, device=ref.device)
+        L.check(L.lib().pstt2_vjp(self._c(), ctypes.byref(tt.struct()),
+                                  ctypes.c_void_p(x.data_ptr() if x is not None else 0),
+                                  ctypes.c_void_p(gbar.data_ptr() if gbar is not None else 0),
+                                  ctypes.c_void_p(gx.data_ptr())), self._ctx)
+        return gx
+
     def get_sketch(self, which: int, k: int) -> np.ndarray:
         """which = 0: right sketch of split k (R_k x ell); 1: transposed left sketch (C_k x ell)."""
         rows = ctypes.c_int64()
@@ -306,3 +325,53 @@ def decompose(x, n: Sequence[int], ell: int, factors: np.ndarray, *, prec: Optio
             ctx.middle_pass(tt, x.reshape(-1))
             _torch().cuda.synchronize()
         return tt
+
+
+def _make_function():
+    torch = _torch()
+
+    class PSTT2Reconstruct(torch.autograd.Function):
+        """X -> X~ (PSTT2-onepass then the entry formula) with the hand-written adjoint.
+
+        forward(x, n, ell, factors, prec, ranks, eps, rmax): x is a flat column-major
+        CUDA tensor; returns X~ in x's dtype.  backward runs pstt2_vjp with the
+        forward pass's pivots and ranks held fixed; gradients flow to x only.
+        """
+
+        @staticmethod
+        def forward(ctx, x, n, ell, factors, prec=None, ranks=None, eps=None, rmax=0):
+            dtype = "f64" if _dtype_code(x) == L.F64 else "f32"
+            p = PSTT2(n, ell, factors, dtype=dtype, prec=prec, ranks=ranks, eps=eps, rmax=rmax)
+            xf = x.detach().reshape(-1)
+            p.sketch(xf)
+            tt = p.recover()
+            ctx.pstt2 = p
+            ctx.tt = tt
+            return tt.reconstruct(dtype=x.dtype).view_as(x)
+
+        @staticmethod
+        def backward(ctx, gout):
+            gx = ctx.pstt2.vjp(ctx.tt, gbar=gout.contiguous().reshape(-1))
+            ctx.tt.free()
+            ctx.pstt2.close()
+            return gx.view_as(gout), None, None, None, None, None, None, None
+
+    return PSTT2Reconstruct
+
+
+_fn = None
+
+
+def __getattr__(name):
+    global _fn
+    if name == "PSTT2Reconstruct":
+        if _fn is None:
+            _fn = _make_function()
+        return _fn
+    raise AttributeError(name)
+
+
+def pstt2_reconstruct(x, n: Sequence[int], ell: int, factors: np.ndarray, *, prec: Optional[str] = None,
+                      ranks: Optional[Sequence[int]] = None, eps: Optional[float] = None, rmax: int = 0):
+    """Differentiable X~ = PSTT2-onepass approximation of x (see PSTT2Reconstruct)."""
+    return __getattr__("PSTT2Reconstruct").apply(x, list(n), int(ell), factors, prec, ranks, eps, rmax)

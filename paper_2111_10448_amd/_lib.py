@@ -70,6 +70,7 @@ def lib():
     L.pstt2_sketch_slabs.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.pstt2_recover.argtypes = [vp, ctypes.POINTER(TTCores)]
     L.pstt2_middle_pass.argtypes = [vp, ctypes.POINTER(TTCores), vp, i64, i64]
+    L.pstt2_vjp.argtypes = [vp, ctypes.POINTER(TTCores), vp, vp, vp]
     L.pstt2_get_sketch.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                    ctypes.POINTER(i64)]
     L.pstt2_get_pivots.argtypes = [vp, i32, ctypes.POINTER(i32)]
@@ -87,7 +88,7 @@ def lib():
     L.pstt2_last_error.restype = ctypes.c_char_p
     L.pstt2_version.argtypes = []
     L.pstt2_version.restype = ctypes.c_char_p
-    for f in ("pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass",
+    for f in ("pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
               "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_reset", "tt_error", "tt_reconstruct", "tt_cores_copy",
               "pstt2_profile", "pstt2_profile_read"):
         getattr(L, f).restype = st
@@ -102,7 +103,7 @@ def check(status: int, ctx=None) -> None:
 
 
 # Every symbol include/pstt2.h declares.
-EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass",
+EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
            "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_profile", "pstt2_profile_read", "pstt2_reset",
            "pstt2_destroy", "tt_error", "tt_reconstruct",
            "tt_cores_copy", "tt_cores_free", "pstt2_last_error", "pstt2_version"]

@@ -591,6 +591,183 @@ pstt2_status pstt2_middle_pass(pstt2_ctx* c, tt_cores* cores, const void* x_dev,
   return PSTT2_OK;
 }
 
+pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, const void* gbar_dev,
+                       void* gx_dev) {
+  if (!c || !cores || !gx_dev) return fail(c, PSTT2_EINVAL, "null argument");
+  if (!gbar_dev && !x_dev) return fail(c, PSTT2_EINVAL, "x_dev is needed for the fused loss (gbar_dev == NULL)");
+  if (!c->recovered) return fail(c, PSTT2_ESTATE, "pstt2_vjp needs a successful pstt2_recover first");
+  if (c->desc.mid != PSTT2_MID_ONEPASS) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the one-pass middle core only");
+  const int d = c->d, m = c->m, ell = c->ell;
+  if (cores->d != d) return fail(c, PSTT2_EINVAL, "cores do not match the context");
+  for (int k = 0; k < d; ++k)
+    if (cores->n[k] != c->n[k] || !cores->core[k]) return fail(c, PSTT2_EINVAL, "cores do not match the context");
+  for (int k = 0; k <= d; ++k)
+    if (cores->r[k] != c->ranks[k]) return fail(c, PSTT2_EINVAL, "core ranks differ from the last recovery");
+  hipStream_t s = c->stream;
+  const int* r = c->ranks;
+  const int64_t* Rk = c->Rk;
+  auto Ck = [&](int k) { return c->N / Rk[k]; };
+  std::vector<void*> ws;
+  hipError_t e = hipSuccess;
+  auto take = [&](int64_t count, bool zero) -> double* {
+    void* p = nullptr;
+    if (e != hipSuccess) return nullptr;
+    e = hipMallocAsync(&p, sizeof(double) * std::max<int64_t>(count, 1), s);
+    if (e != hipSuccess) return nullptr;
+    ws.push_back(p);
+    if (zero) e = hipMemsetAsync(p, 0, sizeof(double) * std::max<int64_t>(count, 1), s);
+    return (double*)p;
+  };
+  auto release = [&]() {
+    for (void* p : ws) (void)hipFreeAsync(p, s);
+    ws.clear();
+  };
+#define VJPCK(call)                        \
+  do {                                     \
+    if (e == hipSuccess) e = (call);       \
+  } while (0)
+  // ---- interfaces L_k (R_k x r_k), k = 1..m, and Rt_k (r_{k-1} x C_{k-1}), k = m+1..d ----
+  std::vector<const double*> Lv(d + 2, nullptr), Rv(d + 2, nullptr);
+  Lv[1] = cores->core[0];
+  for (int k = 2; k <= m; ++k) {
+    double* L = take(Rk[k] * r[k], false);
+    VJPCK(adj_gemm(false, false, Rk[k - 1], c->n[k - 1] * r[k], r[k - 1], 1.0, Lv[k - 1], Rk[k - 1],
+                   cores->core[k - 1], r[k - 1], 0.0, L, Rk[k - 1], s));
+    Lv[k] = L;
+  }
+  Rv[d] = cores->core[d - 1];
+  for (int k = d - 1; k >= m + 1; --k) {
+    double* Rt = take((int64_t)r[k - 1] * Ck(k - 1), false);
+    VJPCK(adj_gemm(false, false, (int64_t)r[k - 1] * c->n[k - 1], Ck(k), r[k], 1.0, cores->core[k - 1],
+                   (int64_t)r[k - 1] * c->n[k - 1], Rv[k + 1], r[k], 0.0, Rt, (int64_t)r[k - 1] * c->n[k - 1], s));
+    Rv[k] = Rt;
+  }
+  const int rm = r[m];
+  const double* Lm = Lv[m];
+  const double* Rtm = Rv[m + 1];
+  // ---- B1: the cotangent and its dual contraction with the interfaces ----
+  double* g64 = take(c->N, false);
+  VJPCK(adj_cotangent(c->dtype, x_dev, gbar_dev, c->N, c->R, rm, Lm, Rtm, g64, s));
+  const int L4r = (rm + 3) / 4 * 4;
+  double* psiT = take(c->R * L4r, false);
+  double* omT = take(c->C * L4r, false);
+  VJPCK(adj_table(Lm, c->R, rm, 1, c->R, L4r, psiT, s));
+  VJPCK(adj_table(Rtm, c->C, rm, rm, 1, L4r, omT, s));
+  SketchArgs a = base_args(c);
+  a.ell = rm;
+  a.L4 = L4r;
+  a.om_tab = omT;
+  a.psi_tab = psiT;
+  int rpb = 0, thr = 0;
+  sketch_geometry(PSTT2_P_F64, 0, &rpb, &thr);
+  a.gi_count = (int)((c->R + rpb - 1) / rpb);
+  a.nchunks = (c->C + 15) / 16;
+  a.gj_count = (int)std::max<int64_t>(1, std::min<int64_t>(a.nchunks, std::max(1, c->ncu / a.gi_count)));
+  a.nseg = 1;
+  a.seg[0].ptr = g64;
+  a.seg[0].gcol0 = 0;
+  a.seg[0].ncols = c->C;
+  a.seg[0].chunk0 = 0;
+  a.ypart = take((int64_t)a.gj_count * rm * c->R, false);
+  a.tpart = take((int64_t)a.gi_count * rm * c->C, false);
+  double* U = take(c->R * rm, true);    // Lbar_m = gbar_m Rt^T        (R x r_m)
+  double* Vt = take(c->C * rm, true);   // (L_m^T gbar_m)^T           (C x r_m)
+  if (e == hipSuccess) e = launch_sketch(PSTT2_P_F64, 0, a, s);
+  if (e == hipSuccess) e = launch_reduce(PSTT2_P_F64, a, U, Vt, c->flag, s);
+  // core cotangents, laid out like the cores
+  std::vector<double*> Gb(d, nullptr);
+  for (int k = 0; k < d; ++k) Gb[k] = take((int64_t)r[k] * c->n[k] * r[k + 1], true);
+  const double* Lb = U;
+  for (int k = m; k >= 2; --k) {
+    const int64_t nr = c->n[k - 1] * r[k];
+    VJPCK(adj_gemm(true, false, r[k - 1], nr, Rk[k - 1], 1.0, Lv[k - 1], Rk[k - 1], Lb, Rk[k - 1], 0.0, Gb[k - 1],
+                   r[k - 1], s));
+    double* Lbp = take(Rk[k - 1] * r[k - 1], false);
+    VJPCK(adj_gemm(false, true, Rk[k - 1], r[k - 1], nr, 1.0, Lb, Rk[k - 1], cores->core[k - 1], r[k - 1], 0.0, Lbp,
+                   Rk[k - 1], s));
+    Lb = Lbp;
+  }
+  VJPCK(adj_axpy(c->n[0] * r[1], 1.0, Lb, Gb[0], s));
+  double* Rb = take((int64_t)rm * c->C, false);
+  VJPCK(adj_transpose(Vt, c->C, rm, Rb, s));
+  for (int k = m + 1; k <= d - 1; ++k) {
+    const int64_t rn = (int64_t)r[k - 1] * c->n[k - 1];
+    VJPCK(adj_gemm(false, true, rn, r[k], Ck(k), 1.0, Rb, rn, Rv[k + 1], r[k], 0.0, Gb[k - 1], rn, s));
+    double* Rbn = take((int64_t)r[k] * Ck(k), false);
+    VJPCK(adj_gemm(true, false, r[k], Ck(k), rn, 1.0, cores->core[k - 1], rn, Rb, rn, 0.0, Rbn, r[k], s));
+    Rb = Rbn;
+  }
+  VJPCK(adj_axpy((int64_t)r[d - 1] * c->n[d - 1], 1.0, Rb, Gb[d - 1], s));
+  // ---- B2: back through the recovery ----
+  std::vector<double*> Qb(d + 1, nullptr);
+  for (int k = 1; k <= d - 1; ++k) Qb[k] = take((k < m ? Rk[k] : Ck(k)) * r[k], true);
+  const double* Qprev = m >= 2 ? c->basis[m - 1] : c->one;
+  const int64_t Rprev = Rk[m - 1];
+  const int rprev = r[m - 1];
+  const int nm = (int)c->n[m - 1];
+  const int64_t p = (int64_t)rprev * nm;
+  double* Z = take(p * ell, false);
+  double* A = take((int64_t)rm * ell, false);
+  double* Zb = take(p * ell, false);
+  double* Ab = take((int64_t)rm * ell, false);
+  VJPCK(middle_z(Qprev, Rprev, rprev, c->Y, c->R, nm, ell, Z, s));
+  SketchArgs geo = base_args(c);
+  VJPCK(middle_a(c->basis[m], c->C, rm, geo, c->prec, A, s));
+  VJPCK(adj_ls(cores->core[m - 1], Gb[m - 1], Z, A, p, rm, ell, Zb, Ab, s));
+  double* Yb = take(c->R * ell, true);
+  if (m >= 2)
+    VJPCK(adj_gemm(false, true, Rprev, rprev, (int64_t)nm * ell, 1.0, c->Y, Rprev, Zb, rprev, 1.0, Qb[m - 1], Rprev,
+                   s));
+  VJPCK(adj_gemm(false, false, Rprev, (int64_t)nm * ell, rprev, 1.0, Qprev, Rprev, Zb, rprev, 1.0, Yb, Rprev, s));
+  VJPCK(adj_pbar(c->om_tab, c->L4, c->C, rm, ell, c->prec, Ab, Qb[m], s));
+  for (int k = m - 1; k >= 2; --k) {
+    const int64_t nr = c->n[k - 1] * r[k];
+    VJPCK(adj_gemm(false, true, Rk[k - 1], r[k - 1], nr, 1.0, c->basis[k], Rk[k - 1], Gb[k - 1], r[k - 1], 1.0,
+                   Qb[k - 1], Rk[k - 1], s));
+    VJPCK(adj_gemm(false, false, Rk[k - 1], nr, r[k - 1], 1.0, c->basis[k - 1], Rk[k - 1], Gb[k - 1], r[k - 1], 1.0,
+                   Qb[k], Rk[k - 1], s));
+  }
+  if (m >= 2) VJPCK(adj_axpy(c->n[0] * r[1], 1.0, Gb[0], Qb[1], s));
+  for (int k = m + 1; k <= d - 1; ++k)
+    VJPCK(adj_core_right(Gb[k - 1], c->basis[k - 1], c->basis[k], Ck(k), (int)c->n[k - 1], r[k - 1], r[k], Qb[k - 1],
+                         Qb[k], s));
+  {
+    // G_d = P_{d-1}^T: Pbar_{d-1} += Gbar_d^T
+    double* tmp = take((int64_t)r[d - 1] * c->n[d - 1], false);
+    VJPCK(adj_transpose(Gb[d - 1], r[d - 1], c->n[d - 1], tmp, s));
+    VJPCK(adj_axpy((int64_t)r[d - 1] * c->n[d - 1], 1.0, tmp, Qb[d - 1], s));
+  }
+  // sketch cotangents: Sbar_k (k < m), Ybar (= Sbar_m), Tbar_k (k >= m, transposed layout)
+  std::vector<double*> Sb(d + 1, nullptr);
+  for (int k = 1; k < m; ++k) Sb[k] = take(Rk[k] * ell, true);
+  Sb[m] = Yb;
+  std::vector<double*> Tb(d + 1, nullptr);
+  for (int k = m; k <= d - 1; ++k) Tb[k] = take(Ck(k) * ell, true);
+  for (int k = 1; k <= d - 1; ++k) {
+    const bool left = k < m;
+    const int64_t Mk = left ? Rk[k] : Ck(k);
+    VJPCK(adj_qr(left ? c->S[k] : c->Tk[k], c->basis[k], Qb[k], Mk, ell, r[k], c->piv_dev + (int64_t)k * ell,
+                 left ? Sb[k] : Tb[k], s));
+  }
+  for (int k = 1; k <= m - 1; ++k)
+    VJPCK(adj_derive_left(Sb[k], Sb[k + 1], Rk[k], (int)c->n[k], ell, c->fac + c->omega_off[k], s));
+  for (int k = d - 1; k >= m + 1; --k)
+    VJPCK(adj_derive_right(Tb[k], Tb[k - 1], Ck(k), (int)c->n[k - 1], ell, c->fac + c->psi_off[k - 1], s));
+  // ---- B3: gx = Ybar Omega_m^T + Psi_m Tbar_m  (+ 2 (X - X~)) ----
+  const bool fused = gbar_dev == nullptr;
+  VJPCK(adj_out(c->dtype, geo, c->prec, Yb, Tb[m], fused ? Lm : nullptr, fused ? Rtm : nullptr, rm, x_dev, gx_dev,
+                s));
+#undef VJPCK
+  release();
+  int hflag = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  hipError_t e2 = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hfail(c, e, "pstt2_vjp");
+  if (e2 != hipSuccess) return hfail(c, e2, "pstt2_vjp");
+  if (hflag & 1) return fail(c, PSTT2_ENUMERIC, "non-finite values in the cotangent");
+  return PSTT2_OK;
+}
+
 pstt2_status pstt2_get_sketch(pstt2_ctx* c, int32_t which, int32_t k, double* host_out, int64_t* rows,
                               int64_t* cols) {
   if (!c || !rows || !cols) return fail(c, PSTT2_EINVAL, "null argument");

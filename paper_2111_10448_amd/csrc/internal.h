@@ -41,6 +41,7 @@ struct SketchArgs {
   int64_t C;         // columns of X_m (for the tpart stride)
   const double* om_tab;  // Omega_m(col, c) table, C x L4, FP64
   int32_t L4;            // its row stride: ell rounded up to a multiple of 4
+  const double* psi_tab; // optional Psi(row, a) table, R x L4 (else products of the factors)
   Seg seg[kMaxSeg];
 };
 
@@ -88,6 +89,30 @@ hipError_t middle_ls(const double* Z, int64_t nz, const double* A, int rm, int e
 hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count, int64_t Rprev, int nm,
                           int64_t Cm, const double* Qprev, int rprev, const double* Pm, int rm, double* G,
                           hipStream_t s);
+
+// Adjoint building blocks (adjoint.hip); FP64, column-major.
+hipError_t adj_gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s);
+hipError_t adj_table(const double* in, int64_t rows, int cnt, int64_t si, int64_t sc, int L4, double* out,
+                     hipStream_t s);
+hipError_t adj_transpose(const double* A, int64_t arows, int64_t acols, double* B, hipStream_t s);
+hipError_t adj_axpy(int64_t n, double alpha, const double* X, double* Y, hipStream_t s);
+hipError_t adj_cotangent(int dtype, const void* x, const void* gbar, int64_t N, int64_t R, int r, const double* L,
+                         const double* Rt, double* out, hipStream_t s);
+hipError_t adj_ls(const double* G, const double* Gb, const double* Z, const double* A, int64_t p, int r, int ell,
+                  double* Zb, double* Ab, hipStream_t s);
+hipError_t adj_core_right(const double* Gb, const double* Pp, const double* Pk, int64_t Ck, int nk, int rp, int rk,
+                          double* Ppb, double* Pkb, hipStream_t s);
+hipError_t adj_pbar(const double* om_tab, int L4, int64_t Cm, int rm, int ell, int prec, const double* Ab, double* Pb,
+                    hipStream_t s);
+hipError_t adj_qr(const double* S, const double* Q, const double* Qb, int64_t M, int ell, int r, const int* piv,
+                  double* Sb, hipStream_t s);
+hipError_t adj_derive_left(const double* Sbk, double* Sbk1, int64_t Rk, int nk1, int ell, const double* om,
+                           hipStream_t s);
+hipError_t adj_derive_right(const double* Tbk, double* Tbp, int64_t Ck, int nk, int ell, const double* ps,
+                            hipStream_t s);
+hipError_t adj_out(int dtype, const SketchArgs& g, int prec, const double* Yb, const double* Tbt, const double* L,
+                   const double* Rt, int r, const void* x, void* gx, hipStream_t s);
 
 // TT evaluation (tt_eval.hip).
 hipError_t tt_interfaces(const tt_cores* c, int split, double** L, double** Rt, hipStream_t s);

@@ -142,6 +142,7 @@ __device__ __forceinline__ void unpack4(uint32_t a, uint32_t b, uint32_t c, uint
 // Psi_m(row, a) for a global row of X_m (0 outside the matrix / sketch).
 __device__ __forceinline__ double psi_row(const SketchArgs& A, int64_t row, int a) {
   if (row >= A.R || a >= A.ell) return 0.0;
+  if (A.psi_tab) return A.psi_tab[row * A.L4 + a];
   double v = 1.0;
   int64_t r = row;
   for (int q = 1; q <= A.m; ++q) {
