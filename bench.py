@@ -98,6 +98,9 @@ def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 30.0):
                       f"tensor: oracle sketches+recovery {ta:.1f} s, error pass {tb:.1f} s, rel. error {err:.3e}"}
 
 
+_HOST = {}
+
+
 def run_workload(name, prec, steps, warmup, ranks_from=None):
     import torch
     import inputs
@@ -105,10 +108,15 @@ def run_workload(name, prec, steps, warmup, ranks_from=None):
 
     w = inputs.WORKLOADS[name]
     t0 = time.perf_counter()
-    x = inputs.make_tensor(w)
-    psi, omega = inputs.drm_factors(w)
+    if _HOST.get("name") != name:     # keep the last workload's host tensor for the next precision
+        _HOST.clear()
+        x = inputs.make_tensor(w)
+        psi, omega = inputs.drm_factors(w)
+        _HOST.update(name=name, x=x, psi=psi, omega=omega)
+        log(f"[bench] {name}: generated {x.nbytes / 1e9:.2f} GB on the host in {time.perf_counter() - t0:.1f} s")
+    x, psi, omega = _HOST["x"], _HOST["psi"], _HOST["omega"]
     fac = inputs.pack_factors(psi, omega, w.d)
-    log(f"[bench] {name}: generated {x.nbytes / 1e9:.2f} GB on the host in {time.perf_counter() - t0:.1f} s")
+    log(f"[bench] {name} {prec}: timing {steps} steps")
     xg = torch.from_numpy(x).to("cuda:0")
     torch.cuda.synchronize()
     kw = dict(dtype=w.dtype, prec=prec)
@@ -120,10 +128,21 @@ def run_workload(name, prec, steps, warmup, ranks_from=None):
         kw["eps"] = w.eps
         kw["rmax"] = w.rmax
     ctx = P.PSTT2(w.n, w.ell, fac, **kw)
+    if w.nslabs > 1:
+        # contiguous runs of whole mode-1 fibres, views of the resident tensor
+        bounds = inputs.slab_bounds(x.size, w.n[0], w.nslabs)
+        xs = [xg[f:f + c] for f, c in bounds]
+        firsts = [f for f, _ in bounds]
+
+    def sketch():
+        if w.nslabs > 1:
+            ctx.sketch_slabs(xs, firsts)
+        else:
+            ctx.sketch(xg)
 
     def step():
         ctx.reset()
-        ctx.sketch(xg)
+        sketch()
         tt = ctx.recover()
         e = tt.error(xg)
         return tt, e
@@ -139,7 +158,7 @@ def run_workload(name, prec, steps, warmup, ranks_from=None):
     for _ in range(steps):
         a = time.perf_counter()
         ctx.reset()
-        ctx.sketch(xg)
+        sketch()
         tt = ctx.recover()
         b = time.perf_counter()
         err = tt.error(xg)
@@ -160,6 +179,44 @@ def run_workload(name, prec, steps, warmup, ranks_from=None):
     return res
 
 
+def run_adjoint(steps, warmup):
+    """Forward PSTT2 + X~ and the hand-written gradient of ||X - X~||_F^2 on the d=4, n=48 FP32 tensor."""
+    import torch
+    import inputs
+    import paper_2111_10448_amd as P
+
+    w = inputs.WORKLOADS["c5"]
+    x = inputs.make_tensor(w)
+    psi, omega = inputs.drm_factors(w)
+    fac = inputs.pack_factors(psi, omega, w.d)
+    xg = torch.from_numpy(x).to("cuda:0")
+    ctx = P.PSTT2(w.n, w.ell, fac, dtype=w.dtype, prec="f32", ranks=w.ranks())
+    fwd = bwd = 0.0
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        ctx.reset()
+        ctx.sketch(xg)
+        tt = ctx.recover()
+        xt = tt.reconstruct(dtype=xg.dtype)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        g = ctx.vjp(tt, x=xg)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        if it >= warmup:
+            fwd += b - a
+            bwd += c - b
+        tt.free()
+    loss = float(torch.sum((xg.double() - xt.double()) ** 2))
+    out = {"workload": f"c5: d={w.d} n={w.n[0]} ({w.numel} entries, f32), TT rank {w.tt_rank} + noise "
+                       f"{w.noise:g}, ranks {w.rank}, sketch size {w.ell}",
+           "forward_ms": round(fwd * 1e3 / steps, 4), "vjp_ms": round(bwd * 1e3 / steps, 4),
+           "loss": loss, "grad_norm": float(torch.linalg.vector_norm(g.double()))}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,8 +225,9 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--prec", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", action="store_true",
-                    help="also time the Chebyshev 1/sum workload in FP64, FP32, split-BF16 and BF16")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the precision study (1/sum tensor in FP64, FP32, split BF16, BF16), the "
+                         "64-slab stream and the adjoint")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a 2 GiB device copy (counter calibration under rocprofv3) and exit")
     args = ap.parse_args()
@@ -219,21 +277,26 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(name, 1),
                      "fp64_frac": round(flops / (r["kernel_ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)},
     }
-    if args.variants:
+    if not args.no_variants:
         var = {}
-        for vp in ("f64", "f32", "bf16x3", "bf16"):
-            wn = "c3_f64" if vp == "f64" else "c3"
+        for wn, vp in (("c3_f64", "f64"), ("c3", "f32"), ("c3", "bf16x3"), ("c3", "bf16"), ("c4", "f32"),
+                       ("c4", "bf16x3")):
             try:
                 rv = run_workload(wn, vp, max(3, args.steps // 2), 1)
                 wv = rv["workload"]
                 kbv = rv["bytes"] / max(rv["launches_per_step"], 1)
-                var[vp] = {"workload": wn, "sketch_kernel_ms": round(rv["kernel_ms"], 4),
+                var[f"{wn}_{vp}"] = {"workload": wn, "sketch_arithmetic": vp,
+                           "sketch_kernel_ms": round(rv["kernel_ms"], 4),
                            "sketch_gbs": round(kbv / (rv["kernel_ms"] * 1e-3) / 1e9, 2),
                            "ms_per_step": round(rv["ms_per_step"], 4), "ranks": rv["ranks"],
                            "tt_rel_error": rv["err"]}
             except Exception as e:   # report, keep the headline line
-                var[vp] = {"error": str(e)}
+                var[f"{wn}_{vp}"] = {"error": str(e)}
         record["variants"] = var
+        try:
+            record["adjoint"] = run_adjoint(max(3, args.steps // 2), 1)
+        except Exception as e:
+            record["adjoint"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         record["cpu_baseline"] = cpu_baseline(r["x"], w, r["psi"], r["omega"])
     print(json.dumps(record), flush=True)

@@ -163,7 +163,7 @@ pstt2_status pstt2_vjp(pstt2_ctx* ctx, const tt_cores* cores, const void* x_dev,
 /* Copy an accumulated or derived sketch to host memory (FP64, column-major).
  * which = 0: the right sketch of split k (1 <= k <= m; k = m is Y_R), R_k x ell.
  * which = 1: the transposed left sketch T_k^T of split k (m <= k <= d-1), C_k x ell.
- * Valid after pstt2_recover.  *rows/*cols receive the shape; host_out must hold
+ * Valid after pstt2_recover.  *rows and *cols receive the shape; host_out must hold
  * rows*cols doubles (pass host_out = NULL to query the shape).  sync. */
 pstt2_status pstt2_get_sketch(pstt2_ctx* ctx, int32_t which, int32_t k, double* host_out, int64_t* rows,
                               int64_t* cols);

@@ -303,10 +303,10 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   if ((e = hipMalloc(&c->one, sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(one)");
   const double one = 1.0;
   if ((e = hipMemcpy(c->one, &one, sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "hipMemcpy");
-  int rows_per_block = 0, threads = 0;
-  sketch_geometry(c->prec, c->lp, &rows_per_block, &threads);
+  int rows_per_block = 0, threads = 0, wg_per_cu = 1;
+  sketch_geometry(c->prec, c->ell, &rows_per_block, &threads, &wg_per_cu);
   c->gi = (int)((c->R + rows_per_block - 1) / rows_per_block);
-  c->gj_max = std::max(1, c->ncu / c->gi);
+  c->gj_max = std::max(1, c->ncu * wg_per_cu / c->gi);
   const size_t psz = c->prec == PSTT2_P_F64 ? 8 : 4;
   if ((e = hipMalloc(&c->ypart, psz * c->gj_max * c->ell * c->R)) != hipSuccess) return bail(e, "hipMalloc(ypart)");
   if ((e = hipMalloc(&c->tpart, psz * c->gi * c->ell * c->C)) != hipSuccess) return bail(e, "hipMalloc(tpart)");
@@ -658,11 +658,11 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   a.L4 = L4r;
   a.om_tab = omT;
   a.psi_tab = psiT;
-  int rpb = 0, thr = 0;
-  sketch_geometry(PSTT2_P_F64, 0, &rpb, &thr);
+  int rpb = 0, thr = 0, wpc = 1;
+  sketch_geometry(PSTT2_P_F64, rm, &rpb, &thr, &wpc);
   a.gi_count = (int)((c->R + rpb - 1) / rpb);
   a.nchunks = (c->C + 15) / 16;
-  a.gj_count = (int)std::max<int64_t>(1, std::min<int64_t>(a.nchunks, std::max(1, c->ncu / a.gi_count)));
+  a.gj_count = (int)std::max<int64_t>(1, std::min<int64_t>(a.nchunks, std::max(1, c->ncu * wpc / a.gi_count)));
   a.nseg = 1;
   a.seg[0].ptr = g64;
   a.seg[0].gcol0 = 0;

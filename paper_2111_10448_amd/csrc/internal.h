@@ -49,8 +49,9 @@ struct SketchArgs {
 hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s);
 // Build the Omega_m table (C x L4, FP64) from the factors.
 hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream_t s);
-// Per-precision launch geometry.
-void sketch_geometry(int prec, int lp, int* rows_per_block, int* threads);
+// Per-precision launch geometry: rows of X_m per workgroup, threads per
+// workgroup, workgroups resident per CU.
+void sketch_geometry(int prec, int ell, int* rows_per_block, int* threads, int* wg_per_cu);
 // Sum the tile partials of one launch into the FP64 accumulators (fixed order).
 hipError_t launch_reduce(int prec, const SketchArgs& a, double* Y, double* Tt, int* flag, hipStream_t s);
 // FP64 contribution of one partial column (rows [r0, r1) of global column gcol).

@@ -613,38 +613,70 @@ __device__ __forceinline__ double drm_effective(double v, int prec) {
   return (double)__uint_as_float(h << 16);
 }
 
-// A(b, c) = sum_col Pm(col, b) Omega_m(col, c): one block per c; every thread
-// forms Omega_m(col, c) once per column and accumulates all r_m rows of A.
-__global__ __launch_bounds__(256) void k_middle_a(const double* __restrict__ Pm, int64_t Cm, int rm,
-                                                  const SketchArgs G, int prec, double* __restrict__ A) {
-  __shared__ double red[PSTT2_MAX_ELL][4];
-  const int c = blockIdx.x;
-  double acc[PSTT2_MAX_ELL];
+// A(b, c) = sum_col Pm(col, b) Omega_m(col, c).  Every block takes a contiguous
+// range of columns in 64-column tiles staged through LDS (coalesced reads of
+// Pm and of the Omega_m table) and writes its r_m x ell partial; a second
+// kernel adds the partials in block order (deterministic).
+constexpr int MA_TILE = 64;
+constexpr int MA_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void k_middle_a_part(const double* __restrict__ Pm, int64_t Cm, int rm,
+                                                       const SketchArgs G, int prec, double* __restrict__ part) {
+  __shared__ double Pl[MA_TILE][PSTT2_MAX_ELL + 1];
+  __shared__ double Ol[MA_TILE][PSTT2_MAX_ELL + 1];
+  const int ell = G.ell;
+  const int nout = rm * ell;
+  const int64_t c0 = (int64_t)blockIdx.x * Cm / gridDim.x, c1 = (int64_t)(blockIdx.x + 1) * Cm / gridDim.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};   // outputs t, t + 256, t + 512, t + 768
+  for (int64_t base = c0; base < c1; base += MA_TILE) {
+    const int nc = (int)std::min<int64_t>(MA_TILE, c1 - base);
+    __syncthreads();
+    for (int i = threadIdx.x; i < MA_TILE * rm; i += blockDim.x) {
+      const int j = i % MA_TILE, b = i / MA_TILE;
+      Pl[j][b] = j < nc ? Pm[(int64_t)b * Cm + base + j] : 0.0;
+    }
+    for (int i = threadIdx.x; i < MA_TILE * G.L4; i += blockDim.x) {
+      const int j = i / G.L4, c = i % G.L4;
+      if (c < ell) Ol[j][c] = j < nc ? drm_effective(G.om_tab[(base + j) * G.L4 + c], prec) : 0.0;
+    }
+    __syncthreads();
 #pragma unroll
-  for (int b = 0; b < PSTT2_MAX_ELL; ++b) acc[b] = 0.0;
-  for (int64_t col = threadIdx.x; col < Cm; col += blockDim.x) {
-    const double v = drm_effective(G.om_tab[col * G.L4 + c], prec);
-#pragma unroll
-    for (int b = 0; b < PSTT2_MAX_ELL; ++b)
-      if (b < rm) acc[b] += Pm[(int64_t)b * Cm + col] * v;
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int b = 0; b < PSTT2_MAX_ELL; ++b) {
-    if (b < rm) {
-      const double t = wave_sum(acc[b]);
-      if (lane == 0) red[b][w] = t;
+    for (int q = 0; q < 4; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      if (t < nout) {
+        const int b = t % rm, c = t / rm;
+        double s = 0.0;
+        for (int j = 0; j < nc; ++j) s += Pl[j][b] * Ol[j][c];
+        acc[q] += s;
+      }
     }
   }
-  __syncthreads();
-  if (threadIdx.x < rm)
-    A[(int64_t)c * rm + threadIdx.x] =
-        red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = threadIdx.x + 256 * q;
+    if (t < nout) part[(int64_t)blockIdx.x * nout + t] = acc[q];
+  }
+}
+
+__global__ void k_middle_a_sum(const double* __restrict__ part, int nb, int nout, double* __restrict__ A) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nout; t += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int g = 0; g < nb; ++g) s += part[(int64_t)g * nout + t];
+    A[t] = s;   // t = b + rm * c
+  }
 }
 
 hipError_t middle_a(const double* Pm, int64_t Cm, int rm, const SketchArgs& geo, int prec, double* A, hipStream_t s) {
-  hipLaunchKernelGGL(k_middle_a, dim3((unsigned)geo.ell), dim3(256), 0, s, Pm, Cm, rm, geo, prec, A);
-  return hipGetLastError();
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(MA_BLOCKS, (Cm + MA_TILE - 1) / MA_TILE));
+  const int nout = rm * geo.ell;
+  double* part = nullptr;
+  hipError_t e = hipMallocAsync((void**)&part, sizeof(double) * nb * nout, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_middle_a_part, dim3(nb), dim3(256), 0, s, Pm, Cm, rm, geo, prec, part);
+  hipLaunchKernelGGL(k_middle_a_sum, dim3((nout + 255) / 256), dim3(256), 0, s, part, nb, nout, A);
+  e = hipGetLastError();
+  (void)hipFreeAsync(part, s);
+  return e;
 }
 
 // Least squares min ||G A - Z||_F for G (nz x rm), A (rm x ell), Z (nz x ell):

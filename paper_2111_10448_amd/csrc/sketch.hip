@@ -481,28 +481,48 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
 // Output layouts: 16x16x4 element v of lane l at (4v + l/16, l%16); 4x4x4
 // block b = (l/4)%4 at (l/16, l%4) of that block.
 // ---------------------------------------------------------------------------
-template <int L4, bool ALIGNED>
-__global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
+// Chunk geometry when the launch holds one segment (the whole-tensor case):
+// closed form, no search over segments.
+__device__ __forceinline__ ChunkInfo chunk_info1(const SketchArgs& A, int64_t ci) {
+  ChunkInfo c;
+  c.ptr = (const char*)A.seg[0].ptr;
+  c.lcol0 = ci * KC;
+  c.gcol0 = A.seg[0].gcol0 + c.lcol0;
+  const int64_t left = A.seg[0].ncols - c.lcol0;
+  c.ncols = (int)(left < KC ? left : KC);
+  return c;
+}
+
+// FP64 workgroups have 4 waves (256 rows) and two of them share a CU, so one
+// workgroup's matrix-core work overlaps the other's barrier and load phases.
+constexpr int NWF = 4;
+constexpr int F64_WG_PER_CU = 2;
+
+template <int L4, bool ALIGNED, bool SEG1>
+__global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const SketchArgs A) {
   constexpr int RW = 64;
   constexpr int ST = RW + 2;
   constexpr int NQ = L4 / 16;          // 16-wide tiles
   constexpr int NS = (L4 % 16) / 4;    // 4-wide groups
   constexpr int KT = RW / 4;           // K steps over rows (left sketch)
   constexpr int NLD = KC * RW / (64 * 2);
+  constexpr int NT = NWF * 64;         // threads
+  constexpr int NOM = (KC * L4 + NT - 1) / NT;   // staged Omega / T entries per thread
   static_assert(L4 % 4 == 0 && L4 >= 4, "ell padded to a multiple of 4");
 
-  __shared__ double Xl[NW][KC * ST];
-  __shared__ double Tred[2][NW][L4 * KC];
-  __shared__ double Om[4][KC * L4];  // 4 buffers: each write is a barrier past the last read
+  __shared__ double Xl[NWF][KC * ST];
+  __shared__ double Tred[2][NWF][L4 * KC];
+  __shared__ __align__(16) double Om[4][KC * L4];  // 4 buffers: each write is a barrier past the last read
 
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int gi = blockIdx.x % A.gi_count;
   const int gj = blockIdx.x / A.gi_count;
-  const int64_t row0w = (int64_t)gi * (NW * RW) + (int64_t)w * RW;
+  const int64_t row0w = (int64_t)gi * (NWF * RW) + (int64_t)w * RW;
   const int64_t cb = (int64_t)gj * A.nchunks / A.gj_count;
   const int64_t ce = (int64_t)(gj + 1) * A.nchunks / A.gj_count;
   const int l16 = lane & 15, g4 = lane >> 4, l4 = lane & 3, blk = (lane >> 2) & 3;
+  auto info = [&](int64_t ci) -> ChunkInfo { return SEG1 ? chunk_info1(A, ci) : chunk_info(A, ci); };
 
   // stationary left-DRM operands: Psi(row0w + 4 ks + g4, a)
   double psiq[KT][NQ > 0 ? NQ : 1];
@@ -516,23 +536,30 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
     for (int s = 0; s < NS; ++s) psis[ks][s] = psi_row(A, row, 16 * NQ + 4 * s + l4);
   }
 
-  // Omega_m rows of a chunk: thread t < KC*L4 loads entry (t / L4, t % L4).
-  // The load is issued one iteration before its value is written to LDS, so
-  // waiting for it never waits for the X prefetch (loads retire in order).
-  auto load_omega = [&](int64_t ci) -> double {
-    const int t = threadIdx.x;
-    double v = 0.0;
-    if (t < KC * L4 && ci < ce) {
-      const int col = t / L4, c = t % L4;
-      ChunkInfo ch = chunk_info(A, ci);
-      if (col < ch.ncols && c < A.ell) v = A.om_tab[(ch.gcol0 + col) * A.L4 + c];
+  // Omega_m rows of a chunk: thread t < KC*L4/2 holds entries (e, e + 1),
+  // e = 2t, of row e / L4 (L4 is even, so both sit in one row; the table's
+  // padding columns ell..L4-1 are zero).  The loads are issued one iteration
+  // before their values are written to LDS, so waiting for them never waits
+  // for the X prefetch (loads retire in order).
+  static_assert(KC * L4 / 2 <= NT, "one Omega pair per thread");
+  double2 omv;
+  auto load_omega = [&](int64_t ci) {
+    const int e = 2 * threadIdx.x;
+    omv = double2{0.0, 0.0};
+    if (e < KC * L4 && ci < ce) {
+      ChunkInfo ch = info(ci);
+      const int col = e / L4, c = e % L4;
+      if (col < ch.ncols) omv = *(const double2*)&A.om_tab[(ch.gcol0 + col) * A.L4 + c];
     }
-    return v;
+  };
+  auto store_omega = [&](int buf) {
+    const int e = 2 * threadIdx.x;
+    if (e < KC * L4) *(double2*)&Om[buf][e] = omv;
   };
 
   double xr[NLD][2];
   auto load_chunk = [&](int64_t ci) {
-    ChunkInfo ch = chunk_info(A, ci);
+    ChunkInfo ch = info(ci);
     const double* base = (const double*)ch.ptr;
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
@@ -565,15 +592,18 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
     }
   };
   auto reduce_t = [&](int buf, int64_t ci) {
-    const int t = threadIdx.x;
-    if (t < L4 * KC) {
-      const int a = t / KC, col = t % KC;
-      double s = 0.0;
+    ChunkInfo ch = info(ci);
 #pragma unroll
-      for (int ww = 0; ww < NW; ++ww) s += Tred[buf][ww][a * KC + col];
-      ChunkInfo ch = chunk_info(A, ci);
-      if (a < A.ell && col < ch.ncols)
-        ((double*)A.tpart)[((int64_t)gi * A.ell + a) * A.C + ch.gcol0 + col] = s;
+    for (int k = 0; k < NOM; ++k) {
+      const int e = threadIdx.x + NT * k;
+      if (e < L4 * KC) {
+        const int a = e / KC, col = e % KC;
+        double s = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NWF; ++ww) s += Tred[buf][ww][a * KC + col];
+        if (a < A.ell && col < ch.ncols)
+          ((double*)A.tpart)[((int64_t)gi * A.ell + a) * A.C + ch.gcol0 + col] = s;
+      }
     }
   };
 
@@ -587,25 +617,24 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
     for (int s = 0; s < NS; ++s) ys[mt][s] = 0.0;
   }
 
-  double omv = 0.0;
   if (cb < ce) {
-    if (threadIdx.x < KC * L4) {
-      Om[0][threadIdx.x] = load_omega(cb);
-      Om[1][threadIdx.x] = load_omega(cb + 1);
-    }
+    load_omega(cb);
+    store_omega(0);
+    load_omega(cb + 1);
+    store_omega(1);
     load_chunk(cb);
-    omv = load_omega(cb + 2);
+    load_omega(cb + 2);
   }
   int it = 0;
   for (int64_t ci = cb; ci < ce; ++ci, ++it) {
     // (a) stage this chunk's X tile and the Omega rows of chunk ci + 2 (both
     //     loaded one iteration ago) in LDS
     store_chunk();
-    if (threadIdx.x < KC * L4) Om[(it + 2) % 4][threadIdx.x] = omv;
+    store_omega((it + 2) % 4);
     __syncthreads();
     // (b) prefetch the next chunk; Omega three chunks ahead
     if (ci + 1 < ce) load_chunk(ci + 1);
-    omv = load_omega(ci + 3);
+    load_omega(ci + 3);
     // (c) finish the previous chunk's left sketch
     if (it >= 1) reduce_t((it - 1) & 1, ci - 1);
     const double* xw = Xl[w];
@@ -688,11 +717,15 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch_f64(const SketchArgs A) {
 
 template <int L4>
 static hipError_t launch_f64(const SketchArgs& a, bool aligned, hipStream_t s) {
-  dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(NW * 64);
-  if (aligned)
-    hipLaunchKernelGGL((k_sketch_f64<L4, true>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((k_sketch_f64<L4, false>), grid, block, 0, s, a);
+  dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(NWF * 64);
+  const bool seg1 = a.nseg == 1 && a.seg[0].chunk0 == 0;
+  if (aligned) {
+    if (seg1) hipLaunchKernelGGL((k_sketch_f64<L4, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_sketch_f64<L4, true, false>), grid, block, 0, s, a);
+  } else {
+    if (seg1) hipLaunchKernelGGL((k_sketch_f64<L4, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_sketch_f64<L4, false, false>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -715,11 +748,12 @@ hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream
   return hipGetLastError();
 }
 
-void sketch_geometry(int prec, int lp, int* rows_per_block, int* threads) {
-  (void)lp;
-  *threads = NW * 64;
+void sketch_geometry(int prec, int ell, int* rows_per_block, int* threads, int* wg_per_cu) {
+  *threads = prec == P_F64 ? NWF * 64 : NW * 64;
+  // FP64: two workgroups fit in a CU's LDS while ell (rounded to 4) <= 28
+  *wg_per_cu = (prec == P_F64 && (ell + 3) / 4 * 4 <= 28) ? F64_WG_PER_CU : 1;
   switch (prec) {
-    case P_F64: *rows_per_block = NW * Eng<P_F64>::RW; break;
+    case P_F64: *rows_per_block = NWF * Eng<P_F64>::RW; break;
     case P_F32: *rows_per_block = NW * Eng<P_F32>::RW; break;
     case P_BF16: *rows_per_block = NW * Eng<P_BF16>::RW; break;
     default: *rows_per_block = NW * Eng<P_BF16X3>::RW; break;
