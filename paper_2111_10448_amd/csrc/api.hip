@@ -444,20 +444,24 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
     HIPCK(c, hipMallocAsync((void**)&c->Tk[k], sizeof(double) * Ck * ell, s));
     HIPCK(c, derive_right(c->Tk[k - 1], c->Tk[k], Ck, (int)c->n[k - 1], ell, c->fac + c->psi_off[k - 1], s));
   }
-  // (2) factor every sketch; the ranks come from the descriptor or, in
-  // tolerance mode, from the singular values (one host synchronisation)
-  std::vector<BasisWork*> work(d + 1, nullptr);
-  auto cleanup = [&]() {
-    for (auto w : work) basis_free(w);
-  };
+  // (2) factor every sketch (one batched TSQR over all splits); the ranks come
+  // from the descriptor or, in tolerance mode, from the singular values (one
+  // host synchronisation)
   const bool tol = c->desc.ranks[0] <= 0;
+  std::vector<const double*> Ap(d - 1);
+  std::vector<int64_t> Mp(d - 1);
+  std::vector<int*> pivp(d - 1);
   for (int k = 1; k <= d - 1; ++k) {
-    const int64_t Mk = k < m ? c->Rk[k] : c->N / c->Rk[k];
-    const double* A = k < m ? c->S[k] : c->Tk[k];
-    hipError_t e = basis_factor(A, Mk, ell, c->piv_dev + (int64_t)k * ell, tol, &work[k], s);
+    Ap[k - 1] = k < m ? c->S[k] : c->Tk[k];
+    Mp[k - 1] = k < m ? c->Rk[k] : c->N / c->Rk[k];
+    pivp[k - 1] = c->piv_dev + (int64_t)k * ell;
+  }
+  BasisBatch* bw = nullptr;
+  {
+    hipError_t e = basis_factor_batch(d - 1, Ap.data(), Mp.data(), ell, pivp.data(), tol, &bw, s);
     if (e != hipSuccess) {
-      cleanup();
-      return hfail(c, e, "basis_factor");
+      basis_batch_free(bw);
+      return hfail(c, e, "basis_factor_batch");
     }
   }
   int r[PSTT2_MAX_D + 1];
@@ -465,16 +469,16 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   std::vector<double> sv((size_t)(d + 1) * ell, 0.0);
   if (tol) {
     for (int k = 1; k <= d - 1; ++k) {
-      hipError_t e = hipMemcpyAsync(sv.data() + (size_t)k * ell, basis_sv(work[k]), sizeof(double) * ell,
+      hipError_t e = hipMemcpyAsync(sv.data() + (size_t)k * ell, basis_batch_sv(bw, k - 1), sizeof(double) * ell,
                                     hipMemcpyDeviceToHost, s);
       if (e != hipSuccess) {
-        cleanup();
+        basis_batch_free(bw);
         return hfail(c, e, "hipMemcpyAsync(sv)");
       }
     }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-      cleanup();
+      basis_batch_free(bw);
       return hfail(c, e, "recover");
     }
   }
@@ -492,16 +496,17 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
     r[k] = rk;
   }
   // (3) bases
-  for (int k = 1; k <= d - 1; ++k) {
-    const int64_t Mk = k < m ? c->Rk[k] : c->N / c->Rk[k];
-    hipError_t e = hipMallocAsync((void**)&c->basis[k], sizeof(double) * Mk * r[k], s);
-    if (e == hipSuccess) e = basis_form_q(work[k], r[k], c->basis[k], s);
-    if (e != hipSuccess) {
-      cleanup();
-      return hfail(c, e, "basis_form_q");
+  {
+    std::vector<double*> Qp(d - 1);
+    hipError_t e = hipSuccess;
+    for (int k = 1; k <= d - 1 && e == hipSuccess; ++k) {
+      e = hipMallocAsync((void**)&c->basis[k], sizeof(double) * Mp[k - 1] * r[k], s);
+      Qp[k - 1] = c->basis[k];
     }
+    if (e == hipSuccess) e = basis_form_q_batch(bw, r + 1, Qp.data(), s);
+    basis_batch_free(bw);
+    if (e != hipSuccess) return hfail(c, e, "basis_form_q_batch");
   }
-  cleanup();
   for (int k = 0; k <= d; ++k) c->ranks[k] = r[k];
   // (4) cores, one allocation based at core[0]
   tt_cores tc;

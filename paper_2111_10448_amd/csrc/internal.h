@@ -64,18 +64,20 @@ hipError_t derive_left(const double* Sin, double* Sout, int64_t Rk, int nk1, int
 hipError_t derive_right(const double* Tin, double* Tout, int64_t Ck, int nk, int ell, const double* psi,
                         hipStream_t s);
 
-// Orthonormal basis of range(A) for an M x ell matrix by TSQR + pivoted QR of R.
-struct BasisWork;
-// Phase 1 (async): factor A (TSQR, CPQR of the final R into piv_dev, singular
-// values of R when want_sv).
-hipError_t basis_factor(const double* A, int64_t M, int ell, int* piv_dev, bool want_sv, BasisWork** w,
-                        hipStream_t s);
-// Device pointer to the ell singular values (descending) of phase 1, or null.
-const double* basis_sv(BasisWork* w);
-// Phase 2 (async): Q (M x r) = first r columns of the sign-fixed pivoted factor.
-hipError_t basis_form_q(BasisWork* w, int r, double* Q, hipStream_t s);
+// Orthonormal bases of range(A_p) for n independent M_p x ell matrices by
+// TSQR + pivoted QR of the final R; every tree level, the pivoted QRs and the
+// singular values run as one launch over all problems.
+struct BasisBatch;
+// Phase 1 (async): factor every A_p; pivots into piv[p] (ell ints); singular
+// values of R when want_sv.
+hipError_t basis_factor_batch(int n, const double* const* A, const int64_t* M, int ell, int* const* piv,
+                              bool want_sv, BasisBatch** w, hipStream_t s);
+// Device pointer to problem p's ell singular values (descending), or null.
+const double* basis_batch_sv(BasisBatch* w, int p);
+// Phase 2 (async): Q_p (M_p x r_p) = first r_p columns of the sign-fixed pivoted factor.
+hipError_t basis_form_q_batch(BasisBatch* w, const int* r, double* const* Q, hipStream_t s);
 // Release (stream-ordered).
-void basis_free(BasisWork* w);
+void basis_batch_free(BasisBatch* w);
 
 hipError_t core_left(const double* Qprev, int64_t Rprev, int rprev, const double* Qk, int nk, int rk, double* G,
                      hipStream_t s);

@@ -5,13 +5,14 @@
 //    with omega_{k+1} (block form of equation "sketch_orig"), starting from
 //    Y_R = S_m; T_k = Psi_k^T X_k follows from T_{k-1} by contracting mode k
 //    with psi_k, starting from T_m.
-//  * basis_factor / basis_form_q: an orthonormal basis of the sketch's range
+//  * basis_factor_batch / basis_form_q_batch: orthonormal bases of the sketches' ranges
 //    by a column-pivoted QR (Algorithm PSTT, CPQR step).  Tall sketches are
 //    first reduced by Householder TSQR (the skinny QR of Section 4.2), one
-//    wavefront per 128-row block; the pivots of a matrix equal the pivots of
-//    its R factor, so the pivoted QR runs on the final ell x ell R.  Signs are
-//    fixed so that diag(R) >= 0.  Singular values (tolerance mode) come from a
-//    one-sided Jacobi sweep on that R.
+//    workgroup per 512- or 1024-row block, all splits in one launch per tree
+//    level; the pivots of a matrix equal the pivots of its R factor, so the
+//    pivoted QR runs on the final ell x ell R.  Signs are fixed so that
+//    diag(R) >= 0.  Singular values (tolerance mode) come from a one-sided
+//    Jacobi sweep on that R.
 //  * core_left / core_right: equation "core" and its row-space mirror.
 //  * middle_z / middle_a / middle_ls: the one-pass middle core, two products and
 //    a least-squares solve (Section 4.2, "PSTT2-onepass").
@@ -20,12 +21,12 @@
 // the host.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "internal.h"
 
 namespace pstt2 {
 
-constexpr int BRW = 128;  // rows per TSQR block: one wavefront, two rows per lane
 
 static unsigned grid_for(int64_t n, int bs) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + bs - 1) / bs, 8192));
@@ -78,74 +79,103 @@ hipError_t derive_right(const double* Tin, double* Tout, int64_t Ck, int nk, int
 }
 
 // ---------------------------------------------------------------------------
-// Householder QR of one 128 x ell block per wavefront (LAPACK dlarfg
-// convention: H = I - tau v v^T, v(j) = 1, beta = -sign(alpha) ||x||, tau = 0
-// when the column below the diagonal is already zero).  Lane t holds rows t
-// and t + 64 of the block.  Rows past M are zero.
+// TSQR leaves.  One workgroup (256 threads) factors a block of BR = 256 * RPT
+// rows by Householder reflections (LAPACK dlarfg convention: H = I - tau v v^T,
+// v(j) = 1, beta = -sign(alpha) ||x||, tau = 0 when the column below the
+// diagonal is already zero).  Thread t holds block rows t + 256 k (k < RPT), so
+// row j < ell sits in thread j.  Rows past M are zero.
+//
+// Step j needs sigma = sum_{i>j} a_ij^2 and p_c = sum_i v_i a_ic for c > j.
+// With v_i = a_ij / (alpha - beta) below the diagonal and v_j = 1, both come
+// from one reduction q_c = sum_{i>j} a_ij a_ic (c >= j; sigma = q_j) and the
+// broadcast row j: p_c = q_c / (alpha - beta) + a_jc.
 // ---------------------------------------------------------------------------
-// Wave-local batched reduction: every lane holds p[c] for the columns c in
-// (j, ell); returns, in every lane, the wave sums W[c] (read back from LDS).
-// P is this wave's LDS scratch with row stride 65 (conflict-free transposes).
+constexpr int RED_LD = 264;   // LDS row stride of the reduction buffer (bank spread)
+
+// Sum Red[c][0..255] for c in [c0, n) into Out[c]; threads t < LP*8 take
+// column t/8 and eight interleaved slices of it.  Caller synchronises.
 template <int LP>
-__device__ __forceinline__ void wave_colsum(const double (&p)[LP], int j, int ell, double* P, double* W) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int c = 0; c < LP; ++c)
-    if (c > j && c < ell) P[c * 65 + lane] = p[c];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // lane (c, h): c = lane % 32 sums half h = lane / 32 of column c's 64 entries
-  const int c = lane & 31, h = lane >> 5;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  if (c > j && c < ell) {
-    const double* q = P + c * 65 + 32 * h;
-#pragma unroll
-    for (int i = 0; i < 32; i += 4) {
-      s0 += q[i];
-      s1 += q[i + 1];
-      s2 += q[i + 2];
-      s3 += q[i + 3];
+__device__ __forceinline__ void wg_colsum(double (*Red)[RED_LD], int c0, int n, double* Out) {
+  const int t = threadIdx.x;
+  if (t < LP * 8) {
+    const int c = t >> 3, s8 = t & 7;
+    double sum = 0.0;
+    if (c >= c0 && c < n) {
+#pragma unroll 8
+      for (int i = 0; i < 32; ++i) sum += Red[c][s8 + 8 * i];
     }
+    sum += __shfl_xor(sum, 1);
+    sum += __shfl_xor(sum, 2);
+    sum += __shfl_xor(sum, 4);
+    if (s8 == 0 && c >= c0 && c < n) Out[c] = sum;
   }
-  double s = (s0 + s1) + (s2 + s3);
-  s += __shfl_xor(s, 32);
-  if (h == 0 && c > j && c < ell) W[c] = s;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int LP>
-__global__ __launch_bounds__(256) void k_hh_block(const double* __restrict__ A, int64_t M, int64_t lda, int ell,
-                                                  int64_t nb, double* __restrict__ V, double* __restrict__ tau,
-                                                  double* __restrict__ Rout, int64_t ldr) {
-  __shared__ double Pbuf[4][LP * 65];
-  __shared__ double Wbuf[4][LP];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t b = (int64_t)blockIdx.x * 4 + wv;
-  if (b >= nb) return;
-  double* P = Pbuf[wv];
-  double* W = Wbuf[wv];
-  const int64_t r0 = b * BRW + lane, r1 = r0 + 64;
-  double a0[LP], a1[LP];
+// Independent problems (one per split) share each launch: workgroup g belongs
+// to problem p with blk0[p] <= g < blk0[p + 1].
+constexpr int MAXB = PSTT2_MAX_D;
+struct LeafBatch {
+  int n;
+  const double* A[MAXB];
+  int64_t M[MAXB], lda[MAXB];
+  double* V[MAXB];
+  double* tau[MAXB];
+  double* Rst[MAXB];
+  int64_t ldr[MAXB];
+  int64_t blk0[MAXB + 1];
+};
+
+__device__ __forceinline__ int batch_find(const int64_t* blk0, int n, int64_t g) {
+  int p = 0;
+  while (p + 1 < n && blk0[p + 1] <= g) ++p;
+  return p;
+}
+
+template <int LP, int RPT>
+__global__ __launch_bounds__(256) void k_qr_leaf(const LeafBatch B, int ell) {
+  constexpr int BR = 256 * RPT;
+  __shared__ double Red[LP][RED_LD];
+  __shared__ double Qs[LP];
+  __shared__ double Rowj[2][LP];
+  const int t = threadIdx.x;
+  const int pb = batch_find(B.blk0, B.n, blockIdx.x);
+  const double* __restrict__ A = B.A[pb];
+  const int64_t M = B.M[pb], lda = B.lda[pb], ldr = B.ldr[pb];
+  double* __restrict__ V = B.V[pb];
+  double* __restrict__ tau = B.tau[pb];
+  double* __restrict__ Rst = B.Rst[pb];
+  const int64_t b = blockIdx.x - B.blk0[pb];
+  const int64_t rb = b * BR;
+  // columns ell..LP-1 are zero: their steps are exact no-ops (sigma = alpha = 0)
+  double a[RPT][LP];
 #pragma unroll
-  for (int c = 0; c < LP; ++c) {
-    a0[c] = (c < ell && r0 < M) ? A[(int64_t)c * lda + r0] : 0.0;
-    a1[c] = (c < ell && r1 < M) ? A[(int64_t)c * lda + r1] : 0.0;
+  for (int k = 0; k < RPT; ++k) {
+    const int64_t row = rb + t + 256 * k;
+#pragma unroll
+    for (int c = 0; c < LP; ++c) a[k][c] = (c < ell && row < M) ? A[(int64_t)c * lda + row] : 0.0;
   }
-  const int t0 = lane, t1 = lane + 64;   // row indices within the block
-  for (int j = 0; j < ell; ++j) {
-    // column j of the two rows (registers are indexed statically)
-    double x0 = 0.0, x1 = 0.0;
+  // fully unrolled over the reflectors: every register index is a constant
 #pragma unroll
-    for (int c = 0; c < LP; ++c)
-      if (c == j) {
-        x0 = a0[c];
-        x1 = a1[c];
-      }
-    const double sigma = wave_sum((t0 > j ? x0 * x0 : 0.0) + x1 * x1);
-    const double alpha = __shfl(x0, j);   // row j (< 64) sits in lane j, first row
+  for (int j = 0; j < LP; ++j) {
+    if (j < ell) {   // uniform: every thread takes the same branch
+    // q_c partials over this thread's rows below j
+#pragma unroll
+    for (int c = j; c < LP; ++c) {
+      double q = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k)
+        if (t + 256 * k > j) q += a[k][j] * a[k][c];
+      Red[c][t] = q;
+    }
+    if (t == j) {
+#pragma unroll
+      for (int c = j; c < LP; ++c) Rowj[j & 1][c] = a[0][c];
+    }
+    __syncthreads();
+    wg_colsum<LP>(Red, j, LP, Qs);
+    __syncthreads();
+    const double sigma = Qs[j];
+    const double alpha = Rowj[j & 1][j];
     double tj, beta, scal;
     if (sigma == 0.0) {
       tj = 0.0;
@@ -156,180 +186,239 @@ __global__ __launch_bounds__(256) void k_hh_block(const double* __restrict__ A, 
       tj = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    const double v0 = (t0 == j) ? 1.0 : (t0 > j ? x0 * scal : 0.0);
-    const double v1 = x1 * scal;
-    double p[LP];
+    double v[RPT];
 #pragma unroll
-    for (int c = 0; c < LP; ++c) p[c] = v0 * a0[c] + v1 * a1[c];
-    wave_colsum<LP>(p, j, ell, P, W);
-#pragma unroll
-    for (int c = 0; c < LP; ++c) {
-      if (c > j && c < ell) {
-        const double wc = W[c] * tj;
-        a0[c] -= wc * v0;
-        a1[c] -= wc * v1;
-      }
+    for (int k = 0; k < RPT; ++k) {
+      const int lr = t + 256 * k;
+      v[k] = lr == j ? 1.0 : (lr > j ? a[k][j] * scal : 0.0);
     }
 #pragma unroll
-    for (int c = 0; c < LP; ++c)
-      if (c == j) {
-        a0[c] = (t0 > j) ? v0 : (t0 == j ? beta : a0[c]);
-        a1[c] = v1;
-      }
-    if (lane == 0) tau[b * ell + j] = tj;
+    for (int c = j + 1; c < LP; ++c) {
+      const double pc = tj * (scal * Qs[c] + Rowj[j & 1][c]);
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) a[k][c] -= pc * v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int lr = t + 256 * k;
+      a[k][j] = lr > j ? v[k] : (lr == j ? beta : a[k][j]);
+    }
+    if (t == 0) tau[b * ell + j] = tj;
+    }
   }
 #pragma unroll
-  for (int c = 0; c < LP; ++c) {
-    if (c < ell) {
-      V[(b * ell + c) * BRW + t0] = (t0 > c) ? a0[c] : (t0 == c ? 1.0 : 0.0);
-      V[(b * ell + c) * BRW + t1] = a1[c];
-      if (t0 < ell) Rout[(int64_t)c * ldr + b * ell + t0] = (t0 <= c) ? a0[c] : 0.0;
+  for (int k = 0; k < RPT; ++k) {
+    const int lr = t + 256 * k;
+#pragma unroll
+    for (int c = 0; c < LP; ++c) {
+      if (c < ell) {
+        V[(b * ell + c) * BR + lr] = lr > c ? a[k][c] : (lr == c ? 1.0 : 0.0);
+        if (k == 0 && lr < ell) Rst[(int64_t)c * ldr + b * ell + lr] = lr <= c ? a[0][c] : 0.0;
+      }
     }
   }
 }
 
-// Apply one block's Q (128 x ell reflectors) to [Zin(b*ell .. b*ell+ell-1, :); 0]
-// and write rows [b*128, b*128 + 128) of Zout (masked to Mout rows).
-template <int RP>
-__global__ __launch_bounds__(256) void k_hh_apply(const double* __restrict__ V, const double* __restrict__ tau,
-                                                  int ell, int64_t nb, const double* __restrict__ Zin, int64_t ldzi,
-                                                  int r, double* __restrict__ Zout, int64_t ldzo, int64_t Mout) {
-  __shared__ double Pbuf[4][RP * 65];
-  __shared__ double Wbuf[4][RP];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t b = (int64_t)blockIdx.x * 4 + wv;
-  if (b >= nb) return;
-  double* P = Pbuf[wv];
-  double* W = Wbuf[wv];
-  double c0[RP], c1[RP];
+// Apply one block's Q (BR x ell reflectors) to [Zin(b*ell .. b*ell+ell-1, :); 0]
+// and write rows [b*BR, b*BR + BR) of Zout (masked to Mout rows).
+struct ApplyBatch {
+  int n;
+  const double* V[MAXB];
+  const double* tau[MAXB];
+  const double* Zin[MAXB];
+  int64_t ldzi[MAXB];
+  int r[MAXB];
+  double* Zout[MAXB];
+  int64_t ldzo[MAXB], Mout[MAXB];
+  int64_t blk0[MAXB + 1];
+};
+
+template <int RP, int RPT>
+__global__ __launch_bounds__(256) void k_qr_apply(const ApplyBatch B, int ell) {
+  constexpr int BR = 256 * RPT;
+  __shared__ double Red[RP][RED_LD];
+  __shared__ double Ws[RP];
+  const int t = threadIdx.x;
+  const int pb = batch_find(B.blk0, B.n, blockIdx.x);
+  const double* __restrict__ V = B.V[pb];
+  const double* __restrict__ tau = B.tau[pb];
+  const double* __restrict__ Zin = B.Zin[pb];
+  const int64_t ldzi = B.ldzi[pb], ldzo = B.ldzo[pb], Mout = B.Mout[pb];
+  const int r = B.r[pb];
+  double* __restrict__ Zout = B.Zout[pb];
+  const int64_t b = blockIdx.x - B.blk0[pb];
+  double z[RPT][RP];
 #pragma unroll
-  for (int c = 0; c < RP; ++c) {
-    c0[c] = (c < r && lane < ell) ? Zin[(int64_t)c * ldzi + b * ell + lane] : 0.0;
-    c1[c] = 0.0;
+  for (int k = 0; k < RPT; ++k) {
+    const int lr = t + 256 * k;
+#pragma unroll
+    for (int c = 0; c < RP; ++c) z[k][c] = (c < r && lr < ell) ? Zin[(int64_t)c * ldzi + b * ell + lr] : 0.0;
+  }
+  // reflector j is loaded one step ahead of its use
+  double vn[RPT];
+  double tn = 0.0;
+  if (ell > 0) {
+    tn = tau[b * ell + ell - 1];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) vn[k] = V[(b * ell + ell - 1) * BR + t + 256 * k];
   }
   for (int j = ell - 1; j >= 0; --j) {
-    const double tj = tau[b * ell + j];
-    const double v0 = V[(b * ell + j) * BRW + lane];
-    const double v1 = V[(b * ell + j) * BRW + lane + 64];
-    double p[RP];
+    const double tj = tn;
+    double v[RPT];
 #pragma unroll
-    for (int c = 0; c < RP; ++c) p[c] = v0 * c0[c] + v1 * c1[c];
-    wave_colsum<RP>(p, -1, r, P, W);
+    for (int k = 0; k < RPT; ++k) v[k] = vn[k];
+    if (j > 0) {
+      tn = tau[b * ell + j - 1];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) vn[k] = V[(b * ell + j - 1) * BR + t + 256 * k];
+    }
+#pragma unroll
+    for (int c = 0; c < RP; ++c) {
+      double q = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) q += v[k] * z[k][c];
+      if (c < r) Red[c][t] = q;
+    }
+    __syncthreads();
+    wg_colsum<RP>(Red, 0, r, Ws);
+    __syncthreads();
 #pragma unroll
     for (int c = 0; c < RP; ++c) {
       if (c < r) {
-        const double wc = W[c] * tj;
-        c0[c] -= wc * v0;
-        c1[c] -= wc * v1;
+        const double wc = tj * Ws[c];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) z[k][c] -= wc * v[k];
       }
     }
   }
-  const int64_t r0 = b * BRW + lane, r1 = r0 + 64;
 #pragma unroll
-  for (int c = 0; c < RP; ++c) {
-    if (c < r) {
-      if (r0 < Mout) Zout[(int64_t)c * ldzo + r0] = c0[c];
-      if (r1 < Mout) Zout[(int64_t)c * ldzo + r1] = c1[c];
-    }
+  for (int k = 0; k < RPT; ++k) {
+    const int64_t row = b * BR + t + 256 * k;
+#pragma unroll
+    for (int c = 0; c < RP; ++c)
+      if (c < r && row < Mout) Zout[(int64_t)c * ldzo + row] = z[k][c];
   }
 }
 
-// Column-pivoted QR of the ell x ell matrix R, one wavefront.  Pivot: first
-// column of largest remaining norm (norms recomputed exactly each step).
-// Outputs: piv (ell) and Qc (ell x ell, columns sign-fixed so that diag >= 0).
-__global__ __launch_bounds__(64) void k_cpqr(const double* __restrict__ R, int64_t ldr, int ell, int* __restrict__ piv,
-                                             double* __restrict__ Qc) {
-  __shared__ double As[PSTT2_MAX_ELL][PSTT2_MAX_ELL + 1];   // [col][row]
-  __shared__ double Vs[PSTT2_MAX_ELL][PSTT2_MAX_ELL + 1];   // reflectors [j][row]
-  __shared__ double taus[PSTT2_MAX_ELL], diag[PSTT2_MAX_ELL];
-  __shared__ int pv[PSTT2_MAX_ELL];
+// Column-pivoted QR of the ell x ell matrix R, one wavefront per problem.
+// Lane t holds column t in registers; pivoting swaps positions, not data: pos
+// is the lane's current column position.  Pivot: the column of largest
+// remaining norm, first position on ties (norms recomputed exactly each
+// step).  Outputs: piv (ell; piv[position] = original column) and Qc
+// (ell x ell, columns sign-fixed so that diag(R) >= 0).
+struct CpqrBatch {
+  const double* R[MAXB];
+  int64_t ldr[MAXB];
+  int* piv[MAXB];
+  double* Qc[MAXB];
+};
+
+template <int LP>
+__global__ __launch_bounds__(64) void k_cpqr(const CpqrBatch B, int ell) {
+  __shared__ double Vs[LP][LP + 1];
+  __shared__ double taus[LP], diag[LP];
+  const int pb = blockIdx.x;
+  const double* __restrict__ R = B.R[pb];
+  const int64_t ldr = B.ldr[pb];
   const int t = threadIdx.x;
-  for (int c = 0; c < ell; ++c)
-    if (t < ell) As[c][t] = R[(int64_t)c * ldr + t];
-  if (t < ell) pv[t] = t;
-  __syncthreads();
-  for (int j = 0; j < ell; ++j) {
-    // residual norms (lane = column), then first-index argmax across lanes
-    double nrm = -1.0;
-    if (t >= j && t < ell) {
-      nrm = 0.0;
-      for (int i = j; i < ell; ++i) nrm += As[t][i] * As[t][i];
-    }
-    int best = t;
-    for (int o = 32; o > 0; o >>= 1) {
-      const double on = __shfl_xor(nrm, o);
-      const int ob = __shfl_xor(best, o);
-      if (on > nrm || (on == nrm && ob < best)) {
-        nrm = on;
-        best = ob;
+  const bool act = t < ell;
+  double a[LP];
+#pragma unroll
+  for (int i = 0; i < LP; ++i) a[i] = (act && i < ell) ? R[(int64_t)t * ldr + i] : 0.0;
+  int pos = t;
+#pragma clang loop unroll(full)
+  for (int j = 0; j < LP; ++j) {
+    if (j < ell) {   // uniform
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = j; i < LP; ++i) nrm += a[i] * a[i];
+      double key = (act && pos >= j) ? nrm : -1.0;
+      int kpos = pos, klane = t;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ok = __shfl_xor(key, o);
+        const int op = __shfl_xor(kpos, o), ol = __shfl_xor(klane, o);
+        if (ok > key || (ok == key && op < kpos)) {
+          key = ok;
+          kpos = op;
+          klane = ol;
+        }
+      }
+      const int w = __shfl(klane, 0);
+      const int wpos = __shfl(pos, w);
+      if (t == w) pos = j;
+      else if (pos == j) pos = wpos;
+      if (t == w) {
+        double sigma = 0.0;
+#pragma unroll
+        for (int i = j + 1; i < LP; ++i) sigma += a[i] * a[i];
+        const double alpha = a[j];
+        double tj, beta, scal;
+        if (sigma == 0.0) {
+          tj = 0.0;
+          beta = alpha;
+          scal = 0.0;
+        } else {
+          beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+          tj = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+#pragma unroll
+        for (int i = 0; i < LP; ++i) Vs[j][i] = i < j ? 0.0 : (i == j ? 1.0 : a[i] * scal);
+        taus[j] = tj;
+        diag[j] = beta;
+        a[j] = beta;
+#pragma unroll
+        for (int i = j + 1; i < LP; ++i) a[i] = 0.0;
+      }
+      __syncthreads();
+      if (act && pos > j) {
+        double pd = 0.0;
+#pragma unroll
+        for (int i = j; i < LP; ++i) pd += Vs[j][i] * a[i];
+        pd *= taus[j];
+#pragma unroll
+        for (int i = j; i < LP; ++i) a[i] -= pd * Vs[j][i];
       }
     }
-    best = __shfl(best, 0);
-    if (best != j) {
-      if (t < ell) {
-        const double tmp = As[j][t];
-        As[j][t] = As[best][t];
-        As[best][t] = tmp;
-      }
-      if (t == 0) {
-        const int tp = pv[j];
-        pv[j] = pv[best];
-        pv[best] = tp;
-      }
-    }
-    __syncthreads();
-    // Householder vector of column j (lane = row)
-    const double x = (t < ell) ? As[j][t] : 0.0;
-    const double sigma = wave_sum(t > j ? x * x : 0.0);
-    const double alpha = __shfl(x, j);
-    double tj, beta, scal;
-    if (sigma == 0.0) {
-      tj = 0.0;
-      beta = alpha;
-      scal = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-      tj = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
-    }
-    if (t < ell) {
-      Vs[j][t] = (t < j) ? 0.0 : (t == j ? 1.0 : x * scal);
-      As[j][t] = (t < j) ? As[j][t] : (t == j ? beta : 0.0);
-    }
-    if (t == 0) {
-      taus[j] = tj;
-      diag[j] = beta;
-    }
-    __syncthreads();
-    // apply to the remaining columns (lane = column)
-    if (t > j && t < ell) {
-      double p = 0.0;
-      for (int i = j; i < ell; ++i) p += Vs[j][i] * As[t][i];
-      p *= tj;
-      for (int i = j; i < ell; ++i) As[t][i] -= p * Vs[j][i];
-    }
-    __syncthreads();
   }
-  // Qc = H_0 ... H_{ell-1} I, column t by lane t (in LDS, reusing As), sign-fixed
-  if (t < ell) {
-    for (int i = 0; i < ell; ++i) As[t][i] = (i == t) ? 1.0 : 0.0;
-    for (int j = ell - 1; j >= 0; --j) {
-      double p = 0.0;
-      for (int i = j; i < ell; ++i) p += Vs[j][i] * As[t][i];
-      p *= taus[j];
-      for (int i = j; i < ell; ++i) As[t][i] -= p * Vs[j][i];
+  // Qc = H_0 ... H_{ell-1} I: lane t forms column t (position t), sign-fixed
+  if (act) {
+    double q[LP];
+#pragma unroll
+    for (int i = 0; i < LP; ++i) q[i] = i == t ? 1.0 : 0.0;
+#pragma clang loop unroll(full)
+    for (int j = LP - 1; j >= 0; --j) {
+      if (j < ell) {
+        double pd = 0.0;
+#pragma unroll
+        for (int i = j; i < LP; ++i) pd += Vs[j][i] * q[i];
+        pd *= taus[j];
+#pragma unroll
+        for (int i = j; i < LP; ++i) q[i] -= pd * Vs[j][i];
+      }
     }
     const double sg = diag[t] < 0.0 ? -1.0 : 1.0;
-    for (int i = 0; i < ell; ++i) Qc[(int64_t)t * ell + i] = sg * As[t][i];
-    piv[t] = pv[t];
+    double* Qc = B.Qc[pb];
+#pragma unroll
+    for (int i = 0; i < LP; ++i)
+      if (i < ell) Qc[(int64_t)t * ell + i] = sg * q[i];
+    B.piv[pb][pos] = t;
   }
 }
 
 // Singular values of an ell x ell matrix by one-sided (Hestenes) Jacobi.
 // 16 wavefront halves; half h rotates pair h of the round-robin schedule, one
 // row per lane.
-__global__ __launch_bounds__(512) void k_jacobi_sv(const double* __restrict__ R, int64_t ldr, int ell,
-                                                   double* __restrict__ sv) {
+struct SvBatch {
+  const double* R[MAXB];
+  int64_t ldr[MAXB];
+  double* sv[MAXB];
+};
+
+__global__ __launch_bounds__(512) void k_jacobi_sv(const SvBatch B, int ell) {
+  const double* __restrict__ R = B.R[blockIdx.x];
+  const int64_t ldr = B.ldr[blockIdx.x];
+  double* __restrict__ sv = B.sv[blockIdx.x];
   __shared__ double U[PSTT2_MAX_ELL][PSTT2_MAX_ELL + 1];  // [col][row]
   __shared__ int rotated;
   const int t = threadIdx.x;
@@ -403,31 +492,24 @@ __global__ __launch_bounds__(512) void k_jacobi_sv(const double* __restrict__ R,
 struct Level {
   int64_t M;      // rows at this level
   int64_t nb;     // blocks
-  double* V;      // nb * ell * BRW
+  double* V;      // nb * ell * br
   double* tau;    // nb * ell
   double* Rst;    // stacked R of this level (nb*ell x ell), input of the next level
 };
 
-struct BasisWork {
-  int ell;
-  hipStream_t s;
-  std::vector<Level> lv;
-  double* Qc = nullptr;  // ell x ell
-  int* piv = nullptr;
-  double* sv = nullptr;
-  double* tmp = nullptr;  // scratch for Q formation
+struct BasisBatch {
+  int n = 0, ell = 0, rpt = 2;
+  hipStream_t s = nullptr;
+  std::vector<std::vector<Level>> lv;   // per problem, leaves first
+  double* ws = nullptr;                 // one stream-ordered workspace for everything
+  std::vector<double*> Qc, sv;
+  double* tmp = nullptr;                // Q formation ping-pong buffers
 };
 
-void basis_free(BasisWork* w) {
+void basis_batch_free(BasisBatch* w) {
   if (!w) return;
-  for (auto& l : w->lv) {
-    hipFreeAsync(l.V, w->s);
-    hipFreeAsync(l.tau, w->s);
-    hipFreeAsync(l.Rst, w->s);
-  }
-  hipFreeAsync(w->Qc, w->s);
-  hipFreeAsync(w->sv, w->s);
-  hipFreeAsync(w->tmp, w->s);
+  if (w->ws) (void)hipFreeAsync(w->ws, w->s);
+  if (w->tmp) (void)hipFreeAsync(w->tmp, w->s);
   delete w;
 }
 
@@ -437,80 +519,185 @@ void basis_free(BasisWork* w) {
     if (e_ != hipSuccess) return e_;   \
   } while (0)
 
-template <int LP>
-static void launch_hh(const double* A, int64_t M, int64_t lda, int ell, const Level& l, hipStream_t s) {
-  hipLaunchKernelGGL((k_hh_block<LP>), dim3((unsigned)((l.nb + 3) / 4)), dim3(256), 0, s, A, M, lda, ell, l.nb, l.V,
-                     l.tau, l.Rst, l.nb * ell);
+// Sketches of up to 16 columns use 1024-row leaves (4 rows per thread); wider
+// ones 512-row leaves, so the registers of a thread stay within 64 values.
+static int leaf_rpt(int ell) { return ell <= 16 ? 4 : 2; }
+
+static void launch_leaf(const LeafBatch& B, int64_t nblk, int ell, hipStream_t s) {
+  const dim3 g((unsigned)nblk), b(256);
+  if (ell <= 8) hipLaunchKernelGGL((k_qr_leaf<8, 4>), g, b, 0, s, B, ell);
+  else if (ell <= 16) hipLaunchKernelGGL((k_qr_leaf<16, 4>), g, b, 0, s, B, ell);
+  else if (ell <= 24) hipLaunchKernelGGL((k_qr_leaf<24, 2>), g, b, 0, s, B, ell);
+  else hipLaunchKernelGGL((k_qr_leaf<32, 2>), g, b, 0, s, B, ell);
 }
 
-hipError_t basis_factor(const double* A, int64_t M, int ell, int* piv_dev, bool want_sv, BasisWork** out,
-                        hipStream_t s) {
-  BasisWork* w = new BasisWork();
-  w->ell = ell;
-  w->s = s;
-  w->piv = piv_dev;
+hipError_t basis_factor_batch(int n, const double* const* A, const int64_t* M, int ell, int* const* piv,
+                              bool want_sv, BasisBatch** out, hipStream_t s) {
+  BasisBatch* w = new BasisBatch();
   *out = w;
-  const double* cur = A;
-  int64_t curM = M, ld = M;
-  for (;;) {
-    Level l;
-    l.M = curM;
-    l.nb = (curM + BRW - 1) / BRW;
-    HCK(hipMallocAsync((void**)&l.V, sizeof(double) * l.nb * ell * BRW, s));
-    HCK(hipMallocAsync((void**)&l.tau, sizeof(double) * l.nb * ell, s));
-    HCK(hipMallocAsync((void**)&l.Rst, sizeof(double) * l.nb * ell * ell, s));
-    if (ell <= 8) launch_hh<8>(cur, curM, ld, ell, l, s);
-    else if (ell <= 16) launch_hh<16>(cur, curM, ld, ell, l, s);
-    else if (ell <= 24) launch_hh<24>(cur, curM, ld, ell, l, s);
-    else launch_hh<32>(cur, curM, ld, ell, l, s);
-    HCK(hipGetLastError());
-    w->lv.push_back(l);
-    if (l.nb == 1) break;
-    cur = l.Rst;
-    curM = l.nb * ell;
-    ld = curM;
+  w->n = n;
+  w->ell = ell;
+  w->rpt = leaf_rpt(ell);
+  w->s = s;
+  w->lv.resize(n);
+  const int64_t br = 256 * (int64_t)w->rpt;
+  // level shapes and one workspace
+  int64_t tot = 0;
+  int maxL = 0;
+  for (int p = 0; p < n; ++p) {
+    int64_t curM = M[p];
+    for (;;) {
+      Level l;
+      l.M = curM;
+      l.nb = (curM + br - 1) / br;
+      tot += l.nb * ell * br + l.nb * ell + l.nb * ell * ell;
+      w->lv[p].push_back(l);
+      if (l.nb == 1) break;
+      curM = l.nb * ell;
+    }
+    maxL = std::max(maxL, (int)w->lv[p].size());
+    tot += ell * ell + (want_sv ? ell : 0);
   }
-  HCK(hipMallocAsync((void**)&w->Qc, sizeof(double) * ell * ell, s));
-  const Level& top = w->lv.back();
-  hipLaunchKernelGGL(k_cpqr, dim3(1), dim3(64), 0, s, top.Rst, (int64_t)ell, ell, w->piv, w->Qc);
+  HCK(hipMallocAsync((void**)&w->ws, sizeof(double) * tot, s));
+  double* cur = w->ws;
+  w->Qc.resize(n);
+  w->sv.assign(n, nullptr);
+  for (int p = 0; p < n; ++p) {
+    for (Level& l : w->lv[p]) {
+      l.V = cur;
+      cur += l.nb * ell * br;
+      l.tau = cur;
+      cur += l.nb * ell;
+      l.Rst = cur;
+      cur += l.nb * ell * ell;
+    }
+    w->Qc[p] = cur;
+    cur += ell * ell;
+    if (want_sv) {
+      w->sv[p] = cur;
+      cur += ell;
+    }
+  }
+  // one launch per tree level over every problem that still has it
+  for (int L = 0; L < maxL; ++L) {
+    LeafBatch B;
+    std::memset(&B, 0, sizeof(B));
+    int64_t nblk = 0;
+    for (int p = 0; p < n; ++p) {
+      if ((int)w->lv[p].size() <= L) continue;
+      const Level& l = w->lv[p][L];
+      const int i = B.n++;
+      B.A[i] = L == 0 ? A[p] : w->lv[p][L - 1].Rst;
+      B.M[i] = l.M;
+      B.lda[i] = l.M;
+      B.V[i] = l.V;
+      B.tau[i] = l.tau;
+      B.Rst[i] = l.Rst;
+      B.ldr[i] = l.nb * ell;
+      B.blk0[i] = nblk;
+      nblk += l.nb;
+    }
+    B.blk0[B.n] = nblk;
+    launch_leaf(B, nblk, ell, s);
+    HCK(hipGetLastError());
+  }
+  CpqrBatch C;
+  SvBatch S;
+  std::memset(&C, 0, sizeof(C));
+  std::memset(&S, 0, sizeof(S));
+  for (int p = 0; p < n; ++p) {
+    C.R[p] = S.R[p] = w->lv[p].back().Rst;
+    C.ldr[p] = S.ldr[p] = ell;
+    C.piv[p] = piv[p];
+    C.Qc[p] = w->Qc[p];
+    S.sv[p] = w->sv[p];
+  }
+  if (ell <= 8) hipLaunchKernelGGL((k_cpqr<8>), dim3(n), dim3(64), 0, s, C, ell);
+  else if (ell <= 16) hipLaunchKernelGGL((k_cpqr<16>), dim3(n), dim3(64), 0, s, C, ell);
+  else if (ell <= 24) hipLaunchKernelGGL((k_cpqr<24>), dim3(n), dim3(64), 0, s, C, ell);
+  else hipLaunchKernelGGL((k_cpqr<32>), dim3(n), dim3(64), 0, s, C, ell);
   HCK(hipGetLastError());
   if (want_sv) {
-    HCK(hipMallocAsync((void**)&w->sv, sizeof(double) * ell, s));
-    hipLaunchKernelGGL(k_jacobi_sv, dim3(1), dim3(512), 0, s, top.Rst, (int64_t)ell, ell, w->sv);
+    hipLaunchKernelGGL(k_jacobi_sv, dim3(n), dim3(512), 0, s, S, ell);
     HCK(hipGetLastError());
   }
   return hipSuccess;
 }
 
-const double* basis_sv(BasisWork* w) { return w->sv; }
+const double* basis_batch_sv(BasisBatch* w, int p) { return w->sv[p]; }
 
-template <int RP>
-static void launch_apply(const Level& l, int ell, const double* zin, int64_t ldzi, int r, double* zout,
-                         hipStream_t s) {
-  hipLaunchKernelGGL((k_hh_apply<RP>), dim3((unsigned)((l.nb + 3) / 4)), dim3(256), 0, s, l.V, l.tau, ell, l.nb, zin,
-                     ldzi, r, zout, l.M, l.M);
+static void launch_apply(const ApplyBatch& B, int64_t nblk, int rpt, int rmax, int ell, hipStream_t s) {
+  const dim3 g((unsigned)nblk), b(256);
+  if (rpt == 4) {
+    if (rmax <= 8) hipLaunchKernelGGL((k_qr_apply<8, 4>), g, b, 0, s, B, ell);
+    else hipLaunchKernelGGL((k_qr_apply<16, 4>), g, b, 0, s, B, ell);
+  } else {
+    if (rmax <= 8) hipLaunchKernelGGL((k_qr_apply<8, 2>), g, b, 0, s, B, ell);
+    else if (rmax <= 16) hipLaunchKernelGGL((k_qr_apply<16, 2>), g, b, 0, s, B, ell);
+    else if (rmax <= 24) hipLaunchKernelGGL((k_qr_apply<24, 2>), g, b, 0, s, B, ell);
+    else hipLaunchKernelGGL((k_qr_apply<32, 2>), g, b, 0, s, B, ell);
+  }
 }
 
-hipError_t basis_form_q(BasisWork* w, int r, double* Q, hipStream_t s) {
-  const int ell = w->ell;
-  const int L = (int)w->lv.size();
-  int64_t maxrows = 0;
-  for (int i = 1; i < L; ++i) maxrows = std::max(maxrows, w->lv[i].M);
-  if (!w->tmp && maxrows > 0) HCK(hipMallocAsync((void**)&w->tmp, sizeof(double) * 2 * maxrows * r, s));
-  double* bufA = w->tmp;
-  double* bufB = w->tmp ? w->tmp + maxrows * r : nullptr;
-  const double* zin = w->Qc;   // ell x r (first r columns of Qc, ld ell)
-  int64_t ldzi = ell;
-  for (int i = L - 1; i >= 0; --i) {
-    const Level& l = w->lv[i];
-    double* zout = (i == 0) ? Q : ((L - 1 - i) % 2 == 0 ? bufA : bufB);
-    if (r <= 8) launch_apply<8>(l, ell, zin, ldzi, r, zout, s);
-    else if (r <= 16) launch_apply<16>(l, ell, zin, ldzi, r, zout, s);
-    else if (r <= 24) launch_apply<24>(l, ell, zin, ldzi, r, zout, s);
-    else launch_apply<32>(l, ell, zin, ldzi, r, zout, s);
+// Q_p (M_p x r_p) = first r_p columns of each problem's pivoted orthogonal
+// factor: the reflector trees applied top-down, one launch per depth.
+hipError_t basis_form_q_batch(BasisBatch* w, const int* r, double* const* Q, hipStream_t s) {
+  const int n = w->n, ell = w->ell;
+  int maxL = 0, rmax = 1;
+  int64_t tmpsz = 0;
+  std::vector<int64_t> off(n, 0);
+  for (int p = 0; p < n; ++p) {
+    const int L = (int)w->lv[p].size();
+    maxL = std::max(maxL, L);
+    rmax = std::max(rmax, r[p]);
+    int64_t maxrows = 0;
+    for (int i = 1; i < L; ++i) maxrows = std::max(maxrows, w->lv[p][i].M);
+    off[p] = tmpsz;
+    tmpsz += 2 * maxrows * r[p];
+  }
+  if (tmpsz > 0) HCK(hipMallocAsync((void**)&w->tmp, sizeof(double) * tmpsz, s));
+  std::vector<const double*> zin(n);
+  std::vector<int64_t> ldzi(n, ell);
+  for (int p = 0; p < n; ++p) zin[p] = w->Qc[p];   // ell x r (first r columns of Qc, ld ell)
+  for (int step = 0; step < maxL; ++step) {
+    ApplyBatch B;
+    std::memset(&B, 0, sizeof(B));
+    int64_t nblk = 0;
+    std::vector<std::pair<int, double*>> outs;
+    for (int p = 0; p < n; ++p) {
+      const int L = (int)w->lv[p].size();
+      const int i_l = L - 1 - step;   // this problem's level at this depth
+      if (i_l < 0) continue;
+      const Level& l = w->lv[p][i_l];
+      double* zout;
+      if (i_l == 0) {
+        zout = Q[p];
+      } else {
+        int64_t mr = 0;
+        for (int i = 1; i < L; ++i) mr = std::max(mr, w->lv[p][i].M);
+        zout = w->tmp + off[p] + (step % 2) * mr * r[p];
+      }
+      const int i = B.n++;
+      B.V[i] = l.V;
+      B.tau[i] = l.tau;
+      B.Zin[i] = zin[p];
+      B.ldzi[i] = ldzi[p];
+      B.r[i] = r[p];
+      B.Zout[i] = zout;
+      B.ldzo[i] = l.M;
+      B.Mout[i] = l.M;
+      B.blk0[i] = nblk;
+      nblk += l.nb;
+      outs.push_back({p, zout});
+    }
+    B.blk0[B.n] = nblk;
+    launch_apply(B, nblk, w->rpt, rmax, ell, s);
     HCK(hipGetLastError());
-    zin = zout;
-    ldzi = l.M;
+    for (auto& o : outs) {
+      const int L = (int)w->lv[o.first].size();
+      zin[o.first] = o.second;
+      ldzi[o.first] = w->lv[o.first][L - 1 - step].M;
+    }
   }
   return hipSuccess;
 }
@@ -658,12 +845,17 @@ __global__ __launch_bounds__(256) void k_middle_a_part(const double* __restrict_
   }
 }
 
-__global__ void k_middle_a_sum(const double* __restrict__ part, int nb, int nout, double* __restrict__ A) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nout; t += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int g = 0; g < nb; ++g) s += part[(int64_t)g * nout + t];
-    A[t] = s;   // t = b + rm * c
-  }
+// one wavefront per entry of A; lanes take partials g = lane, lane + 64, ...
+// and a fixed butterfly adds them (deterministic)
+__global__ __launch_bounds__(256) void k_middle_a_sum(const double* __restrict__ part, int nb, int nout,
+                                                      double* __restrict__ A) {
+  const int lane = threadIdx.x & 63;
+  const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (t >= nout) return;
+  double s = 0.0;
+  for (int g = lane; g < nb; g += 64) s += part[(int64_t)g * nout + t];
+  s = wave_sum(s);
+  if (lane == 0) A[t] = s;   // t = b + rm * c
 }
 
 hipError_t middle_a(const double* Pm, int64_t Cm, int rm, const SketchArgs& geo, int prec, double* A, hipStream_t s) {
@@ -673,7 +865,7 @@ hipError_t middle_a(const double* Pm, int64_t Cm, int rm, const SketchArgs& geo,
   hipError_t e = hipMallocAsync((void**)&part, sizeof(double) * nb * nout, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_middle_a_part, dim3(nb), dim3(256), 0, s, Pm, Cm, rm, geo, prec, part);
-  hipLaunchKernelGGL(k_middle_a_sum, dim3((nout + 255) / 256), dim3(256), 0, s, part, nb, nout, A);
+  hipLaunchKernelGGL(k_middle_a_sum, dim3((nout + 3) / 4), dim3(256), 0, s, part, nb, nout, A);
   e = hipGetLastError();
   (void)hipFreeAsync(part, s);
   return e;
