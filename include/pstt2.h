@@ -98,6 +98,7 @@ typedef struct {
   int32_t r[PSTT2_MAX_D + 1];  /* r[0] = r[d] = 1 */
   double* core[PSTT2_MAX_D];   /* device pointers */
   int32_t owned;               /* 1: allocated by the library, release with tt_cores_free */
+  void* stream;                /* owned cores: the HIP stream that orders their release */
 } tt_cores;
 
 typedef struct pstt2_ctx pstt2_ctx;
@@ -203,7 +204,9 @@ pstt2_status tt_reconstruct(const tt_cores* cores, void* x_out_dev, pstt2_dtype 
  * core pointers are caller-provided device memory).  sync.  Errors: EINVAL, EDEVICE. */
 pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream);
 
-/* Release library-owned cores (owned == 1) and clear the struct.  NULL is ignored. */
+/* Release library-owned cores (owned == 1), stream-ordered after the work
+ * already enqueued on the stream that produced them, and clear the struct.
+ * NULL is ignored. */
 void tt_cores_free(tt_cores* cores);
 
 /* Message for the last failing call on ctx, or (ctx == NULL) on this thread. */

@@ -44,6 +44,7 @@ class TTCores(ctypes.Structure):
         ("r", ctypes.c_int32 * (MAX_D + 1)),
         ("core", ctypes.c_void_p * MAX_D),
         ("owned", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
     ]
 
 

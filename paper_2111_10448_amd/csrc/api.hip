@@ -54,6 +54,16 @@ struct pstt2_ctx {
 
 namespace {
 
+// Small pinned host buffer for device-to-host results (flags, singular values,
+// error sums): copies into pageable memory take a slow staged path.  One per
+// host thread, allocated on first use, held until the process ends.
+double* pinned_scratch() {
+  thread_local double* buf = nullptr;
+  if (!buf && hipHostMalloc((void**)&buf, sizeof(double) * (PSTT2_MAX_D + 1) * PSTT2_MAX_ELL, 0) != hipSuccess)
+    buf = nullptr;
+  return buf;
+}
+
 pstt2_status fail(pstt2_ctx* c, pstt2_status st, const std::string& msg) {
   if (c) c->err = msg;
   pstt2_set_tls_error(msg);
@@ -300,6 +310,17 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   if ((e = hipMalloc(&c->Tt, sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(T)");
   if ((e = hipMalloc(&c->flag, sizeof(int))) != hipSuccess) return bail(e, "hipMalloc(flag)");
   if ((e = hipMalloc(&c->piv_dev, sizeof(int) * (d + 1) * c->ell)) != hipSuccess) return bail(e, "hipMalloc(piv)");
+  {
+    // keep stream-ordered workspace in the device's default pool between
+    // synchronisations (the recovery and the error pass allocate and free
+    // small buffers every call; returning them to the driver costs ~0.3 ms)
+    hipMemPool_t pool = nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  }
   if ((e = hipMalloc(&c->one, sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(one)");
   const double one = 1.0;
   if ((e = hipMemcpy(c->one, &one, sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "hipMemcpy");
@@ -468,9 +489,10 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   r[0] = r[d] = 1;
   std::vector<double> sv((size_t)(d + 1) * ell, 0.0);
   if (tol) {
+    double* pin = pinned_scratch();
     for (int k = 1; k <= d - 1; ++k) {
-      hipError_t e = hipMemcpyAsync(sv.data() + (size_t)k * ell, basis_batch_sv(bw, k - 1), sizeof(double) * ell,
-                                    hipMemcpyDeviceToHost, s);
+      hipError_t e = hipMemcpyAsync(pin ? pin + (size_t)k * ell : sv.data() + (size_t)k * ell,
+                                    basis_batch_sv(bw, k - 1), sizeof(double) * ell, hipMemcpyDeviceToHost, s);
       if (e != hipSuccess) {
         basis_batch_free(bw);
         return hfail(c, e, "hipMemcpyAsync(sv)");
@@ -481,6 +503,9 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
       basis_batch_free(bw);
       return hfail(c, e, "recover");
     }
+    if (pin)
+      for (int k = 1; k <= d - 1; ++k)
+        for (int i = 0; i < ell; ++i) sv[(size_t)k * ell + i] = pin[(size_t)k * ell + i];
   }
   for (int k = 1; k <= d - 1; ++k) {
     const int64_t cap = std::min<int64_t>({c->Rk[k], c->N / c->Rk[k], (int64_t)ell});
@@ -520,7 +545,8 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   }
   for (int k = 0; k <= d; ++k) tc.r[k] = r[k];
   double* base = nullptr;
-  HIPCK(c, hipMalloc(&base, sizeof(double) * tot));
+  HIPCK(c, hipMallocAsync((void**)&base, sizeof(double) * tot, s));
+  tc.stream = (void*)s;
   int64_t o = 0;
   for (int k = 0; k < d; ++k) {
     tc.core[k] = base + o;
@@ -567,8 +593,10 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   if (e != hipSuccess) return cfail(e, "middle core");
   // (5) the single completion point: non-finite sketches, singular LS
   int hflag = 0;
-  e = hipMemcpyAsync(&hflag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  int* pin = (int*)pinned_scratch();
+  e = hipMemcpyAsync(pin ? pin : &hflag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (pin) hflag = *pin;
   if (e != hipSuccess) return cfail(e, "recover");
   if (hflag & 1) {
     tt_cores_free(&tc);
@@ -765,8 +793,10 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
 #undef VJPCK
   release();
   int hflag = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  int* pin = (int*)pinned_scratch();
+  if (e == hipSuccess) e = hipMemcpyAsync(pin ? pin : &hflag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s);
   hipError_t e2 = hipStreamSynchronize(s);
+  if (pin) hflag = *pin;
   if (e != hipSuccess) return hfail(c, e, "pstt2_vjp");
   if (e2 != hipSuccess) return hfail(c, e2, "pstt2_vjp");
   if (hflag & 1) return fail(c, PSTT2_ENUMERIC, "non-finite values in the cotangent");
@@ -824,7 +854,8 @@ pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream)
 
 void tt_cores_free(tt_cores* t) {
   if (!t) return;
-  if (t->owned && t->d >= 1) (void)hipFree(t->core[0]);   // one allocation, based at core[0]
+  // one stream-ordered allocation, based at core[0]
+  if (t->owned && t->d >= 1) (void)hipFreeAsync(t->core[0], (hipStream_t)t->stream);
   std::memset(t, 0, sizeof(*t));
 }
 
@@ -843,7 +874,12 @@ pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtyp
   if (st != PSTT2_OK) return st;
   if (!x_dev || !rel_err) return fail(nullptr, PSTT2_EINVAL, "null argument");
   double e2x2[2] = {0, 0};
-  hipError_t e = tt_error_run(cores, x_dev, dtype, e2x2, (hipStream_t)hip_stream);
+  double* pin = pinned_scratch();
+  hipError_t e = tt_error_run(cores, x_dev, dtype, pin ? pin : e2x2, (hipStream_t)hip_stream);
+  if (pin) {
+    e2x2[0] = pin[0];
+    e2x2[1] = pin[1];
+  }
   if (e != hipSuccess) return hfail(nullptr, e, "tt_error");
   *rel_err = e2x2[1] > 0 ? std::sqrt(e2x2[0] / e2x2[1]) : (e2x2[0] > 0 ? INFINITY : 0.0);
   if (!std::isfinite(*rel_err)) return fail(nullptr, PSTT2_ENUMERIC, "non-finite error");

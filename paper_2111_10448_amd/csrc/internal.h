@@ -118,7 +118,7 @@ hipError_t adj_out(int dtype, const SketchArgs& g, int prec, const double* Yb, c
                    const double* Rt, int r, const void* x, void* gx, hipStream_t s);
 
 // TT evaluation (tt_eval.hip).
-hipError_t tt_interfaces(const tt_cores* c, int split, double** L, double** Rt, hipStream_t s);
+hipError_t tt_interfaces(const tt_cores* c, int split, double** L, double** Rt, double** base, hipStream_t s);
 }  // namespace pstt2
 
 // Thread-local error text for calls without a context.

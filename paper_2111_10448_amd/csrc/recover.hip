@@ -871,81 +871,65 @@ hipError_t middle_a(const double* Pm, int64_t Cm, int rm, const SketchArgs& geo,
   return e;
 }
 
-// Least squares min ||G A - Z||_F for G (nz x rm), A (rm x ell), Z (nz x ell):
-// A^T = Qa Ra by Householder QR (one wavefront, lane = row of A^T), then every
-// row of G solves g Ra^T = z Qa.
+// Least squares min ||G A - Z||_F for G (nz x rm), A (rm x ell), Z (nz x ell),
+// A of full row rank: G = Z A^+ with A^+ = A^T W, W = (A A^T)^{-1}.  W comes
+// from Gauss-Jordan elimination on the rm x rm SPD matrix A A^T (one thread per
+// column); then Bm = A^T W (ell x rm) and every row of G is z Bm.  A is a
+// Gaussian-like rm x ell matrix (rm < ell), so cond(A A^T) = cond(A)^2 stays
+// small.  A pivot below 1e-26 of the largest diagonal (A numerically
+// rank-deficient) sets flag bit 2.
 __global__ __launch_bounds__(256) void k_middle_ls(const double* __restrict__ Z, int64_t nz,
                                                    const double* __restrict__ A, int rm, int ell,
                                                    double* __restrict__ G, int* flag) {
-  __shared__ double At[PSTT2_MAX_ELL][PSTT2_MAX_ELL + 1];  // A^T: [col b][row c] (ell x rm)
-  __shared__ double Vs[PSTT2_MAX_ELL][PSTT2_MAX_ELL + 1];
-  __shared__ double taus[PSTT2_MAX_ELL];
-  __shared__ double Qa[PSTT2_MAX_ELL][PSTT2_MAX_ELL + 1];  // [col b][row c]
-  __shared__ double Ra[PSTT2_MAX_ELL][PSTT2_MAX_ELL + 1];  // [col][row]
+  constexpr int MX = PSTT2_MAX_ELL;
+  __shared__ double As[MX][MX + 1];        // A (rm x ell)
+  __shared__ double Aug[MX][2 * MX + 1];   // [A A^T | I] -> [I | W]
+  __shared__ double Bm[MX][MX + 1];        // A^T W: [c][b]
+  __shared__ double fcol[MX];
+  __shared__ double dmax;
   const int t = threadIdx.x;
-  if (t < ell)
-    for (int b = 0; b < rm; ++b) At[b][t] = A[(int64_t)t * rm + b];
+  for (int i = t; i < rm * ell; i += blockDim.x) As[i % rm][i / rm] = A[i];
   __syncthreads();
-  if (t < 64) {   // first wavefront: Householder QR of A^T, lane = row
-    for (int j = 0; j < rm; ++j) {
-      const double x = (t < ell) ? At[j][t] : 0.0;
-      const double sigma = wave_sum(t > j ? x * x : 0.0);
-      const double alpha = __shfl(x, j);
-      double tj, beta, scal;
-      if (sigma == 0.0) {
-        tj = 0.0;
-        beta = alpha;
-        scal = 0.0;
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
-        tj = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      const double v = (t < j || t >= ell) ? 0.0 : (t == j ? 1.0 : x * scal);
-      if (t < ell) {
-        Vs[j][t] = v;
-        At[j][t] = (t < j) ? At[j][t] : (t == j ? beta : 0.0);
-      }
-      if (t == 0) taus[j] = tj;
-      for (int c = j + 1; c < rm; ++c) {
-        const double w = wave_sum(t < ell ? v * At[c][t] : 0.0) * tj;
-        if (t < ell) At[c][t] -= w * v;
-      }
+  for (int i = t; i < rm * rm; i += blockDim.x) {
+    const int a = i % rm, b = i / rm;
+    double sum = 0.0;
+    for (int c = 0; c < ell; ++c) sum += As[a][c] * As[b][c];
+    Aug[a][b] = sum;
+    Aug[a][rm + b] = a == b ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double mx = 0.0;
+    for (int a = 0; a < rm; ++a) mx = fmax(mx, Aug[a][a]);
+    dmax = mx;
+  }
+  for (int k = 0; k < rm; ++k) {
+    if (t < rm) fcol[t] = Aug[t][k];
+    __syncthreads();
+    if (t == 0 && !(fcol[k] > 1e-26 * dmax)) atomicOr(flag, 2);
+    if (t < 2 * rm) {
+      const double pk = Aug[k][t] / fcol[k];
+      Aug[k][t] = pk;
+      for (int i = 0; i < rm; ++i)
+        if (i != k) Aug[i][t] -= fcol[i] * pk;
     }
-    // explicit Qa (ell x rm), lane = row
-    for (int c = 0; c < rm; ++c) {
-      double q = (t == c) ? 1.0 : 0.0;
-      for (int j = rm - 1; j >= 0; --j) {
-        const double v = (t < ell) ? Vs[j][t] : 0.0;
-        const double w = wave_sum(v * q) * taus[j];
-        q -= w * v;
-      }
-      if (t < ell) Qa[c][t] = q;
-    }
-    if (t < rm)
-      for (int c = 0; c < rm; ++c) Ra[c][t] = At[c][t];
-    if (t == 0) {
-      double dmax = 0.0;
-      for (int j = 0; j < rm; ++j) dmax = fmax(dmax, fabs(At[j][j]));
-      for (int j = 0; j < rm; ++j)
-        if (!(fabs(At[j][j]) > 1e-13 * dmax)) atomicOr(flag, 2);
-    }
+    __syncthreads();
+  }
+  for (int i = t; i < ell * rm; i += blockDim.x) {
+    const int c = i % ell, b = i / ell;
+    double sum = 0.0;
+    for (int a = 0; a < rm; ++a) sum += As[a][c] * Aug[a][rm + b];
+    Bm[c][b] = sum;
   }
   __syncthreads();
   for (int64_t rho = t; rho < nz; rho += blockDim.x) {
-    double y[PSTT2_MAX_ELL];
+    double z[MX];
+    for (int c = 0; c < ell; ++c) z[c] = Z[(int64_t)c * nz + rho];
     for (int b = 0; b < rm; ++b) {
-      double s = 0.0;
-      for (int c = 0; c < ell; ++c) s += Z[(int64_t)c * nz + rho] * Qa[b][c];
-      y[b] = s;
+      double sum = 0.0;
+      for (int c = 0; c < ell; ++c) sum += z[c] * Bm[c][b];
+      G[(int64_t)b * nz + rho] = sum;
     }
-    // g Ra^T = y  <=>  sum_{b' >= b} g[b'] Ra(b, b') = y[b]
-    for (int b = rm - 1; b >= 0; --b) {
-      double s = y[b];
-      for (int bp = b + 1; bp < rm; ++bp) s -= y[bp] * Ra[bp][b];
-      y[b] = s / Ra[b][b];
-    }
-    for (int b = 0; b < rm; ++b) G[(int64_t)b * nz + rho] = y[b];
   }
 }
 

@@ -51,42 +51,48 @@ __global__ void k_right_iface(const double* __restrict__ G, int rp, int nk, int 
   }
 }
 
-// Interfaces in stream-ordered memory (release with hipFreeAsync on the same stream).
-hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** Rout, hipStream_t s) {
+// Interfaces in one stream-ordered allocation: *base is returned for a single
+// hipFreeAsync on the same stream; *Lout (R_split x r_split) and *Rout
+// (r_split x C_split) point into it.
+hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** Rout, double** base, hipStream_t s) {
   const int d = c->d;
-  int64_t Rp = c->n[0];
-  double* L = nullptr;
-  hipError_t e = hipMallocAsync((void**)&L, sizeof(double) * Rp * c->r[1], s);
+  // sizes of every intermediate level
+  int64_t tot = 0, Rp = c->n[0];
+  tot += Rp * c->r[1];
+  for (int k = 1; k < split; ++k) {
+    Rp *= c->n[k];
+    tot += Rp * c->r[k + 1];
+  }
+  int64_t Ck = c->n[d - 1];
+  tot += Ck * c->r[d - 1];
+  for (int k = d - 2; k >= split; --k) {
+    Ck *= c->n[k];
+    tot += Ck * c->r[k];
+  }
+  double* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, sizeof(double) * tot, s);
   if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(L, c->core[0], sizeof(double) * Rp * c->r[1], hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return e;
+  *base = ws;
+  double* cur = ws;
+  Rp = c->n[0];
+  double* L = c->core[0];   // L_1 = G_1 (read only)
   for (int k = 1; k < split; ++k) {
     const int nk = (int)c->n[k];
-    double* Ln = nullptr;
-    e = hipMallocAsync((void**)&Ln, sizeof(double) * Rp * nk * c->r[k + 1], s);
-    if (e != hipSuccess) return e;
+    double* Ln = cur;
+    cur += Rp * nk * c->r[k + 1];
     hipLaunchKernelGGL(k_left_iface, dim3(grid_for(Rp * nk * c->r[k + 1], 256)), dim3(256), 0, s, L, Rp, c->r[k],
                        c->core[k], nk, c->r[k + 1], Ln);
-    e = hipFreeAsync(L, s);
-    if (e != hipSuccess) return e;
     L = Ln;
     Rp *= nk;
   }
-  int64_t Ck = c->n[d - 1];
-  double* R = nullptr;
-  e = hipMallocAsync((void**)&R, sizeof(double) * Ck * c->r[d - 1], s);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(R, c->core[d - 1], sizeof(double) * Ck * c->r[d - 1], hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return e;
+  Ck = c->n[d - 1];
+  double* R = c->core[d - 1];   // Rt_d = G_d (read only)
   for (int k = d - 2; k >= split; --k) {
     const int nk = (int)c->n[k];
-    double* Rn = nullptr;
-    e = hipMallocAsync((void**)&Rn, sizeof(double) * Ck * nk * c->r[k], s);
-    if (e != hipSuccess) return e;
+    double* Rn = cur;
+    cur += Ck * nk * c->r[k];
     hipLaunchKernelGGL(k_right_iface, dim3(grid_for(Ck * nk * c->r[k], 256)), dim3(256), 0, s, c->core[k], c->r[k],
                        nk, c->r[k + 1], R, Ck, Rn);
-    e = hipFreeAsync(R, s);
-    if (e != hipSuccess) return e;
     R = Rn;
     Ck *= nk;
   }
@@ -200,8 +206,8 @@ static hipError_t launch_err(const T* x, int64_t R, int64_t C, int r, const doub
 hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s) {
   const int d = c->d;
   const int split = (d + 1) / 2;
-  double *L = nullptr, *Rt = nullptr;
-  hipError_t e = tt_interfaces(c, split, &L, &Rt, s);
+  double *L = nullptr, *Rt = nullptr, *ifb = nullptr;
+  hipError_t e = tt_interfaces(c, split, &L, &Rt, &ifb, s);
   if (e != hipSuccess) return e;
   int64_t R = 1, C = 1;
   for (int k = 0; k < split; ++k) R *= c->n[k];
@@ -219,8 +225,7 @@ hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x
     e = hipMemcpyAsync(e2x2, part + 2 * (int64_t)gi * gj, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
   }
   hipFreeAsync(part, s);
-  hipFreeAsync(L, s);
-  hipFreeAsync(Rt, s);
+  hipFreeAsync(ifb, s);
   hipError_t e2 = hipStreamSynchronize(s);
   return e != hipSuccess ? e : e2;
 }
@@ -240,8 +245,8 @@ __global__ void k_reconstruct(T* __restrict__ out, int64_t first, int64_t count,
 hipError_t tt_reconstruct_run(const tt_cores* c, void* out, int dtype, int64_t first, int64_t count, hipStream_t s) {
   const int d = c->d;
   const int split = (d + 1) / 2;
-  double *L = nullptr, *Rt = nullptr;
-  hipError_t e = tt_interfaces(c, split, &L, &Rt, s);
+  double *L = nullptr, *Rt = nullptr, *ifb = nullptr;
+  hipError_t e = tt_interfaces(c, split, &L, &Rt, &ifb, s);
   if (e != hipSuccess) return e;
   int64_t R = 1;
   for (int k = 0; k < split; ++k) R *= c->n[k];
@@ -255,8 +260,7 @@ hipError_t tt_reconstruct_run(const tt_cores* c, void* out, int dtype, int64_t f
                          count, R, r, L, Rt);
     e = hipGetLastError();
   }
-  hipFreeAsync(L, s);
-  hipFreeAsync(Rt, s);
+  hipFreeAsync(ifb, s);
   hipError_t e2 = hipStreamSynchronize(s);
   return e != hipSuccess ? e : e2;
 }

@@ -38,8 +38,9 @@ def test_struct_layouts_match_header():
     from paper_2111_10448_amd import _lib as L
     assert ctypes.sizeof(L.Desc) == 432
     assert L.Desc.eps.offset == 408 and L.Desc.drm_factors.offset == 424
-    assert ctypes.sizeof(L.TTCores) == 4 + 4 + 256 + 132 + 4 + 256 + 4 + 4
-    assert L.TTCores.core.offset == 400
+    # d, pad, n[32], r[33], pad, core[32], owned, pad, stream
+    assert ctypes.sizeof(L.TTCores) == 4 + 4 + 256 + 132 + 4 + 256 + 4 + 4 + 8
+    assert L.TTCores.core.offset == 400 and L.TTCores.stream.offset == 664
 
 
 @pytest.mark.parametrize("field,value,msg", [
