@@ -75,6 +75,18 @@ typedef enum { PSTT2_P_F64 = 0, PSTT2_P_F32 = 1, PSTT2_P_BF16 = 2, PSTT2_P_BF16X
  * (equation "PSTT2_final_core"); see pstt2_middle_pass. */
 typedef enum { PSTT2_MID_ONEPASS = 0, PSTT2_MID_TWOPASS = 1 } pstt2_mid;
 
+/* Khatri-Rao DRM scheme (Section 3.2, equation "sketch_orig").
+ *   NESTED       one Gaussian factor per mode, shared by every split: the
+ *                pass forms the two sketches of the middle unfolding and every
+ *                other split's sketch follows by contracting modes (2 products
+ *                per tile of X).
+ *   INDEPENDENT  every split draws its own factors (the paper's Psi^(j)): the
+ *                pass forms one right sketch per split k <= m and one left
+ *                sketch per split k >= m (d products per tile), each slab read
+ *                once per pair of them.
+ * The adjoint (pstt2_vjp) covers NESTED. */
+typedef enum { PSTT2_DRM_NESTED = 0, PSTT2_DRM_INDEPENDENT = 1 } pstt2_drm;
+
 typedef struct {
   int32_t d;                  /* order, 2 <= d <= PSTT2_MAX_D */
   int64_t n[PSTT2_MAX_D];     /* mode sizes n_1..n_d in n[0..d-1], each >= 1 */
@@ -85,9 +97,12 @@ typedef struct {
   double eps;                 /* tolerance mode: target relative Frobenius error, 0 < eps < 1 */
   int32_t rmax;               /* tolerance mode: rank cap (<= 0: ell - 2) */
   int32_t ell;                /* sketch size r + p, 1 <= ell <= PSTT2_MAX_ELL */
-  const double* drm_factors;  /* host, copied at create: psi_1..psi_{d-1} then omega_2..omega_d,
-                                 factor q is n_q x ell with ell fastest (element (i, c) at i*ell + c),
-                                 iid standard Gaussian in the paper's DRMs (Section 3.2) */
+  const double* drm_factors;  /* host, copied at create; factor q is n_q x ell with ell fastest
+                                 (element (i, c) at i*ell + c), iid standard Gaussian in the
+                                 paper's DRMs (Section 3.2).  NESTED: psi_1..psi_{d-1} then
+                                 omega_2..omega_d.  INDEPENDENT: for split k = 1..d-1 in turn,
+                                 psi^(k)_1..psi^(k)_k then omega^(k)_{k+1}..omega^(k)_d */
+  pstt2_drm drm;              /* factor scheme */
 } pstt2_desc;
 
 /* A tensor train.  Core k (0-based) is r[k] x n[k] x r[k+1], column-major

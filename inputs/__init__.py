@@ -243,6 +243,16 @@ def pack_factors(psi: dict, omega: dict, d: int) -> np.ndarray:
     return np.concatenate(parts)
 
 
+def pack_factors_independent(psi: dict, omega: dict, d: int) -> np.ndarray:
+    """Flat FP64 buffer for per-split factors: for split k = 1..d-1, psi[k][1..k] then omega[k][k+1..d],
+    each n_q x ell with ell fastest."""
+    parts = []
+    for k in range(1, d):
+        parts += [np.ascontiguousarray(psi[k][q], dtype=np.float64).reshape(-1) for q in range(1, k + 1)]
+        parts += [np.ascontiguousarray(omega[k][q], dtype=np.float64).reshape(-1) for q in range(k + 1, d + 1)]
+    return np.concatenate(parts)
+
+
 def slab_bounds(numel: int, fiber: int, nslabs: int):
     """Split [0, numel) into nslabs contiguous runs of whole fibers of length `fiber`.
 

@@ -153,7 +153,7 @@ class PSTT2:
 
     def __init__(self, n: Sequence[int], ell: int, factors: np.ndarray, *, dtype: str = "f64",
                  prec: Optional[str] = None, ranks: Optional[Sequence[int]] = None, eps: Optional[float] = None,
-                 rmax: int = 0, mid: str = "onepass", stream=None):
+                 rmax: int = 0, mid: str = "onepass", drm: str = "nested", stream=None):
         self.n = [int(v) for v in n]
         self.d = len(self.n)
         self.ell = int(ell)
@@ -167,6 +167,7 @@ class PSTT2:
         desc.dtype = L.F64 if dtype == "f64" else L.F32
         desc.prec = L.PREC[prec]
         desc.mid = L.MID[mid]
+        desc.drm = L.DRM[drm]
         if ranks is not None:
             for k, v in enumerate(ranks):
                 desc.ranks[k] = int(v)
@@ -315,10 +316,11 @@ def tt_reconstruct(tt, first: int = 0, count: Optional[int] = None, dtype=None, 
 
 def decompose(x, n: Sequence[int], ell: int, factors: np.ndarray, *, prec: Optional[str] = None,
               ranks: Optional[Sequence[int]] = None, eps: Optional[float] = None, rmax: int = 0,
-              mid: str = "onepass") -> TT:
+              mid: str = "onepass", drm: str = "nested") -> TT:
     """One-shot PSTT2 of a whole flat column-major CUDA tensor."""
     dtype = "f64" if _dtype_code(x) == L.F64 else "f32"
-    with PSTT2(n, ell, factors, dtype=dtype, prec=prec, ranks=ranks, eps=eps, rmax=rmax, mid=mid) as ctx:
+    with PSTT2(n, ell, factors, dtype=dtype, prec=prec, ranks=ranks, eps=eps, rmax=rmax, mid=mid,
+               drm=drm) as ctx:
         ctx.sketch(x.reshape(-1))
         tt = ctx.recover()
         if mid == "twopass":

@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EDEVICE"
 F64, F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 MID = {"onepass": 0, "twopass": 1}
+DRM = {"nested": 0, "independent": 1}
 
 
 class Desc(ctypes.Structure):
@@ -34,6 +35,7 @@ class Desc(ctypes.Structure):
         ("rmax", ctypes.c_int32),
         ("ell", ctypes.c_int32),
         ("drm_factors", ctypes.POINTER(ctypes.c_double)),
+        ("drm", ctypes.c_int),
     ]
 
 

@@ -45,8 +45,19 @@ struct pstt2_ctx {
   int ranks[PSTT2_MAX_D + 1] = {};
   bool recovered = false;
   double* one = nullptr;       // device scalar 1.0 (Q_0 when m == 1)
-  double* om_tab = nullptr;    // Omega_m table, C x L4
+  double* om_tab = nullptr;    // Omega_m table, C x L4 (independent scheme: split m's)
   int L4 = 4;
+  // independent DRM scheme: per-split factor offsets, Omega_m tables of the
+  // right splits k < m, the extra sketches of X_m, and sinks for pass groups
+  // with only one side
+  bool indep = false;
+  int64_t ipsi_off[PSTT2_MAX_D + 1][PSTT2_MAX_D] = {};  // [split k][mode q-1]
+  int64_t iom_off[PSTT2_MAX_D + 1][PSTT2_MAX_D] = {};
+  std::vector<double*> iom_tab;   // [k], k < m
+  std::vector<double*> iY;        // [k], k < m: X_m Omega_m^(k), R x ell
+  std::vector<double*> iT;        // [k], m < k < d: (Psi_m^(k)T X_m)^T, C x ell
+  double* sinkY = nullptr;
+  double* sinkT = nullptr;
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_pool;
   std::string err;
@@ -105,8 +116,8 @@ SketchArgs base_args(const pstt2_ctx* c) {
   for (int q = 0; q < c->d; ++q) a.n[q] = (int32_t)c->n[q];
   a.fac = c->fac;
   for (int q = 0; q < PSTT2_MAX_D; ++q) {
-    a.psi_off[q] = c->psi_off[q];
-    a.omega_off[q] = c->omega_off[q];
+    a.psi_off[q] = c->indep ? c->ipsi_off[c->m][q] : c->psi_off[q];
+    a.omega_off[q] = c->indep ? c->iom_off[c->m][q] : c->omega_off[q];
   }
   a.ypart = c->ypart;
   a.tpart = c->tpart;
@@ -145,10 +156,46 @@ struct Piece {
 };
 
 // Stream a list of slabs: partial columns one by one, whole columns batched.
+// Pass groups.  Nested scheme: one group (Y_R and T_m).  Independent scheme:
+// group g forms the right sketch of split g + 1 (if g + 1 <= m) and the left
+// sketch of split m + g (if m + g <= d - 1), each with its own factors; the
+// absent side of a group goes to a sink.
+int pass_groups(const pstt2_ctx* c) { return c->indep ? std::max(c->m, c->d - c->m) : 1; }
+
+SketchArgs group_args(const pstt2_ctx* c, int g, double** Ydst, double** Tdst) {
+  SketchArgs a = base_args(c);
+  if (!c->indep) {
+    *Ydst = c->Y;
+    *Tdst = c->Tt;
+    return a;
+  }
+  const int m = c->m, d = c->d;
+  const int kr = g + 1, kl = m + g;
+  if (kr <= m) {
+    for (int q = 0; q < PSTT2_MAX_D; ++q) a.omega_off[q] = c->iom_off[kr][q];
+    a.om_tab = kr == m ? c->om_tab : c->iom_tab[kr];
+    *Ydst = kr == m ? c->Y : c->iY[kr];
+  } else {
+    *Ydst = c->sinkY;
+  }
+  if (kl <= d - 1) {
+    for (int q = 0; q < PSTT2_MAX_D; ++q) a.psi_off[q] = c->ipsi_off[kl][q];
+    *Tdst = kl == m ? c->Tt : c->iT[kl];
+  } else {
+    *Tdst = c->sinkT;
+  }
+  return a;
+}
+
 pstt2_status run_slabs(pstt2_ctx* c, const std::vector<Piece>& ps) {
   const int esz = c->dtype == PSTT2_F64 ? 8 : 4;
   const int64_t R = c->R;
   std::vector<Seg> segs;
+  struct Edge {
+    const char* x;
+    int64_t r0, r1, col;
+  };
+  std::vector<Edge> edges;
   for (const Piece& p : ps) {
     if (p.count == 0) continue;
     const int64_t lo = p.first, hi = p.first + p.count;
@@ -157,47 +204,50 @@ pstt2_status run_slabs(pstt2_ctx* c, const std::vector<Piece>& ps) {
     if (lo % R != 0) {   // head piece of column lo / R
       const int64_t col = lo / R;
       const int64_t r0 = lo % R, r1 = std::min<int64_t>(R, r0 + p.count);
-      SketchArgs a = base_args(c);
-      HIPCK(c, launch_partial_col(c->dtype, base, r0, r1, col, a, c->Y, c->Tt, c->stream));
+      edges.push_back(Edge{base, r0, r1, col});
     }
     if (c1 > c0) segs.push_back(Seg{base + (c0 * R - lo) * esz, c0, c1 - c0, 0});
     if (hi % R != 0 && hi / R >= c0 && (lo / R != hi / R || lo % R == 0)) {   // tail piece
       const int64_t col = hi / R;
-      SketchArgs a = base_args(c);
-      HIPCK(c, launch_partial_col(c->dtype, base + (col * R - lo) * esz, 0, hi % R, col, a, c->Y, c->Tt,
-                                  c->stream));
+      edges.push_back(Edge{base + (col * R - lo) * esz, 0, hi % R, col});
     }
   }
-  for (size_t s0 = 0; s0 < segs.size(); s0 += kMaxSeg) {
-    SketchArgs a = base_args(c);
-    const size_t s1 = std::min(segs.size(), s0 + kMaxSeg);
-    int64_t nch = 0;
-    a.nseg = (int32_t)(s1 - s0);
-    for (size_t i = s0; i < s1; ++i) {
-      Seg g = segs[i];
-      g.chunk0 = nch;
-      nch += (g.ncols + 15) / 16;
-      a.seg[i - s0] = g;
-    }
-    a.nchunks = nch;
-    a.gj_count = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nch, c->gj_max));
-    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    if (c->profile) {
-      if (c->ev_pool.empty()) {
-        HIPCK(c, hipEventCreate(&ev.first));
-        HIPCK(c, hipEventCreate(&ev.second));
-      } else {
-        ev = c->ev_pool.back();
-        c->ev_pool.pop_back();
+  for (int g = 0; g < pass_groups(c); ++g) {
+    double *Yd = nullptr, *Td = nullptr;
+    const SketchArgs ga = group_args(c, g, &Yd, &Td);
+    for (const Edge& ed : edges)
+      HIPCK(c, launch_partial_col(c->dtype, ed.x, ed.r0, ed.r1, ed.col, ga, Yd, Td, c->stream));
+    for (size_t s0 = 0; s0 < segs.size(); s0 += kMaxSeg) {
+      SketchArgs a = ga;
+      const size_t s1 = std::min(segs.size(), s0 + kMaxSeg);
+      int64_t nch = 0;
+      a.nseg = (int32_t)(s1 - s0);
+      for (size_t i = s0; i < s1; ++i) {
+        Seg sg = segs[i];
+        sg.chunk0 = nch;
+        nch += (sg.ncols + 15) / 16;
+        a.seg[i - s0] = sg;
       }
-      HIPCK(c, hipEventRecord(ev.first, c->stream));
+      a.nchunks = nch;
+      a.gj_count = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nch, c->gj_max));
+      std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+      if (c->profile) {
+        if (c->ev_pool.empty()) {
+          HIPCK(c, hipEventCreate(&ev.first));
+          HIPCK(c, hipEventCreate(&ev.second));
+        } else {
+          ev = c->ev_pool.back();
+          c->ev_pool.pop_back();
+        }
+        HIPCK(c, hipEventRecord(ev.first, c->stream));
+      }
+      HIPCK(c, launch_sketch(c->prec, c->lp, a, c->stream));
+      if (c->profile) {
+        HIPCK(c, hipEventRecord(ev.second, c->stream));
+        c->ev_used.push_back(ev);
+      }
+      HIPCK(c, launch_reduce(c->prec, a, Yd, Td, c->flag, c->stream));
     }
-    HIPCK(c, launch_sketch(c->prec, c->lp, a, c->stream));
-    if (c->profile) {
-      HIPCK(c, hipEventRecord(ev.second, c->stream));
-      c->ev_used.push_back(ev);
-    }
-    HIPCK(c, launch_reduce(c->prec, a, c->Y, c->Tt, c->flag, c->stream));
   }
   return PSTT2_OK;
 }
@@ -252,6 +302,7 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
     return fail(nullptr, PSTT2_EINVAL, "FP32 tensors use PSTT2_P_F32, PSTT2_P_BF16 or PSTT2_P_BF16X3");
   if (desc->mid != PSTT2_MID_ONEPASS && desc->mid != PSTT2_MID_TWOPASS) return fail(nullptr, PSTT2_EINVAL, "bad mid");
   if (!desc->drm_factors) return fail(nullptr, PSTT2_EINVAL, "drm_factors is required");
+  if (desc->drm != PSTT2_DRM_NESTED && desc->drm != PSTT2_DRM_INDEPENDENT) return fail(nullptr, PSTT2_EINVAL, "bad drm");
   const bool tol = desc->ranks[0] <= 0;
   if (tol && !(desc->eps > 0.0 && desc->eps < 1.0)) return fail(nullptr, PSTT2_EINVAL, "tolerance mode needs 0 < eps < 1");
   int64_t N = 1;
@@ -287,15 +338,30 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   (void)hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (c->ncu <= 0) c->ncu = 256;
 
-  // factors: psi_1..psi_{d-1}, omega_2..omega_d
+  // factors: nested psi_1..psi_{d-1}, omega_2..omega_d; independent: per
+  // split k, psi^(k)_1..psi^(k)_k then omega^(k)_{k+1}..omega^(k)_d
+  c->indep = desc->drm == PSTT2_DRM_INDEPENDENT;
   int64_t off = 0;
-  for (int q = 1; q <= d - 1; ++q) {
-    c->psi_off[q - 1] = off;
-    off += c->n[q - 1] * c->ell;
-  }
-  for (int q = 2; q <= d; ++q) {
-    c->omega_off[q - 1] = off;
-    off += c->n[q - 1] * c->ell;
+  if (!c->indep) {
+    for (int q = 1; q <= d - 1; ++q) {
+      c->psi_off[q - 1] = off;
+      off += c->n[q - 1] * c->ell;
+    }
+    for (int q = 2; q <= d; ++q) {
+      c->omega_off[q - 1] = off;
+      off += c->n[q - 1] * c->ell;
+    }
+  } else {
+    for (int k = 1; k <= d - 1; ++k) {
+      for (int q = 1; q <= k; ++q) {
+        c->ipsi_off[k][q - 1] = off;
+        off += c->n[q - 1] * c->ell;
+      }
+      for (int q = k + 1; q <= d; ++q) {
+        c->iom_off[k][q - 1] = off;
+        off += c->n[q - 1] * c->ell;
+      }
+    }
   }
   auto bail = [&](hipError_t e, const char* w) {
     pstt2_status st = hfail(c, e, w);
@@ -335,6 +401,22 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   if ((e = hipMalloc(&c->om_tab, sizeof(double) * c->C * c->L4)) != hipSuccess) return bail(e, "hipMalloc(omega)");
   if ((e = build_omega_table(base_args(c), c->L4, c->om_tab, c->stream)) != hipSuccess)
     return bail(e, "omega table");
+  if (c->indep) {
+    c->iom_tab.assign(d + 1, nullptr);
+    c->iY.assign(d + 1, nullptr);
+    c->iT.assign(d + 1, nullptr);
+    for (int k = 1; k < c->m; ++k) {
+      if ((e = hipMalloc(&c->iom_tab[k], sizeof(double) * c->C * c->L4)) != hipSuccess) return bail(e, "hipMalloc(omega)");
+      if ((e = hipMalloc(&c->iY[k], sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Y)");
+      SketchArgs a = base_args(c);
+      for (int q = 0; q < PSTT2_MAX_D; ++q) a.omega_off[q] = c->iom_off[k][q];
+      if ((e = build_omega_table(a, c->L4, c->iom_tab[k], c->stream)) != hipSuccess) return bail(e, "omega table");
+    }
+    for (int k = c->m + 1; k <= d - 1; ++k)
+      if ((e = hipMalloc(&c->iT[k], sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(T)");
+    if ((e = hipMalloc(&c->sinkY, sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(sink)");
+    if ((e = hipMalloc(&c->sinkT, sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(sink)");
+  }
   c->S.assign(d + 1, nullptr);
   c->Tk.assign(d + 1, nullptr);
   c->basis.assign(d + 1, nullptr);
@@ -353,6 +435,10 @@ pstt2_status pstt2_reset(pstt2_ctx* c) {
   free_recovery(c);
   HIPCK(c, hipMemsetAsync(c->Y, 0, sizeof(double) * c->R * c->ell, c->stream));
   HIPCK(c, hipMemsetAsync(c->Tt, 0, sizeof(double) * c->C * c->ell, c->stream));
+  for (double* y : c->iY)
+    if (y) HIPCK(c, hipMemsetAsync(y, 0, sizeof(double) * c->R * c->ell, c->stream));
+  for (double* t : c->iT)
+    if (t) HIPCK(c, hipMemsetAsync(t, 0, sizeof(double) * c->C * c->ell, c->stream));
   HIPCK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
   c->cover.clear();
   c->covered = 0;
@@ -404,6 +490,11 @@ void pstt2_destroy(pstt2_ctx* c) {
   (void)hipFree(c->piv_dev);
   (void)hipFree(c->one);
   (void)hipFree(c->om_tab);
+  for (double* p : c->iom_tab) (void)hipFree(p);
+  for (double* p : c->iY) (void)hipFree(p);
+  for (double* p : c->iT) (void)hipFree(p);
+  (void)hipFree(c->sinkY);
+  (void)hipFree(c->sinkT);
   delete c;
 }
 
@@ -455,15 +546,42 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   hipStream_t s = c->stream;
   // (1) every split's sketch
   c->S[m] = c->Y;
-  for (int k = m - 1; k >= 1; --k) {
-    HIPCK(c, hipMallocAsync((void**)&c->S[k], sizeof(double) * c->Rk[k] * ell, s));
-    HIPCK(c, derive_left(c->S[k + 1], c->S[k], c->Rk[k], (int)c->n[k], ell, c->fac + c->omega_off[k], s));
-  }
   c->Tk[m] = c->Tt;
-  for (int k = m + 1; k <= d - 1; ++k) {
-    const int64_t Ck = c->N / c->Rk[k];
-    HIPCK(c, hipMallocAsync((void**)&c->Tk[k], sizeof(double) * Ck * ell, s));
-    HIPCK(c, derive_right(c->Tk[k - 1], c->Tk[k], Ck, (int)c->n[k - 1], ell, c->fac + c->psi_off[k - 1], s));
+  if (!c->indep) {
+    for (int k = m - 1; k >= 1; --k) {
+      HIPCK(c, hipMallocAsync((void**)&c->S[k], sizeof(double) * c->Rk[k] * ell, s));
+      HIPCK(c, derive_left(c->S[k + 1], c->S[k], c->Rk[k], (int)c->n[k], ell, c->fac + c->omega_off[k], s));
+    }
+    for (int k = m + 1; k <= d - 1; ++k) {
+      const int64_t Ck = c->N / c->Rk[k];
+      HIPCK(c, hipMallocAsync((void**)&c->Tk[k], sizeof(double) * Ck * ell, s));
+      HIPCK(c, derive_right(c->Tk[k - 1], c->Tk[k], Ck, (int)c->n[k - 1], ell, c->fac + c->psi_off[k - 1], s));
+    }
+  } else {
+    // split k's own sketch of X_m, contracted down mode by mode with split k's factors
+    for (int k = 1; k < m; ++k) {
+      const double* cur = c->iY[k];
+      for (int q = m; q >= k + 1; --q) {   // contract mode q: R_q -> R_{q-1} rows
+        double* nxt = nullptr;
+        HIPCK(c, hipMallocAsync((void**)&nxt, sizeof(double) * c->Rk[q - 1] * ell, s));
+        HIPCK(c, derive_left(cur, nxt, c->Rk[q - 1], (int)c->n[q - 1], ell, c->fac + c->iom_off[k][q - 1], s));
+        if (cur != c->iY[k]) HIPCK(c, hipFreeAsync((void*)cur, s));
+        cur = nxt;
+      }
+      c->S[k] = (double*)cur;
+    }
+    for (int k = m + 1; k <= d - 1; ++k) {
+      const double* cur = c->iT[k];
+      for (int q = m + 1; q <= k; ++q) {   // contract mode q: C_{q-1} -> C_q columns
+        const int64_t Cq = c->N / c->Rk[q];
+        double* nxt = nullptr;
+        HIPCK(c, hipMallocAsync((void**)&nxt, sizeof(double) * Cq * ell, s));
+        HIPCK(c, derive_right(cur, nxt, Cq, (int)c->n[q - 1], ell, c->fac + c->ipsi_off[k][q - 1], s));
+        if (cur != c->iT[k]) HIPCK(c, hipFreeAsync((void*)cur, s));
+        cur = nxt;
+      }
+      c->Tk[k] = (double*)cur;
+    }
   }
   // (2) factor every sketch (one batched TSQR over all splits); the ranks come
   // from the descriptor or, in tolerance mode, from the singular values (one
@@ -630,6 +748,7 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   if (!gbar_dev && !x_dev) return fail(c, PSTT2_EINVAL, "x_dev is needed for the fused loss (gbar_dev == NULL)");
   if (!c->recovered) return fail(c, PSTT2_ESTATE, "pstt2_vjp needs a successful pstt2_recover first");
   if (c->desc.mid != PSTT2_MID_ONEPASS) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the one-pass middle core only");
+  if (c->indep) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the nested DRM scheme only");
   const int d = c->d, m = c->m, ell = c->ell;
   if (cores->d != d) return fail(c, PSTT2_EINVAL, "cores do not match the context");
   for (int k = 0; k < d; ++k)

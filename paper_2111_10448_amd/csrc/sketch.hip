@@ -186,8 +186,40 @@ __device__ __forceinline__ ChunkInfo chunk_info(const SketchArgs& A, int64_t ci)
   return c;
 }
 
-template <int PREC, int LP, bool ALIGNED>
-__global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
+// Chunk geometry for a workgroup that visits its chunks in increasing order:
+// the segment index only moves forward, so each lookup costs O(1) amortised
+// instead of a search over all segments.
+struct SegCursor {
+  int s = 0;
+  __device__ __forceinline__ ChunkInfo at(const SketchArgs& A, int64_t ci) {
+    while (s + 1 < A.nseg && A.seg[s + 1].chunk0 <= ci) ++s;
+    ChunkInfo c;
+    c.ptr = (const char*)A.seg[s].ptr;
+    c.lcol0 = (ci - A.seg[s].chunk0) * KC;
+    c.gcol0 = A.seg[s].gcol0 + c.lcol0;
+    const int64_t left = A.seg[s].ncols - c.lcol0;
+    c.ncols = (int)(left < KC ? left : KC);
+    return c;
+  }
+};
+
+// Chunk geometry when the launch holds one segment (the whole-tensor case):
+// closed form, no search over segments.
+__device__ __forceinline__ ChunkInfo chunk_info1(const SketchArgs& A, int64_t ci) {
+  ChunkInfo c;
+  c.ptr = (const char*)A.seg[0].ptr;
+  c.lcol0 = ci * KC;
+  c.gcol0 = A.seg[0].gcol0 + c.lcol0;
+  const int64_t left = A.seg[0].ncols - c.lcol0;
+  c.ncols = (int)(left < KC ? left : KC);
+  return c;
+}
+
+// Workgroups of 4 waves, two per CU (as the FP64 kernel).
+constexpr int NWS = 4;
+
+template <int PREC, int LP, bool ALIGNED, bool SEG1>
+__global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
   using E = Eng<PREC>;
   using elem = typename E::elem;
   using lds_t = typename E::lds_t;
@@ -202,15 +234,18 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
   constexpr int VEC = E::VEC;       // elements per 16-byte load
   constexpr int NLD = KC * RW / (64 * VEC);  // 16-byte loads per lane per chunk
 
-  __shared__ lds_t Xl[NW][KC * ST];
-  __shared__ acc Tred[2][NW][LP * KC];
-  __shared__ lds_t Om[4][KC * LP];   // 4 buffers: each write is a barrier past the last read
+  constexpr int NTH = NWS * 64;          // threads
+  constexpr int NRT = (LP * KC + NTH - 1) / NTH;   // T outputs per thread in the reduction
+  static_assert(KC * LP / 2 <= NTH, "one Omega pair per thread");
+  __shared__ lds_t Xl[NWS][KC * ST];
+  __shared__ acc Tred[2][NWS][LP * KC];
+  __shared__ __align__(16) lds_t Om[4][KC * LP];   // 4 buffers: each write is a barrier past the last read
 
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int gi = blockIdx.x % A.gi_count;
   const int gj = blockIdx.x / A.gi_count;
-  const int64_t row0w = (int64_t)gi * (NW * RW) + (int64_t)w * RW;
+  const int64_t row0w = (int64_t)gi * (NWS * RW) + (int64_t)w * RW;
   const int64_t cb = (int64_t)gj * A.nchunks / A.gj_count;
   const int64_t ce = (int64_t)(gj + 1) * A.nchunks / A.gj_count;
   const int l16 = lane & 15, g4 = lane >> 4;
@@ -247,24 +282,38 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
     }
   }
 
-  // Omega_m rows of a chunk (thread t < KC*LP holds entry (t / LP, t % LP)),
-  // loaded one iteration before they are written to LDS so that waiting for
-  // them never waits for the X prefetch (loads retire in order).
-  auto load_omega = [&](int64_t ci) -> double {
-    const int t = threadIdx.x;
-    double v = 0.0;
-    if (t < KC * LP && ci < ce) {
-      const int col = t / LP, c = t % LP;
-      ChunkInfo ch = chunk_info(A, ci);
-      if (col < ch.ncols && c < A.ell) v = A.om_tab[(ch.gcol0 + col) * A.L4 + c];
+  // one cursor per stream of lookups (X loads, Omega loads, T partials), each
+  // visiting chunks in increasing order
+  SegCursor cx, co, ct;
+  auto info = [&](SegCursor& cu, int64_t ci) -> ChunkInfo { return SEG1 ? chunk_info1(A, ci) : cu.at(A, ci); };
+
+  // Omega_m rows of a chunk: thread t < KC*LP/2 holds entries e = 2t, 2t + 1 of
+  // row e / LP (LP is even; the table's columns ell..L4-1 are zero and the
+  // ones past L4 are skipped).  Loaded one iteration before they are written
+  // to LDS, so waiting for them never waits for the X prefetch (loads retire
+  // in order).
+  double2 omv;
+  auto load_omega = [&](int64_t ci) {
+    const int e = 2 * threadIdx.x;
+    omv = double2{0.0, 0.0};
+    if (e < KC * LP && ci < ce) {
+      ChunkInfo ch = info(co, ci);
+      const int col = e / LP, c = e % LP;
+      if (col < ch.ncols && c < A.L4) omv = *(const double2*)&A.om_tab[(ch.gcol0 + col) * A.L4 + c];
     }
-    return v;
+  };
+  auto store_omega = [&](int buf) {
+    const int e = 2 * threadIdx.x;
+    if (e < KC * LP) {
+      Om[buf][e] = drm_to_lds<PREC>(omv.x);
+      Om[buf][e + 1] = drm_to_lds<PREC>(omv.y);
+    }
   };
 
   // ---- global loads of one chunk (16-byte, coalesced along rows) ----
   elem xr[NLD][VEC];
   auto load_chunk = [&](int64_t ci) {
-    ChunkInfo ch = chunk_info(A, ci);
+    ChunkInfo ch = info(cx, ci);
     const elem* base = (const elem*)ch.ptr;
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
@@ -307,15 +356,18 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
   };
 
   auto reduce_t = [&](int buf, int64_t ci) {
-    const int t = threadIdx.x;
-    if (t < LP * KC) {
-      const int a = t / KC, col = t % KC;
-      acc s = 0;
+    ChunkInfo ch = info(ct, ci);
 #pragma unroll
-      for (int ww = 0; ww < NW; ++ww) s += Tred[buf][ww][a * KC + col];
-      ChunkInfo ch = chunk_info(A, ci);
-      if (a < A.ell && col < ch.ncols)
-        ((part*)A.tpart)[((int64_t)gi * A.ell + a) * A.C + ch.gcol0 + col] = (part)s;
+    for (int q = 0; q < NRT; ++q) {
+      const int t = threadIdx.x + NTH * q;
+      if (t < LP * KC) {
+        const int a = t / KC, col = t % KC;
+        acc s = 0;
+#pragma unroll
+        for (int ww = 0; ww < NWS; ++ww) s += Tred[buf][ww][a * KC + col];
+        if (a < A.ell && col < ch.ncols)
+          ((part*)A.tpart)[((int64_t)gi * A.ell + a) * A.C + ch.gcol0 + col] = (part)s;
+      }
     }
   };
 
@@ -325,14 +377,13 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) yacc[mt][nt] = accv{0, 0, 0, 0};
 
-  double omv = 0.0;
   if (cb < ce) {
-    if (threadIdx.x < KC * LP) {
-      Om[0][threadIdx.x] = drm_to_lds<PREC>(load_omega(cb));
-      Om[1][threadIdx.x] = drm_to_lds<PREC>(load_omega(cb + 1));
-    }
+    load_omega(cb);
+    store_omega(0);
+    load_omega(cb + 1);
+    store_omega(1);
     load_chunk(cb);
-    omv = load_omega(cb + 2);
+    load_omega(cb + 2);
   }
 
   int it = 0;
@@ -340,11 +391,11 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
     // (a) stage this chunk in the wave's LDS tile and the Omega rows of chunk
     //     ci + 2 (both loaded one iteration ago); one barrier per chunk
     store_chunk();
-    if (threadIdx.x < KC * LP) Om[(it + 2) % 4][threadIdx.x] = drm_to_lds<PREC>(omv);
+    store_omega((it + 2) % 4);
     __syncthreads();
     // (b) prefetch the next chunk and Omega three chunks ahead
     if (ci + 1 < ce) load_chunk(ci + 1);
-    omv = load_omega(ci + 3);
+    load_omega(ci + 3);
     // (c) finish the previous chunk's left sketch
     if (it >= 1) reduce_t((it - 1) & 1, ci - 1);
     // (d) matrix-core tiles
@@ -481,18 +532,6 @@ __global__ __launch_bounds__(NW * 64, 1) void k_sketch(const SketchArgs A) {
 // Output layouts: 16x16x4 element v of lane l at (4v + l/16, l%16); 4x4x4
 // block b = (l/4)%4 at (l/16, l%4) of that block.
 // ---------------------------------------------------------------------------
-// Chunk geometry when the launch holds one segment (the whole-tensor case):
-// closed form, no search over segments.
-__device__ __forceinline__ ChunkInfo chunk_info1(const SketchArgs& A, int64_t ci) {
-  ChunkInfo c;
-  c.ptr = (const char*)A.seg[0].ptr;
-  c.lcol0 = ci * KC;
-  c.gcol0 = A.seg[0].gcol0 + c.lcol0;
-  const int64_t left = A.seg[0].ncols - c.lcol0;
-  c.ncols = (int)(left < KC ? left : KC);
-  return c;
-}
-
 // FP64 workgroups have 4 waves (256 rows) and two of them share a CU, so one
 // workgroup's matrix-core work overlaps the other's barrier and load phases.
 constexpr int NWF = 4;
@@ -522,7 +561,8 @@ __global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const Sk
   const int64_t cb = (int64_t)gj * A.nchunks / A.gj_count;
   const int64_t ce = (int64_t)(gj + 1) * A.nchunks / A.gj_count;
   const int l16 = lane & 15, g4 = lane >> 4, l4 = lane & 3, blk = (lane >> 2) & 3;
-  auto info = [&](int64_t ci) -> ChunkInfo { return SEG1 ? chunk_info1(A, ci) : chunk_info(A, ci); };
+  SegCursor cx, co, ct;   // X loads, Omega loads, T partials: each in increasing chunk order
+  auto info = [&](SegCursor& cu, int64_t ci) -> ChunkInfo { return SEG1 ? chunk_info1(A, ci) : cu.at(A, ci); };
 
   // stationary left-DRM operands: Psi(row0w + 4 ks + g4, a)
   double psiq[KT][NQ > 0 ? NQ : 1];
@@ -547,7 +587,7 @@ __global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const Sk
     const int e = 2 * threadIdx.x;
     omv = double2{0.0, 0.0};
     if (e < KC * L4 && ci < ce) {
-      ChunkInfo ch = info(ci);
+      ChunkInfo ch = info(co, ci);
       const int col = e / L4, c = e % L4;
       if (col < ch.ncols) omv = *(const double2*)&A.om_tab[(ch.gcol0 + col) * A.L4 + c];
     }
@@ -559,7 +599,7 @@ __global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const Sk
 
   double xr[NLD][2];
   auto load_chunk = [&](int64_t ci) {
-    ChunkInfo ch = info(ci);
+    ChunkInfo ch = info(cx, ci);
     const double* base = (const double*)ch.ptr;
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
@@ -592,7 +632,7 @@ __global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const Sk
     }
   };
   auto reduce_t = [&](int buf, int64_t ci) {
-    ChunkInfo ch = info(ci);
+    ChunkInfo ch = info(ct, ci);
 #pragma unroll
     for (int k = 0; k < NOM; ++k) {
       const int e = threadIdx.x + NT * k;
@@ -749,24 +789,29 @@ hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream
 }
 
 void sketch_geometry(int prec, int ell, int* rows_per_block, int* threads, int* wg_per_cu) {
-  *threads = prec == P_F64 ? NWF * 64 : NW * 64;
-  // FP64: two workgroups fit in a CU's LDS while ell (rounded to 4) <= 28
-  *wg_per_cu = (prec == P_F64 && (ell + 3) / 4 * 4 <= 28) ? F64_WG_PER_CU : 1;
+  *threads = prec == P_F64 ? NWF * 64 : NWS * 64;
+  // FP64: two workgroups fit in a CU's LDS while ell (rounded to 4) <= 28;
+  // the FP32-family kernels always fit two
+  *wg_per_cu = (prec != P_F64 || (ell + 3) / 4 * 4 <= 28) ? 2 : 1;
   switch (prec) {
     case P_F64: *rows_per_block = NWF * Eng<P_F64>::RW; break;
-    case P_F32: *rows_per_block = NW * Eng<P_F32>::RW; break;
-    case P_BF16: *rows_per_block = NW * Eng<P_BF16>::RW; break;
-    default: *rows_per_block = NW * Eng<P_BF16X3>::RW; break;
+    case P_F32: *rows_per_block = NWS * Eng<P_F32>::RW; break;
+    case P_BF16: *rows_per_block = NWS * Eng<P_BF16>::RW; break;
+    default: *rows_per_block = NWS * Eng<P_BF16X3>::RW; break;
   }
 }
 
 template <int PREC, int LP>
 static hipError_t launch_t(const SketchArgs& a, bool aligned, hipStream_t s) {
-  dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(NW * 64);
-  if (aligned)
-    hipLaunchKernelGGL((k_sketch<PREC, LP, true>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((k_sketch<PREC, LP, false>), grid, block, 0, s, a);
+  dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(NWS * 64);
+  const bool seg1 = a.nseg == 1 && a.seg[0].chunk0 == 0;
+  if (aligned) {
+    if (seg1) hipLaunchKernelGGL((k_sketch<PREC, LP, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_sketch<PREC, LP, true, false>), grid, block, 0, s, a);
+  } else {
+    if (seg1) hipLaunchKernelGGL((k_sketch<PREC, LP, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_sketch<PREC, LP, false, false>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -31,19 +31,19 @@ def setup(w, n=None, ell=None):
     return x, psi, omega, fac
 
 
-def oracle_run(x, w, psi, omega, middle="onepass"):
+def oracle_run(x, w, psi, omega, middle="onepass", drm="nested"):
     x64 = np.asarray(x, dtype=np.float64)
-    drm = O.NestedKR(psi, omega)
+    drm = O.NestedKR(psi, omega) if drm == "nested" else O.IndependentKR(psi, omega)
     if w.rank is not None:
         return O.pstt2(x64, w.n, drm, ranks=w.ranks(), middle=middle)
     return O.pstt2(x64, w.n, drm, eps=w.eps, rmax=w.rmax, middle=middle)
 
 
-def gpu_run(x, w, fac, prec, slabs=None, middle="onepass", batched=False, ranks=None):
+def gpu_run(x, w, fac, prec, slabs=None, middle="onepass", batched=False, ranks=None, drm="nested"):
     import torch
     import paper_2111_10448_amd as P
     xg = torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
-    kw = dict(dtype=w.dtype, prec=prec, mid=middle)
+    kw = dict(dtype=w.dtype, prec=prec, mid=middle, drm=drm)
     if ranks is not None:
         kw["ranks"] = list(ranks)
     elif w.rank is not None:

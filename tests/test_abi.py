@@ -36,8 +36,8 @@ def test_library_exports_every_symbol():
 def test_struct_layouts_match_header():
     """ctypes layouts mirror the C structs (natural alignment, x86-64)."""
     from paper_2111_10448_amd import _lib as L
-    assert ctypes.sizeof(L.Desc) == 432
-    assert L.Desc.eps.offset == 408 and L.Desc.drm_factors.offset == 424
+    assert ctypes.sizeof(L.Desc) == 440
+    assert L.Desc.eps.offset == 408 and L.Desc.drm_factors.offset == 424 and L.Desc.drm.offset == 432
     # d, pad, n[32], r[33], pad, core[32], owned, pad, stream
     assert ctypes.sizeof(L.TTCores) == 4 + 4 + 256 + 132 + 4 + 256 + 4 + 4 + 8
     assert L.TTCores.core.offset == 400 and L.TTCores.stream.offset == 664

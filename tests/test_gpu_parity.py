@@ -64,6 +64,30 @@ def test_slab_streaming(prec, batched):
     ctx.close()
 
 
+@pytest.mark.parametrize("name,n,prec,nslabs", [
+    ("c2_small", None, "f64", 0),           # d = 6: m = 3, three pass groups
+    ("c4_small", None, "f32", 7),           # d = 8 in 7 slabs: four groups, multi-segment launches
+    ("c1", (9, 7, 8), "f64", 0),            # d = 3: right splits 1, 2; left split 2
+    ("c1", (6, 5, 7, 4, 5), "f64", 0),      # d = 5: m = 3, left splits 3, 4
+])
+def test_independent_drm_scheme(name, n, prec, nslabs):
+    """Per-split factors (the paper's Psi^(j)): every split's sketch, pivots, ranks and X~ vs the oracle."""
+    import dataclasses
+    w = inputs.WORKLOADS[name]
+    if n is not None:
+        w = dataclasses.replace(w, name="indep", index=70 + len(n), n=tuple(n))
+    say(f"[gpu] independent DRMs {w.name} n={w.n} prec={prec} slabs={nslabs}")
+    x = inputs.make_tensor(w)
+    psi, omega = inputs.drm_factors_independent(w)
+    fac = inputs.pack_factors_independent(psi, omega, w.d)
+    ref = oracle_run(x, w, psi, omega, drm="independent")
+    slabs = inputs.slab_bounds(x.size, w.n[0], nslabs) if nslabs else None
+    ctx, tt, xg = gpu_run(x, w, fac, prec, slabs=slabs, batched=bool(nslabs), drm="independent")
+    out = compare(ctx, tt, xg, x, w, ref, prec, check_cores=(prec == "f64"))
+    say(f"    {out}")
+    ctx.close()
+
+
 def test_twopass_middle_core():
     w = inputs.WORKLOADS["c2_small"]
     say("[gpu] two-pass middle core c2_small")
