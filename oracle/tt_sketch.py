@@ -25,14 +25,19 @@ PSTT2 (Section 3.2, end; equation "PSTT2_final_core"), m = ceil(d/2):
   * outer cores from neighbouring bases (equation "core" and its row mirror);
   * the middle core either from a second pass over X (two-pass PSTT2) or from
     the extra sketch Y_R = X_m Omega_m and a least-squares solve (PSTT2-onepass,
-    equation "onepass_final_core" applied to the middle unfolding).
+    equation "onepass_final_core" applied to the middle unfolding), or from
+    the same Y_R sketched once more on its leading modes and a pseudo-inverse
+    on each side ("twosided");
+  * the two-sided sketches B_k = Psi_k^T X_k Omega_k of every split.
 
 Parity pins (tests/test_oracle_*.py):
   unfold, khatri_rao, right/left sketches .... brute-force index loops, np.kron,
                                                the eq. sketch_orig block form, a
                                                rank-one closed form
   cpqr_basis ................................. LAPACK geqp3 invariants, pivots of R
-  pstt2 (both middle-core forms) ............. exact recovery of exact-rank TTs,
+  two_sided_sketch ........................... brute-force index loops, a rank-one
+                                               closed form, Psi_k^T S_k = T_k Omega_k
+  pstt2 (all middle-core forms) .............. exact recovery of exact-rank TTs,
                                                the deterministic projection bound
                                                (eq. proj_acc), Thm 3/4 expectation
                                                bounds by Monte Carlo
@@ -52,7 +57,8 @@ __all__ = [
     "middle_index", "rows_of", "cols_of", "unfold", "khatri_rao", "NestedKR", "IndependentKR",
     "DenseDRM", "sketch_right_dense", "sketch_left_dense", "sketch_right_modewise",
     "sketch_left_modewise", "cpqr_basis", "rank_from_tolerance", "outer_core_left",
-    "outer_core_right", "middle_core_twopass", "middle_core_onepass", "pstt2", "pstt",
+    "outer_core_right", "middle_core_twopass", "middle_core_onepass", "middle_core_twosided",
+    "two_sided_sketch", "pstt2", "pstt",
     "tt_full", "tt_entry", "tt_error", "tt_storage", "kmode_product", "tt_ranks",
 ]
 
@@ -161,6 +167,17 @@ def sketch_right_dense(x: np.ndarray, n: Sequence[int], k: int, omega_k: np.ndar
 def sketch_left_dense(x: np.ndarray, n: Sequence[int], k: int, psi_k: np.ndarray) -> np.ndarray:
     """T_k = Psi_k^T X_k: the row-space sketch "using X_j^T" (Section 4.2)."""
     return psi_k.T @ unfold(x, n, k)
+
+
+def two_sided_sketch(x: np.ndarray, n: Sequence[int], k: int, drm) -> np.ndarray:
+    """B_k = Psi_k^T X_k Omega_k (ell x ell): the split-k unfolding sketched from both sides.
+
+    Section 3.2 sketches X_k from the right (column space, Algorithm PSTT) and,
+    for PSTT2, from the left (row space); B_k applies both DRMs of split k at
+    once.  Written from the definition with the dense Khatri-Rao DRMs.
+    """
+    d = len(n)
+    return drm.psi_dense(k).T @ unfold(x, n, k) @ drm.omega_dense(k, d)
 
 
 def sketch_right_modewise(x: np.ndarray, n: Sequence[int], k: int, factors: Sequence[np.ndarray]) -> np.ndarray:
@@ -308,6 +325,29 @@ def middle_core_onepass(y_r: np.ndarray, omega_m: np.ndarray, q_prev: np.ndarray
     return np.reshape(g_t.T, (r_prev, n_m, r_m), order="F")
 
 
+def middle_core_twosided(y_r: np.ndarray, psi_prev: np.ndarray, q_prev: np.ndarray, omega_m: np.ndarray,
+                         p_m: np.ndarray, n_m: int) -> np.ndarray:
+    """Two-sided one-pass middle core (Section 3.2, PSTT2-onepass, with both outer modes sketched).
+
+    The middle core of equation "PSTT2_final_core" is X3 x_1 Q_{m-1}^T x_3 P_m^T
+    with X3 = reshape(X, R_{m-1}, n_m, C_m).  Sketch X3 on both outer modes,
+        H = X3 x_1 Psi'^T x_3 Omega_m^T   (ell x n_m x ell),
+    where Psi' = Psi_{m-1} (R_{m-1} x ell) and H is the leading-mode
+    contraction of Y_R = X_m Omega_m.  With X3 ~ G x_1 Q_{m-1} x_3 P_m,
+    H ~ G x_1 (Psi'^T Q_{m-1}) x_3 (Omega_m^T P_m), so
+        G = H x_1 (Psi'^T Q_{m-1})^+ x_3 (Omega_m^T P_m)^+,
+    the pseudo-inverse step of equation "onepass_final_core" taken on both
+    sides.
+    """
+    r_rows = q_prev.shape[0]
+    ell = y_r.shape[1]
+    y3 = np.reshape(y_r, (r_rows, n_m, ell), order="F")          # (row', i_m, c)
+    h = np.einsum("ra,rjc->ajc", psi_prev, y3)                   # (a, i_m, c)
+    a1 = psi_prev.T @ q_prev                                     # ell x r_{m-1}
+    a3 = omega_m.T @ p_m                                         # ell x r_m
+    return np.einsum("pa,ajc,qc->pjq", np.linalg.pinv(a1), h, np.linalg.pinv(a3))
+
+
 # ----------------------------------------------------------------------------
 # The driver
 # ----------------------------------------------------------------------------
@@ -340,7 +380,7 @@ def pstt2(x: np.ndarray, n: Sequence[int], drm, ranks: Optional[Sequence[int]] =
 
     s_sk = {k: _right_sketch(x, n, k, drm, dense_limit) for k in range(1, m)}
     t_sk = {k: _left_sketch(x, n, k, drm, dense_limit) for k in range(m, d)}
-    y_r = _right_sketch(x, n, m, drm, dense_limit) if middle == "onepass" else None
+    y_r = _right_sketch(x, n, m, drm, dense_limit) if middle in ("onepass", "twosided") else None
 
     if ranks is None:
         if eps is None:
@@ -374,9 +414,13 @@ def pstt2(x: np.ndarray, n: Sequence[int], drm, ranks: Optional[Sequence[int]] =
             cores[d - 1] = np.reshape(p[d - 1].T, (r[d - 1], n[d - 1], 1), order="F")
         else:
             cores[k - 1] = outer_core_right(p[k - 1], p[k], n[k - 1])
-    if middle == "onepass":
+    if middle == "onepass" or (middle == "twosided" and m == 1):
         om = drm.omega_dense(m, d) if not isinstance(drm, DenseDRM) else drm.omega[m]
         cores[m - 1] = middle_core_onepass(y_r, om, q[m - 1], p[m], n[m - 1])
+    elif middle == "twosided":
+        # d >= 3: Psi' is split (m-1)'s left DRM, drawn independently of Q_{m-1}
+        om = drm.omega_dense(m, d) if not isinstance(drm, DenseDRM) else drm.omega[m]
+        cores[m - 1] = middle_core_twosided(y_r, drm.psi_dense(m - 1), q[m - 1], om, p[m], n[m - 1])
     elif middle == "twopass":
         cores[m - 1] = middle_core_twopass(x, n, q[m - 1], p[m], m)
     else:

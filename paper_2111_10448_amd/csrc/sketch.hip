@@ -9,15 +9,16 @@
 // (equation "sketch_orig"): Omega_m(j, c) = prod_{q>m} omega_q(j_q, c),
 // Psi_m(i, a) = prod_{q<=m} psi_q(i_q, a).
 //
-// Work decomposition (one workgroup = 8 waves of 64 lanes):
-//   * a workgroup owns a block of 8*RW consecutive rows and a contiguous share of
+// Work decomposition (one workgroup = 4 waves of 64 lanes, two workgroups per
+// compute unit):
+//   * a workgroup owns a block of 4*RW consecutive rows and a contiguous share of
 //     the launch's 16-column chunks; each wave owns RW of the rows;
 //   * per chunk a wave loads its RW x 16 tile with 16-byte coalesced loads,
 //     stages it in a wave-private LDS tile, and runs matrix-core (MFMA) tiles
 //       right sketch: Y(rows, ell) += X(rows, 16 cols) * Omega(16 cols, ell)
 //       left sketch : T(ell, 16 cols) = Psi(rows, ell)^T * X(rows, 16 cols);
 //   * Y accumulates in registers over the workgroup's whole column share and is
-//     written once as a partial; T of the 8 waves is summed through LDS and
+//     written once as a partial; T of the 4 waves is summed through LDS and
 //     written per chunk as a partial (one per row block);
 //   * Psi rows are stationary (computed once per workgroup from the factors);
 //     Omega rows of a chunk are built cooperatively into LDS two chunks ahead.
@@ -34,7 +35,6 @@ typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 
-constexpr int NW = 8;   // waves per workgroup
 constexpr int KC = 16;  // columns per chunk
 
 // Round-to-nearest-even FP32 -> BF16 (bit pattern in the low 16 bits).

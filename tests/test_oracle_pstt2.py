@@ -68,7 +68,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("n,rank,ell", CASES)
-@pytest.mark.parametrize("middle", ["onepass", "twopass"])
+@pytest.mark.parametrize("middle", ["onepass", "twosided", "twopass"])
 @pytest.mark.parametrize("scheme", ["nested", "independent", "dense"])
 def test_exact_recovery(n, rank, ell, middle, scheme):
     x, cores = _exact_tt(n, rank, 100 + len(n))
