@@ -72,8 +72,13 @@ typedef enum { PSTT2_P_F64 = 0, PSTT2_P_F32 = 1, PSTT2_P_BF16 = 2, PSTT2_P_BF16X
 /* Middle-core rule.  ONEPASS: least squares from the extra right sketch of the
  * middle unfolding (PSTT2-onepass).  TWOPASS: second stream over X,
  * G_m = reshape(X, R_{m-1}, n_m, C_m) x_1 Q_{m-1}^T x_3 P_m^T
- * (equation "PSTT2_final_core"); see pstt2_middle_pass. */
-typedef enum { PSTT2_MID_ONEPASS = 0, PSTT2_MID_TWOPASS = 1 } pstt2_mid;
+ * (equation "PSTT2_final_core"); see pstt2_middle_pass.  TWOSIDED: still one
+ * pass; Y_R is sketched once more on its leading m-1 modes with split (m-1)'s
+ * left DRM Psi' (R_{m-1} x ell), H = reshape(Y_R) x_1 Psi'^T (ell x n_m x ell),
+ * and G_m = H x_1 (Psi'^T Q_{m-1})^+ x_3 (Omega_m^T P_m)^+: the pseudo-inverse
+ * step of equation "onepass_final_core" taken on both outer modes.  For d = 2
+ * (m = 1) TWOSIDED is ONEPASS. */
+typedef enum { PSTT2_MID_ONEPASS = 0, PSTT2_MID_TWOPASS = 1, PSTT2_MID_TWOSIDED = 2 } pstt2_mid;
 
 /* Khatri-Rao DRM scheme (Section 3.2, equation "sketch_orig").
  *   NESTED       one Gaussian factor per mode, shared by every split: the
@@ -139,7 +144,9 @@ pstt2_status pstt2_sketch_slabs(pstt2_ctx* ctx, int32_t nslabs, const void* cons
                                 const int64_t* firsts, const int64_t* counts);
 
 /* Recover the TT cores from the accumulated sketches: derive every split's
- * sketch, bases by TSQR + column-pivoted QR of the small R factor (sign fixed
+ * sketch and its two-sided sketch B_k = Psi_k^T X_k Omega_k (ell x ell; as
+ * Psi_k^T S_k for k < m and T_k Omega_k for k >= m, FP64 DRM entries), bases
+ * by TSQR + column-pivoted QR of the small R factor (sign fixed
  * so that diag(R) >= 0), outer cores, middle core.  In tolerance mode the
  * ranks follow the rule sum_{i>r} sigma_i(S_k)^2 <= eps^2/(d-1) ||S_k||_F^2
  * capped at rmax.  out->core[k] are library-allocated (out->owned = 1).  sync.
@@ -171,7 +178,8 @@ pstt2_status pstt2_middle_pass(pstt2_ctx* ctx, tt_cores* cores, const void* x_de
  *                     tensor that was sketched.
  * gx_dev is caller-owned device memory of N entries of the context's dtype.
  * Uses stream-ordered device workspace (about 8 N bytes).  sync.
- * Errors: ESTATE (no successful pstt2_recover, or two-pass middle core),
+ * Errors: ESTATE (no successful pstt2_recover; a two-pass or two-sided middle core;
+ *         the independent DRM scheme),
  * EINVAL (null pointers, cores not from this context), ENOMEM, EDEVICE. */
 pstt2_status pstt2_vjp(pstt2_ctx* ctx, const tt_cores* cores, const void* x_dev, const void* gbar_dev,
                        void* gx_dev);
@@ -179,6 +187,9 @@ pstt2_status pstt2_vjp(pstt2_ctx* ctx, const tt_cores* cores, const void* x_dev,
 /* Copy an accumulated or derived sketch to host memory (FP64, column-major).
  * which = 0: the right sketch of split k (1 <= k <= m; k = m is Y_R), R_k x ell.
  * which = 1: the transposed left sketch T_k^T of split k (m <= k <= d-1), C_k x ell.
+ * which = 2: the two-sided sketch B_k = Psi_k^T X_k Omega_k (1 <= k <= d-1), ell x ell.
+ * which = 3: the two-sided middle sketch H (PSTT2_MID_TWOSIDED, d >= 3; k ignored),
+ *            (ell n_m) x ell, row a + ell i_m.
  * Valid after pstt2_recover.  *rows and *cols receive the shape; host_out must hold
  * rows*cols doubles (pass host_out = NULL to query the shape).  sync. */
 pstt2_status pstt2_get_sketch(pstt2_ctx* ctx, int32_t which, int32_t k, double* host_out, int64_t* rows,

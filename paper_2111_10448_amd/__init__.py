@@ -240,7 +240,9 @@ class PSTT2:
         return gx
 
     def get_sketch(self, which: int, k: int) -> np.ndarray:
-        """which = 0: right sketch of split k (R_k x ell); 1: transposed left sketch (C_k x ell)."""
+        """which = 0: right sketch of split k (R_k x ell); 1: transposed left sketch (C_k x ell);
+        2: two-sided sketch B_k = Psi_k^T X_k Omega_k (ell x ell); 3: two-sided middle sketch H
+        ((ell n_m) x ell, mid="twosided")."""
         rows = ctypes.c_int64()
         cols = ctypes.c_int64()
         L.check(L.lib().pstt2_get_sketch(self._c(), which, k, None, ctypes.byref(rows), ctypes.byref(cols)),

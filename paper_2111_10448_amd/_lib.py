@@ -19,7 +19,7 @@ OK, EINVAL, ESHAPE, ENOMEM, EDEVICE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENUMERIC", -6: "ESTATE"}
 F64, F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
-MID = {"onepass": 0, "twopass": 1}
+MID = {"onepass": 0, "twopass": 1, "twosided": 2}
 DRM = {"nested": 0, "independent": 1}
 
 

@@ -42,6 +42,8 @@ struct pstt2_ctx {
   std::vector<double*> S;      // S[k], k = 1..m-1, R_k x ell (S[m] aliases Y)
   std::vector<double*> Tk;     // Tk[k], k = m+1..d-1, C_k x ell (Tk[m] aliases Tt)
   std::vector<double*> basis;  // Q_k (k < m) or P_k (k >= m)
+  double* Bk = nullptr;        // two-sided sketches, split k at Bk + k ell^2 (ell x ell)
+  double* H = nullptr;         // two-sided middle sketch, (ell n_m) x ell (TWOSIDED only)
   int ranks[PSTT2_MAX_D + 1] = {};
   bool recovered = false;
   double* one = nullptr;       // device scalar 1.0 (Q_0 when m == 1)
@@ -99,10 +101,34 @@ void free_recovery(pstt2_ctx* c) {
     if (c->Tk[k] && c->Tk[k] != c->Tt) (void)hipFreeAsync(c->Tk[k], c->stream);
   for (auto p : c->basis)
     if (p) (void)hipFreeAsync(p, c->stream);
+  if (c->H) (void)hipFreeAsync(c->H, c->stream);
+  c->H = nullptr;
   c->S.assign(c->d + 1, nullptr);
   c->Tk.assign(c->d + 1, nullptr);
   c->basis.assign(c->d + 1, nullptr);
   c->recovered = false;
+}
+
+// Split k's left DRM Psi_k (modes 1..k) and right DRM Omega_k (modes k+1..d)
+// as chains of factors in the context's factor buffer
+KRChain left_chain(const pstt2_ctx* c, int k) {
+  KRChain ch;
+  std::memset(&ch, 0, sizeof(ch));
+  for (int q = 1; q <= k; ++q) {
+    ch.n[ch.cnt] = (int32_t)c->n[q - 1];
+    ch.off[ch.cnt++] = c->indep ? c->ipsi_off[k][q - 1] : c->psi_off[q - 1];
+  }
+  return ch;
+}
+
+KRChain right_chain(const pstt2_ctx* c, int k) {
+  KRChain ch;
+  std::memset(&ch, 0, sizeof(ch));
+  for (int q = k + 1; q <= c->d; ++q) {
+    ch.n[ch.cnt] = (int32_t)c->n[q - 1];
+    ch.off[ch.cnt++] = c->indep ? c->iom_off[k][q - 1] : c->omega_off[q - 1];
+  }
+  return ch;
 }
 
 SketchArgs base_args(const pstt2_ctx* c) {
@@ -300,7 +326,8 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
     return fail(nullptr, PSTT2_EINVAL, "FP64 tensors use PSTT2_P_F64 arithmetic");
   if (desc->dtype == PSTT2_F32 && desc->prec == PSTT2_P_F64)
     return fail(nullptr, PSTT2_EINVAL, "FP32 tensors use PSTT2_P_F32, PSTT2_P_BF16 or PSTT2_P_BF16X3");
-  if (desc->mid != PSTT2_MID_ONEPASS && desc->mid != PSTT2_MID_TWOPASS) return fail(nullptr, PSTT2_EINVAL, "bad mid");
+  if (desc->mid != PSTT2_MID_ONEPASS && desc->mid != PSTT2_MID_TWOPASS && desc->mid != PSTT2_MID_TWOSIDED)
+    return fail(nullptr, PSTT2_EINVAL, "bad mid");
   if (!desc->drm_factors) return fail(nullptr, PSTT2_EINVAL, "drm_factors is required");
   if (desc->drm != PSTT2_DRM_NESTED && desc->drm != PSTT2_DRM_INDEPENDENT) return fail(nullptr, PSTT2_EINVAL, "bad drm");
   const bool tol = desc->ranks[0] <= 0;
@@ -388,6 +415,7 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
     }
   }
   if ((e = hipMalloc(&c->one, sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(one)");
+  if ((e = hipMalloc(&c->Bk, sizeof(double) * (d + 1) * c->ell * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Bk)");
   const double one = 1.0;
   if ((e = hipMemcpy(c->one, &one, sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "hipMemcpy");
   int rows_per_block = 0, threads = 0, wg_per_cu = 1;
@@ -489,6 +517,7 @@ void pstt2_destroy(pstt2_ctx* c) {
   (void)hipFree(c->flag);
   (void)hipFree(c->piv_dev);
   (void)hipFree(c->one);
+  (void)hipFree(c->Bk);
   (void)hipFree(c->om_tab);
   for (double* p : c->iom_tab) (void)hipFree(p);
   for (double* p : c->iY) (void)hipFree(p);
@@ -582,6 +611,29 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
       }
       c->Tk[k] = (double*)cur;
     }
+  }
+  // two-sided sketches: B_k = Psi_k^T S_k (k < m), B_k = T_k Omega_k (k >= m)
+  {
+    int64_t kmax = 0;
+    for (int k = 1; k <= d - 1; ++k) kmax = std::max(kmax, k < m ? c->Rk[k] : c->N / c->Rk[k]);
+    double* tab = nullptr;
+    HIPCK(c, hipMallocAsync((void**)&tab, sizeof(double) * kmax * ell, s));
+    hipError_t e = hipSuccess;
+    for (int k = 1; k <= d - 1 && e == hipSuccess; ++k) {
+      double* Bk = c->Bk + (int64_t)k * ell * ell;
+      if (k < m) {
+        e = kr_table(c->fac, left_chain(c, k), c->Rk[k], ell, tab, s);
+        if (e == hipSuccess)
+          e = adj_gemm(true, false, ell, ell, c->Rk[k], 1.0, tab, c->Rk[k], c->S[k], c->Rk[k], 0.0, Bk, ell, s);
+      } else {
+        const int64_t Ck = c->N / c->Rk[k];
+        e = kr_table(c->fac, right_chain(c, k), Ck, ell, tab, s);
+        // Tk[k] holds T_k^T (C_k x ell)
+        if (e == hipSuccess) e = adj_gemm(true, false, ell, ell, Ck, 1.0, c->Tk[k], Ck, tab, Ck, 0.0, Bk, ell, s);
+      }
+    }
+    (void)hipFreeAsync(tab, s);
+    if (e != hipSuccess) return hfail(c, e, "two-sided sketches");
   }
   // (2) factor every sketch (one batched TSQR over all splits); the ranks come
   // from the descriptor or, in tolerance mode, from the singular values (one
@@ -695,11 +747,37 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   const double* Qprev = m >= 2 ? c->basis[m - 1] : c->one;
   const int64_t Rprev = c->Rk[m - 1];
   const int64_t nz = (int64_t)r[m - 1] * c->n[m - 1];
-  if (c->desc.mid == PSTT2_MID_ONEPASS) {
+  if (c->desc.mid == PSTT2_MID_ONEPASS || c->desc.mid == PSTT2_MID_TWOSIDED) {
     double *Z = nullptr, *A = nullptr;
+    const int nm = (int)c->n[m - 1];
     e = hipMallocAsync((void**)&Z, sizeof(double) * nz * ell, s);
     if (e == hipSuccess) e = hipMallocAsync((void**)&A, sizeof(double) * r[m] * ell, s);
-    if (e == hipSuccess) e = middle_z(Qprev, Rprev, r[m - 1], c->Y, c->R, (int)c->n[m - 1], ell, Z, s);
+    if (c->desc.mid == PSTT2_MID_ONEPASS || m == 1) {
+      // Z = (I (x) Q_{m-1})^T Y_R
+      if (e == hipSuccess) e = middle_z(Qprev, Rprev, r[m - 1], c->Y, c->R, nm, ell, Z, s);
+    } else {
+      // H = (I (x) Psi')^T Y_R with Psi' split (m-1)'s left DRM; then
+      // Z = (I (x) M1) H with M1 = (Psi'^T Q_{m-1})^+ = (A1^T A1)^{-1} A1^T,
+      // A1 = Psi'^T Q_{m-1} (ell x r_{m-1}).  The least-squares kernel with
+      // right-hand side I_ell and system matrix A1^T returns M1^T.
+      const int rp = r[m - 1];
+      double *ptab = nullptr, *a1t = nullptr, *id = nullptr, *m1t = nullptr;
+      if (e == hipSuccess) e = hipMallocAsync((void**)&c->H, sizeof(double) * ell * nm * ell, s);
+      if (e == hipSuccess) e = hipMallocAsync((void**)&ptab, sizeof(double) * Rprev * ell, s);
+      if (e == hipSuccess) e = hipMallocAsync((void**)&a1t, sizeof(double) * rp * ell, s);
+      if (e == hipSuccess) e = hipMallocAsync((void**)&id, sizeof(double) * ell * ell, s);
+      if (e == hipSuccess) e = hipMallocAsync((void**)&m1t, sizeof(double) * ell * rp, s);
+      if (e == hipSuccess) e = kr_table(c->fac, left_chain(c, m - 1), Rprev, ell, ptab, s);
+      if (e == hipSuccess) e = middle_z(ptab, Rprev, ell, c->Y, c->R, nm, ell, c->H, s);
+      if (e == hipSuccess) e = adj_gemm(true, false, rp, ell, Rprev, 1.0, Qprev, Rprev, ptab, Rprev, 0.0, a1t, rp, s);
+      if (e == hipSuccess) e = eye(ell, id, s);
+      if (e == hipSuccess) e = middle_ls(id, ell, a1t, rp, ell, m1t, c->flag, s);
+      if (e == hipSuccess) e = middle_z(m1t, ell, rp, c->H, (int64_t)ell * nm, nm, ell, Z, s);
+      (void)hipFreeAsync(ptab, s);
+      (void)hipFreeAsync(a1t, s);
+      (void)hipFreeAsync(id, s);
+      (void)hipFreeAsync(m1t, s);
+    }
     SketchArgs geo = base_args(c);
     if (e == hipSuccess) e = middle_a(c->basis[m], c->C, r[m], geo, c->prec, A, s);
     if (e == hipSuccess) e = middle_ls(Z, nz, A, r[m], ell, tc.core[m - 1], c->flag, s);
@@ -933,6 +1011,12 @@ pstt2_status pstt2_get_sketch(pstt2_ctx* c, int32_t which, int32_t k, double* ho
   } else if (which == 1 && k >= c->m && k <= c->d - 1) {
     p = c->Tk[k];
     *rows = c->N / c->Rk[k];
+  } else if (which == 2 && k >= 1 && k <= c->d - 1) {
+    p = c->Bk + (int64_t)k * c->ell * c->ell;
+    *rows = c->ell;
+  } else if (which == 3 && c->H) {
+    p = c->H;
+    *rows = (int64_t)c->ell * c->n[c->m - 1];
   } else {
     return fail(c, PSTT2_EINVAL, "no such sketch");
   }

@@ -89,6 +89,19 @@ hipError_t middle_a(const double* Pm, int64_t Cm, int rm, const SketchArgs& geo,
                     hipStream_t s);
 hipError_t middle_ls(const double* Z, int64_t nz, const double* A, int rm, int ell, double* G, int* flag,
                      hipStream_t s);
+// Khatri-Rao DRM over a run of consecutive modes: entry (row, u) is the product
+// of f_q(i_q, u) over the chain's modes, with row = i_1 + n_1 (i_2 + n_2 (...))
+// (first listed mode fastest); factor f_q sits at fac + off[q], n[q] x ell,
+// ell fastest.
+struct KRChain {
+  int32_t cnt;
+  int32_t n[PSTT2_MAX_D];
+  int64_t off[PSTT2_MAX_D];
+};
+// out (rows x ell, column-major) = the chain's DRM; rows = prod n[q]
+hipError_t kr_table(const double* fac, const KRChain& ch, int64_t rows, int ell, double* out, hipStream_t s);
+// out (k x k) = identity
+hipError_t eye(int k, double* out, hipStream_t s);
 hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count, int64_t Rprev, int nm,
                           int64_t Cm, const double* Qprev, int rprev, const double* Pm, int rm, double* G,
                           hipStream_t s);

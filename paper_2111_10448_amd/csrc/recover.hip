@@ -415,77 +415,93 @@ struct SvBatch {
   double* sv[MAXB];
 };
 
-__global__ __launch_bounds__(512) void k_jacobi_sv(const SvBatch B, int ell) {
+// One-sided (Hestenes) Jacobi on the ell x ell R factor, one wavefront per
+// problem: a round rotates E/2 disjoint column pairs (round-robin ordering,
+// E = ell rounded up to even), four lanes per pair with eight rows each, so a
+// round is a few LDS accesses, two shuffle steps and one rotation per lane.
+// Sweeps end when no pair needed a rotation; the singular values are the
+// final column norms, sorted in decreasing order.
+__global__ __launch_bounds__(64) void k_jacobi_sv(const SvBatch B, int ell) {
   const double* __restrict__ R = B.R[blockIdx.x];
   const int64_t ldr = B.ldr[blockIdx.x];
   double* __restrict__ sv = B.sv[blockIdx.x];
-  __shared__ double U[PSTT2_MAX_ELL][PSTT2_MAX_ELL + 1];  // [col][row]
-  __shared__ int rotated;
+  constexpr int MX = PSTT2_MAX_ELL;
+  __shared__ double U[MX][MX + 1];  // [col][row], zero outside ell x ell
   const int t = threadIdx.x;
-  const int half = t >> 5, li = t & 31;
-  for (int i = t; i < ell * ell; i += blockDim.x) U[i / ell][i % ell] = R[(int64_t)(i / ell) * ldr + i % ell];
+  for (int i = t; i < MX * MX; i += 64) {
+    const int c = i / MX, r = i % MX;
+    U[c][r] = (c < ell && r < ell) ? R[(int64_t)c * ldr + r] : 0.0;
+  }
+  __syncthreads();
   const int E = (ell + 1) & ~1;
+  const int pr = t >> 2, r0 = (t & 3) * 8;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (t == 0) rotated = 0;
-    __syncthreads();
+    int rot = 0;
     for (int rnd = 0; rnd < E - 1; ++rnd) {
-      if (half < E / 2) {
-        int p, q;
-        if (half == 0) {
+      int p = -1, q = -1;
+      if (pr < E / 2) {
+        if (pr == 0) {
           p = E - 1;
           q = rnd;
         } else {
-          p = (rnd + half) % (E - 1);
-          q = (rnd - half + (E - 1)) % (E - 1);
+          p = (rnd + pr) % (E - 1);
+          q = (rnd - pr + (E - 1)) % (E - 1);
         }
         if (p > q) {
           const int tmp = p;
           p = q;
           q = tmp;
         }
-        if (q < ell) {
-          const double up = li < ell ? U[p][li] : 0.0, uq = li < ell ? U[q][li] : 0.0;
-          double app = up * up, aqq = uq * uq, apq = up * uq;
-          for (int o = 16; o > 0; o >>= 1) {
-            app += __shfl_xor(app, o, 32);
-            aqq += __shfl_xor(aqq, o, 32);
-            apq += __shfl_xor(apq, o, 32);
-          }
-          if (fabs(apq) > 1e-15 * sqrt(app * aqq) && apq != 0.0) {
-            const double zeta = (aqq - app) / (2.0 * apq);
-            const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + tt * tt);
-            const double sn = cs * tt;
-            if (li < ell) {
-              U[p][li] = cs * up - sn * uq;
-              U[q][li] = sn * up + cs * uq;
-            }
-            if (li == 0) rotated = 1;
-          }
+      }
+      const bool act = q >= 0 && q < ell;
+      double up[8], uq[8];
+      double app = 0.0, aqq = 0.0, apq = 0.0;
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          up[i] = U[p][r0 + i];
+          uq[i] = U[q][r0 + i];
+          app += up[i] * up[i];
+          aqq += uq[i] * uq[i];
+          apq += up[i] * uq[i];
         }
+      }
+      // the four lanes of a pair are adjacent: two xor steps finish the sums
+      for (int o = 1; o <= 2; o <<= 1) {
+        app += __shfl_xor(app, o);
+        aqq += __shfl_xor(aqq, o);
+        apq += __shfl_xor(apq, o);
+      }
+      if (act && fabs(apq) > 1e-15 * sqrt(app * aqq) && apq != 0.0) {
+        const double zeta = (aqq - app) / (2.0 * apq);
+        const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt);
+        const double sn = cs * tt;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          U[p][r0 + i] = cs * up[i] - sn * uq[i];
+          U[q][r0 + i] = sn * up[i] + cs * uq[i];
+        }
+        rot = 1;
       }
       __syncthreads();
     }
-    if (!rotated) break;
-    __syncthreads();
+    if (!__any(rot)) break;
   }
-  if (t == 0) {
-    double s[PSTT2_MAX_ELL];
-    for (int c = 0; c < ell; ++c) {
-      double v = 0.0;
-      for (int i = 0; i < ell; ++i) v += U[c][i] * U[c][i];
-      s[c] = sqrt(v);
-    }
-    for (int i = 1; i < ell; ++i) {
-      const double v = s[i];
-      int j = i - 1;
-      while (j >= 0 && s[j] < v) {
-        s[j + 1] = s[j];
-        --j;
-      }
-      s[j + 1] = v;
-    }
-    for (int c = 0; c < ell; ++c) sv[c] = s[c];
+  // lane c < ell holds column c's norm; its place in decreasing order (ties
+  // by column index) is the number of columns ranked before it
+  __shared__ double nrm[MX];
+  if (t < ell) {
+    double v = 0.0;
+    for (int i = 0; i < ell; ++i) v += U[t][i] * U[t][i];
+    nrm[t] = sqrt(v);
+  }
+  __syncthreads();
+  if (t < ell) {
+    const double v = nrm[t];
+    int pos = 0;
+    for (int c = 0; c < ell; ++c) pos += (nrm[c] > v || (nrm[c] == v && c < t)) ? 1 : 0;
+    sv[pos] = v;
   }
 }
 
@@ -618,7 +634,7 @@ hipError_t basis_factor_batch(int n, const double* const* A, const int64_t* M, i
   else hipLaunchKernelGGL((k_cpqr<32>), dim3(n), dim3(64), 0, s, C, ell);
   HCK(hipGetLastError());
   if (want_sv) {
-    hipLaunchKernelGGL(k_jacobi_sv, dim3(n), dim3(512), 0, s, S, ell);
+    hipLaunchKernelGGL(k_jacobi_sv, dim3(n), dim3(64), 0, s, S, ell);
     HCK(hipGetLastError());
   }
   return hipSuccess;
@@ -785,6 +801,37 @@ hipError_t middle_z(const double* Qprev, int64_t Rprev, int rprev, const double*
   return hipGetLastError();
 }
 
+__global__ void k_kr_table(const double* __restrict__ fac, const KRChain ch, int64_t rows, int ell,
+                           double* __restrict__ out) {
+  const int64_t tot = rows * ell;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+    const int u = (int)(t / rows);
+    int64_t row = t % rows;
+    double f = 1.0;
+    for (int q = 0; q < ch.cnt; ++q) {
+      const int64_t i = row % ch.n[q];
+      row /= ch.n[q];
+      f *= fac[ch.off[q] + i * ell + u];
+    }
+    out[t] = f;
+  }
+}
+
+hipError_t kr_table(const double* fac, const KRChain& ch, int64_t rows, int ell, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_kr_table, dim3(grid_for(rows * ell, 256)), dim3(256), 0, s, fac, ch, rows, ell, out);
+  return hipGetLastError();
+}
+
+__global__ void k_eye(int k, double* __restrict__ out) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < k * k; t += gridDim.x * blockDim.x)
+    out[t] = (t % k == t / k) ? 1.0 : 0.0;
+}
+
+hipError_t eye(int k, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_eye, dim3(1), dim3(256), 0, s, k, out);
+  return hipGetLastError();
+}
+
 // The value of a DRM entry as the sketch kernel used it: the FP64 product of
 // factors rounded to the sketch arithmetic (FP32 for FP32 and split BF16, or
 // BF16).  The
@@ -922,14 +969,13 @@ __global__ __launch_bounds__(256) void k_middle_ls(const double* __restrict__ Z,
     Bm[c][b] = sum;
   }
   __syncthreads();
-  for (int64_t rho = t; rho < nz; rho += blockDim.x) {
-    double z[MX];
-    for (int c = 0; c < ell; ++c) z[c] = Z[(int64_t)c * nz + rho];
-    for (int b = 0; b < rm; ++b) {
-      double sum = 0.0;
-      for (int c = 0; c < ell; ++c) sum += z[c] * Bm[c][b];
-      G[(int64_t)b * nz + rho] = sum;
-    }
+  // G(rho, b) = sum_c Z(rho, c) Bm(c, b): consecutive threads take consecutive rows
+  for (int64_t o = t; o < nz * rm; o += blockDim.x) {
+    const int64_t rho = o % nz;
+    const int b = (int)(o / nz);
+    double sum = 0.0;
+    for (int c = 0; c < ell; ++c) sum += Z[(int64_t)c * nz + rho] * Bm[c][b];
+    G[o] = sum;
   }
 }
 

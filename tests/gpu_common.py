@@ -35,8 +35,11 @@ def oracle_run(x, w, psi, omega, middle="onepass", drm="nested"):
     x64 = np.asarray(x, dtype=np.float64)
     drm = O.NestedKR(psi, omega) if drm == "nested" else O.IndependentKR(psi, omega)
     if w.rank is not None:
-        return O.pstt2(x64, w.n, drm, ranks=w.ranks(), middle=middle)
-    return O.pstt2(x64, w.n, drm, eps=w.eps, rmax=w.rmax, middle=middle)
+        ref = O.pstt2(x64, w.n, drm, ranks=w.ranks(), middle=middle)
+    else:
+        ref = O.pstt2(x64, w.n, drm, eps=w.eps, rmax=w.rmax, middle=middle)
+    ref["drm"] = drm
+    return ref
 
 
 def gpu_run(x, w, fac, prec, slabs=None, middle="onepass", batched=False, ranks=None, drm="nested"):
@@ -89,6 +92,12 @@ def compare(ctx, tt, xg, x, w, ref, prec, check_pivots=True, check_cores=False):
         t = ctx.get_sketch(1, k)
         out[f"T{k}"] = rel(t, ref["T"][k].T)
         assert out[f"T{k}"] < tol_sk, (f"T_{k}", out[f"T{k}"])
+    # two-sided sketches B_k = Psi_k^T X_k Omega_k, from their definition
+    x64 = np.asarray(x, dtype=np.float64)
+    for k in range(1, d):
+        b = ctx.get_sketch(2, k)
+        out[f"B{k}"] = rel(b, O.two_sided_sketch(x64, w.n, k, ref["drm"]))
+        assert out[f"B{k}"] < tol_sk, (f"B_{k}", out[f"B{k}"])
     # ranks
     assert tt.ranks == [1] + list(ref["ranks"]) + [1], (tt.ranks, ref["ranks"])
     # pivots (the first r_k decide the basis)

@@ -33,6 +33,18 @@ def test_library_exports_every_symbol():
     assert b"gfx950" in lib.pstt2_version()
 
 
+def test_enums_match_header():
+    """Every enumerator the header defines has the same value in the binding's tables."""
+    from paper_2111_10448_amd import _lib as L
+    src = open(os.path.join(ROOT, "include", "pstt2.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    vals = {k: int(v) for k, v in re.findall(r"(PSTT2_\w+)\s*=\s*(-?\d+)", src)}
+    for table, prefix in ((L.MID, "PSTT2_MID_"), (L.DRM, "PSTT2_DRM_")):
+        names = {k[len(prefix):].lower(): v for k, v in vals.items() if k.startswith(prefix)}
+        assert names == table, (prefix, names, table)
+    assert vals["PSTT2_MID_TWOSIDED"] == 2
+
+
 def test_struct_layouts_match_header():
     """ctypes layouts mirror the C structs (natural alignment, x86-64)."""
     from paper_2111_10448_amd import _lib as L
@@ -48,6 +60,7 @@ def test_struct_layouts_match_header():
     ("ell", 0, "ell must be"),
     ("ell", 33, "ell must be"),
     ("dtype", 7, "bad dtype"),
+    ("mid", 3, "bad mid"),
 ])
 def test_create_rejects_bad_descriptors(field, value, msg):
     from paper_2111_10448_amd import _lib as L

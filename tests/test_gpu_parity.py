@@ -11,7 +11,7 @@ import pytest
 import inputs
 from oracle import tt_sketch as O
 
-from gpu_common import TOL_XT, compare, gpu_run, oracle_run, rel, say, setup
+from gpu_common import TOL_SK, TOL_XT, compare, gpu_run, oracle_run, rel, say, setup
 
 pytestmark = pytest.mark.gpu
 
@@ -83,6 +83,44 @@ def test_independent_drm_scheme(name, n, prec, nslabs):
     ref = oracle_run(x, w, psi, omega, drm="independent")
     slabs = inputs.slab_bounds(x.size, w.n[0], nslabs) if nslabs else None
     ctx, tt, xg = gpu_run(x, w, fac, prec, slabs=slabs, batched=bool(nslabs), drm="independent")
+    out = compare(ctx, tt, xg, x, w, ref, prec, check_cores=(prec == "f64"))
+    say(f"    {out}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,n,prec,drm", [
+    ("c2_small", None, "f64", "nested"),
+    ("c2_small", None, "f64", "independent"),
+    ("c3_small", None, "f32", "nested"),      # tolerance-mode ranks
+    ("c1", (6, 5, 7, 4, 5), "f64", "nested"),  # d = 5, m = 3
+    ("c1", (9, 7, 8), "f64", "independent"),   # d = 3, m = 2: Psi' is split 1's left DRM
+    ("c1", (37, 41), "f64", "nested"),         # d = 2: the rule is the one-pass rule
+])
+def test_twosided_middle_core(name, n, prec, drm):
+    """Middle core from the two-sided middle sketch H: H, cores / X~ and ranks vs the oracle."""
+    import dataclasses
+    w = inputs.WORKLOADS[name]
+    if n is not None:
+        w = dataclasses.replace(w, name="twosided", index=110 + len(n), n=tuple(n))
+    say(f"[gpu] two-sided middle core {w.name} n={w.n} prec={prec} drm={drm}")
+    x = inputs.make_tensor(w)
+    if drm == "nested":
+        psi, omega = inputs.drm_factors(w)
+        fac = inputs.pack_factors(psi, omega, w.d)
+    else:
+        psi, omega = inputs.drm_factors_independent(w)
+        fac = inputs.pack_factors_independent(psi, omega, w.d)
+    ref = oracle_run(x, w, psi, omega, middle="twosided", drm=drm)
+    ctx, tt, xg = gpu_run(x, w, fac, prec, middle="twosided", drm=drm)
+    m = O.middle_index(w.d)
+    if m >= 2:
+        h = ctx.get_sketch(3, 0)
+        rp = O.rows_of(w.n, m - 1)
+        y3 = np.reshape(ref["Y"], (rp, w.n[m - 1], w.ell), order="F")
+        h_ref = np.einsum("ra,rjc->ajc", ref["drm"].psi_dense(m - 1), y3).reshape(-1, w.ell, order="F")
+        e_h = rel(h, h_ref)
+        say(f"    H rel {e_h:.2e}")
+        assert e_h < TOL_SK[prec]
     out = compare(ctx, tt, xg, x, w, ref, prec, check_cores=(prec == "f64"))
     say(f"    {out}")
     ctx.close()
