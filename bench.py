@@ -101,7 +101,7 @@ def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 30.0):
 _HOST = {}
 
 
-def run_workload(name, prec, steps, warmup, ranks_from=None):
+def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass"):
     import torch
     import inputs
     import paper_2111_10448_amd as P
@@ -119,7 +119,7 @@ def run_workload(name, prec, steps, warmup, ranks_from=None):
     log(f"[bench] {name} {prec}: timing {steps} steps")
     xg = torch.from_numpy(x).to("cuda:0")
     torch.cuda.synchronize()
-    kw = dict(dtype=w.dtype, prec=prec)
+    kw = dict(dtype=w.dtype, prec=prec, mid=mid)
     if ranks_from is not None:
         kw["ranks"] = ranks_from
     elif w.rank is not None:
@@ -226,8 +226,8 @@ def main():
     ap.add_argument("--prec", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the precision study (1/sum tensor in FP64, FP32, split BF16, BF16), the "
-                         "64-slab stream and the adjoint")
+                    help="skip the two-sided middle core, the precision study (1/sum tensor in FP64, FP32, "
+                         "split BF16, BF16), the 64-slab stream and the adjoint")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a 2 GiB device copy (counter calibration under rocprofv3) and exit")
     args = ap.parse_args()
@@ -279,19 +279,20 @@ def main():
     }
     if not args.no_variants:
         var = {}
-        for wn, vp in (("c3_f64", "f64"), ("c3", "f32"), ("c3", "bf16x3"), ("c3", "bf16"), ("c4", "f32"),
-                       ("c4", "bf16x3")):
+        for wn, vp, mid in (("c2", "f64", "twosided"), ("c3_f64", "f64", "onepass"), ("c3", "f32", "onepass"),
+                            ("c3", "bf16x3", "onepass"), ("c3", "bf16", "onepass"), ("c4", "f32", "onepass"),
+                            ("c4", "bf16x3", "onepass")):
+            key = f"{wn}_{vp}" if mid == "onepass" else f"{wn}_{vp}_{mid}"
             try:
-                rv = run_workload(wn, vp, max(3, args.steps // 2), 1)
-                wv = rv["workload"]
+                rv = run_workload(wn, vp, max(3, args.steps // 2), 1, mid=mid)
                 kbv = rv["bytes"] / max(rv["launches_per_step"], 1)
-                var[f"{wn}_{vp}"] = {"workload": wn, "sketch_arithmetic": vp,
+                var[key] = {"workload": wn, "sketch_arithmetic": vp, "middle_core": mid,
                            "sketch_kernel_ms": round(rv["kernel_ms"], 4),
                            "sketch_gbs": round(kbv / (rv["kernel_ms"] * 1e-3) / 1e9, 2),
                            "ms_per_step": round(rv["ms_per_step"], 4), "ranks": rv["ranks"],
                            "tt_rel_error": rv["err"]}
             except Exception as e:   # report, keep the headline line
-                var[f"{wn}_{vp}"] = {"error": str(e)}
+                var[key] = {"error": str(e)}
         record["variants"] = var
         try:
             record["adjoint"] = run_adjoint(max(3, args.steps // 2), 1)

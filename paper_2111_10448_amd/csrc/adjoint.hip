@@ -75,10 +75,85 @@ __global__ __launch_bounds__(256) void k_gemm_w(bool ta, bool tb, int64_t M, int
   }
 }
 
+// C = A^T B for tall, narrow A (K x M) and B (K x N), M, N <= 32, in two
+// steps: workgroup g stages rows [g TN_ROWS, (g+1) TN_ROWS) of both operands in
+// LDS, 64 rows at a time, and writes the partial product of its slice; a
+// wavefront per entry of C then adds the slices' partials in slice order with a
+// fixed butterfly (deterministic for any K).
+constexpr int TN_ROWS = 128;
+constexpr int TN_SUB = 64;
+
+__global__ __launch_bounds__(256) void k_gemm_tn_part(int M, int N, int64_t K, const double* __restrict__ A,
+                                                      int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                                      double* __restrict__ part) {
+  __shared__ double As[TN_SUB][33];
+  __shared__ double Bs[TN_SUB][33];
+  const int t = threadIdx.x;
+  const int nout = M * N;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = (int64_t)blockIdx.x * TN_ROWS;
+  const int64_t r1 = std::min<int64_t>(K, r0 + TN_ROWS);
+  for (int64_t k0 = r0; k0 < r1; k0 += TN_SUB) {
+    const int nr = (int)std::min<int64_t>(TN_SUB, r1 - k0);
+    for (int e = t; e < TN_SUB * M; e += 256) {
+      const int r = e % TN_SUB, c = e / TN_SUB;
+      As[r][c] = r < nr ? A[k0 + r + lda * c] : 0.0;
+    }
+    for (int e = t; e < TN_SUB * N; e += 256) {
+      const int r = e % TN_SUB, c = e / TN_SUB;
+      Bs[r][c] = r < nr ? B[k0 + r + ldb * c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = t + 256 * q;
+      if (o < nout) {
+        const int i = o % M, j = o / M;
+        double sacc = acc[q];
+        for (int r = 0; r < TN_SUB; ++r) sacc += As[r][i] * Bs[r][j];
+        acc[q] = sacc;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int o = t + 256 * q;
+    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = acc[q];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_tn_sum(const double* __restrict__ part, int nb, int M, int N,
+                                                     double alpha, double beta, double* __restrict__ C, int64_t ldc) {
+  const int lane = threadIdx.x & 63;
+  const int o = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nout = M * N;
+  if (o >= nout) return;
+  double s = 0.0;
+  for (int g = lane; g < nb; g += 64) s += part[(int64_t)g * nout + o];
+  s = wsum(s);
+  if (lane == 0) {
+    double* c = C + (o % M) + ldc * (o / M);
+    *c = alpha * s + (beta == 0.0 ? 0.0 : beta * *c);
+  }
+}
+
 // op(B)(k, j): B is K x N (tb false) or N x K (tb true); at(B, ldb, !tb, j, k) reads it.
 static hipError_t gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                        const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (ta && !tb && M <= 32 && N <= 32 && K >= 2 * TN_ROWS) {
+    const int nb = (int)((K + TN_ROWS - 1) / TN_ROWS);
+    double* part = nullptr;
+    hipError_t e = hipMallocAsync((void**)&part, sizeof(double) * nb * M * N, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gemm_tn_part, dim3(nb), dim3(256), 0, s, (int)M, (int)N, K, A, lda, B, ldb, part);
+    hipLaunchKernelGGL(k_gemm_tn_sum, dim3((unsigned)((M * N + 3) / 4)), dim3(256), 0, s, part, nb, (int)M, (int)N,
+                       alpha, beta, C, ldc);
+    e = hipGetLastError();
+    (void)hipFreeAsync(part, s);
+    return e;
+  }
   if (K >= 256)
     hipLaunchKernelGGL(k_gemm_w, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((M * N + 3) / 4, 16384))),
                        dim3(256), 0, s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);

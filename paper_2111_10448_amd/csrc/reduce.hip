@@ -1,0 +1,76 @@
+// Fixed-order reduction of the sketch kernels' workgroup partials into the
+// FP64 sketches Y_R and T_m of the middle unfolding (PSTT2-onepass, Section
+// 3.2): every entry adds its partials in increasing partial index, so the
+// sketches are bitwise reproducible for a given launch sequence.
+#include "internal.h"
+
+namespace pstt2 {
+
+// ---- fixed-order reduction of the tile partials into the FP64 sketches ----
+template <typename P>
+__global__ void k_reduce_y(const P* __restrict__ yp, int gj_count, int64_t R, int ell, double* __restrict__ Y,
+                           int* flag) {
+  const int64_t tot = R * ell;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = Y[i];
+    for (int g = 0; g < gj_count; ++g) s += (double)yp[(int64_t)g * tot + i];
+    Y[i] = s;
+    if (!isfinite(s)) atomicOr(flag, 1);
+  }
+}
+
+// Tt is C x ell column-major (the transposed left sketch); tpart is [gi][a][gcol].
+// One launch covers every segment of a sketch launch (blockIdx.y = segment).
+// Each thread adds the gi partials of one entry in increasing g, sixteen loads
+// in flight: the order, and so the result, does not depend on the launch shape.
+template <typename P>
+__global__ void k_reduce_t(const P* __restrict__ tp, const SketchArgs A, double* __restrict__ Tt, int* flag) {
+  constexpr int U = 16;
+  const int64_t gc0 = A.seg[blockIdx.y].gcol0, ncols = A.seg[blockIdx.y].ncols;
+  const int ell = A.ell, gi = A.gi_count;
+  const int64_t C = A.C, st = (int64_t)ell * C;
+  const int64_t tot = ncols * ell;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(i / ncols);
+    const int64_t col = gc0 + i % ncols;
+    const P* p = tp + (int64_t)a * C + col;
+    double s = Tt[(int64_t)a * C + col];
+    int g = 0;
+    for (; g + U <= gi; g += U) {
+      P v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = p[(int64_t)(g + u) * st];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += (double)v[u];
+    }
+    for (; g < gi; ++g) s += (double)p[(int64_t)g * st];
+    Tt[(int64_t)a * C + col] = s;
+    if (!isfinite(s)) atomicOr(flag, 1);
+  }
+}
+
+hipError_t launch_reduce(int prec, const SketchArgs& a, double* Y, double* Tt, int* flag, hipStream_t s) {
+  const int bs = 256;
+  const int64_t ny = a.R * a.ell;
+  const unsigned gy = (unsigned)std::min<int64_t>((ny + bs - 1) / bs, 4096);
+  if (prec == PSTT2_P_F64)
+    hipLaunchKernelGGL(k_reduce_y<double>, dim3(gy), dim3(bs), 0, s, (const double*)a.ypart, a.gj_count, a.R,
+                       a.ell, Y, flag);
+  else
+    hipLaunchKernelGGL(k_reduce_y<float>, dim3(gy), dim3(bs), 0, s, (const float*)a.ypart, a.gj_count, a.R,
+                       a.ell, Y, flag);
+  if (a.nseg > 0) {
+    int64_t nt = 0;
+    for (int i = 0; i < a.nseg; ++i) nt = std::max<int64_t>(nt, a.seg[i].ncols * a.ell);
+    const unsigned gt = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nt + bs - 1) / bs, 4096));
+    if (prec == PSTT2_P_F64)
+      hipLaunchKernelGGL(k_reduce_t<double>, dim3(gt, (unsigned)a.nseg), dim3(bs), 0, s, (const double*)a.tpart, a,
+                         Tt, flag);
+    else
+      hipLaunchKernelGGL(k_reduce_t<float>, dim3(gt, (unsigned)a.nseg), dim3(bs), 0, s, (const float*)a.tpart, a,
+                         Tt, flag);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pstt2
