@@ -145,13 +145,13 @@ static hipError_t gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
   if (ta && !tb && M <= 32 && N <= 32 && K >= 2 * TN_ROWS) {
     const int nb = (int)((K + TN_ROWS - 1) / TN_ROWS);
     double* part = nullptr;
-    hipError_t e = hipMallocAsync((void**)&part, sizeof(double) * nb * M * N, s);
+    hipError_t e = ws_alloc((void**)&part, sizeof(double) * nb * M * N, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gemm_tn_part, dim3(nb), dim3(256), 0, s, (int)M, (int)N, K, A, lda, B, ldb, part);
     hipLaunchKernelGGL(k_gemm_tn_sum, dim3((unsigned)((M * N + 3) / 4)), dim3(256), 0, s, part, nb, (int)M, (int)N,
                        alpha, beta, C, ldc);
     e = hipGetLastError();
-    (void)hipFreeAsync(part, s);
+    ws_free(part, s);
     return e;
   }
   if (K >= 256)
@@ -560,8 +560,8 @@ hipError_t adj_pbar(const double* om_tab, int L4, int64_t Cm, int rm, int ell, i
 hipError_t adj_qr(const double* S, const double* Q, const double* Qb, int64_t M, int ell, int r, const int* piv,
                   double* Sb, hipStream_t s) {
   double *B = nullptr, *RM = nullptr;
-  hipError_t e = hipMallocAsync((void**)&B, sizeof(double) * M * r, s);
-  if (e == hipSuccess) e = hipMallocAsync((void**)&RM, sizeof(double) * 2 * r * r, s);
+  hipError_t e = ws_alloc((void**)&B, sizeof(double) * M * r, s);
+  if (e == hipSuccess) e = ws_alloc((void**)&RM, sizeof(double) * 2 * r * r, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gather_cols, dim3(grid_for(M * r, 256)), dim3(256), 0, s, S, M, piv, r, B);
   e = gemm(true, false, r, r, M, 1.0, Q, M, B, M, 0.0, RM, r, s);                 // R = Q^T B
@@ -570,8 +570,8 @@ hipError_t adj_qr(const double* S, const double* Q, const double* Qb, int64_t M,
     hipLaunchKernelGGL(k_qr_adj_rows, dim3(grid_for(M, 256)), dim3(256), 0, s, Q, Qb, M, r, RM, RM + r * r, piv, Sb);
     e = hipGetLastError();
   }
-  (void)hipFreeAsync(B, s);
-  (void)hipFreeAsync(RM, s);
+  ws_free(B, s);
+  ws_free(RM, s);
   return e;
 }
 

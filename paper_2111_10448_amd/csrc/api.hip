@@ -42,6 +42,7 @@ struct pstt2_ctx {
   std::vector<double*> S;      // S[k], k = 1..m-1, R_k x ell (S[m] aliases Y)
   std::vector<double*> Tk;     // Tk[k], k = m+1..d-1, C_k x ell (Tk[m] aliases Tt)
   std::vector<double*> basis;  // Q_k (k < m) or P_k (k >= m)
+  Arena arena;                 // recovery workspace: sketches, bases, temporaries
   double* Bk = nullptr;        // two-sided sketches, split k at Bk + k ell^2 (ell x ell)
   double* H = nullptr;         // two-sided middle sketch, (ell n_m) x ell (TWOSIDED only)
   int ranks[PSTT2_MAX_D + 1] = {};
@@ -77,6 +78,17 @@ double* pinned_scratch() {
   return buf;
 }
 
+// Workspace arena of tt_error for the current device on this host thread;
+// held until the process ends.
+Arena* error_arena() {
+  thread_local std::map<int, Arena*> by_dev;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  Arena*& a = by_dev[dev];
+  if (!a) a = new Arena();
+  return a;
+}
+
 pstt2_status fail(pstt2_ctx* c, pstt2_status st, const std::string& msg) {
   if (c) c->err = msg;
   pstt2_set_tls_error(msg);
@@ -94,14 +106,9 @@ pstt2_status hfail(pstt2_ctx* c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hfail((ctx), e_, #call);     \
   } while (0)
 
+// The recovery products live in the context's arena until the next recovery;
+// forgetting them is enough.
 void free_recovery(pstt2_ctx* c) {
-  for (size_t k = 0; k < c->S.size(); ++k)
-    if (c->S[k] && c->S[k] != c->Y) (void)hipFreeAsync(c->S[k], c->stream);
-  for (size_t k = 0; k < c->Tk.size(); ++k)
-    if (c->Tk[k] && c->Tk[k] != c->Tt) (void)hipFreeAsync(c->Tk[k], c->stream);
-  for (auto p : c->basis)
-    if (p) (void)hipFreeAsync(p, c->stream);
-  if (c->H) (void)hipFreeAsync(c->H, c->stream);
   c->H = nullptr;
   c->S.assign(c->d + 1, nullptr);
   c->Tk.assign(c->d + 1, nullptr);
@@ -276,6 +283,14 @@ pstt2_status run_slabs(pstt2_ctx* c, const std::vector<Piece>& ps) {
     }
   }
   return PSTT2_OK;
+}
+
+__global__ void k_zero_sketches(double* __restrict__ Y, int64_t ny, double* __restrict__ T, int64_t nt, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < ny; i += stride) Y[i] = 0.0;
+  for (int64_t i = t0; i < nt; i += stride) T[i] = 0.0;
+  if (t0 == 0) *flag = 0;
 }
 
 __global__ void k_transpose_last(const double* P, int64_t rows, int r, double* G) {
@@ -461,13 +476,14 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
 pstt2_status pstt2_reset(pstt2_ctx* c) {
   if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
   free_recovery(c);
-  HIPCK(c, hipMemsetAsync(c->Y, 0, sizeof(double) * c->R * c->ell, c->stream));
-  HIPCK(c, hipMemsetAsync(c->Tt, 0, sizeof(double) * c->C * c->ell, c->stream));
+  // one fill launch for both middle sketches and the flag word
+  hipLaunchKernelGGL(k_zero_sketches, dim3(1024), dim3(256), 0, c->stream, c->Y, c->R * c->ell, c->Tt,
+                     c->C * c->ell, c->flag);
+  HIPCK(c, hipGetLastError());
   for (double* y : c->iY)
     if (y) HIPCK(c, hipMemsetAsync(y, 0, sizeof(double) * c->R * c->ell, c->stream));
   for (double* t : c->iT)
     if (t) HIPCK(c, hipMemsetAsync(t, 0, sizeof(double) * c->C * c->ell, c->stream));
-  HIPCK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
   c->cover.clear();
   c->covered = 0;
   return PSTT2_OK;
@@ -508,6 +524,7 @@ void pstt2_destroy(pstt2_ctx* c) {
     (void)hipEventDestroy(e.second);
   }
   free_recovery(c);
+  arena_release(&c->arena, c->stream);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(c->fac);
   (void)hipFree(c->Y);
@@ -573,17 +590,19 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   free_recovery(c);
   const int d = c->d, m = c->m, ell = c->ell;
   hipStream_t s = c->stream;
+  HIPCK(c, arena_begin(&c->arena, s));
+  ArenaScope arena_scope(&c->arena);
   // (1) every split's sketch
   c->S[m] = c->Y;
   c->Tk[m] = c->Tt;
   if (!c->indep) {
     for (int k = m - 1; k >= 1; --k) {
-      HIPCK(c, hipMallocAsync((void**)&c->S[k], sizeof(double) * c->Rk[k] * ell, s));
+      HIPCK(c, ws_alloc((void**)&c->S[k], sizeof(double) * c->Rk[k] * ell, s));
       HIPCK(c, derive_left(c->S[k + 1], c->S[k], c->Rk[k], (int)c->n[k], ell, c->fac + c->omega_off[k], s));
     }
     for (int k = m + 1; k <= d - 1; ++k) {
       const int64_t Ck = c->N / c->Rk[k];
-      HIPCK(c, hipMallocAsync((void**)&c->Tk[k], sizeof(double) * Ck * ell, s));
+      HIPCK(c, ws_alloc((void**)&c->Tk[k], sizeof(double) * Ck * ell, s));
       HIPCK(c, derive_right(c->Tk[k - 1], c->Tk[k], Ck, (int)c->n[k - 1], ell, c->fac + c->psi_off[k - 1], s));
     }
   } else {
@@ -592,9 +611,9 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
       const double* cur = c->iY[k];
       for (int q = m; q >= k + 1; --q) {   // contract mode q: R_q -> R_{q-1} rows
         double* nxt = nullptr;
-        HIPCK(c, hipMallocAsync((void**)&nxt, sizeof(double) * c->Rk[q - 1] * ell, s));
+        HIPCK(c, ws_alloc((void**)&nxt, sizeof(double) * c->Rk[q - 1] * ell, s));
         HIPCK(c, derive_left(cur, nxt, c->Rk[q - 1], (int)c->n[q - 1], ell, c->fac + c->iom_off[k][q - 1], s));
-        if (cur != c->iY[k]) HIPCK(c, hipFreeAsync((void*)cur, s));
+        if (cur != c->iY[k]) ws_free((void*)cur, s);
         cur = nxt;
       }
       c->S[k] = (double*)cur;
@@ -604,9 +623,9 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
       for (int q = m + 1; q <= k; ++q) {   // contract mode q: C_{q-1} -> C_q columns
         const int64_t Cq = c->N / c->Rk[q];
         double* nxt = nullptr;
-        HIPCK(c, hipMallocAsync((void**)&nxt, sizeof(double) * Cq * ell, s));
+        HIPCK(c, ws_alloc((void**)&nxt, sizeof(double) * Cq * ell, s));
         HIPCK(c, derive_right(cur, nxt, Cq, (int)c->n[q - 1], ell, c->fac + c->ipsi_off[k][q - 1], s));
-        if (cur != c->iT[k]) HIPCK(c, hipFreeAsync((void*)cur, s));
+        if (cur != c->iT[k]) ws_free((void*)cur, s);
         cur = nxt;
       }
       c->Tk[k] = (double*)cur;
@@ -617,7 +636,7 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
     int64_t kmax = 0;
     for (int k = 1; k <= d - 1; ++k) kmax = std::max(kmax, k < m ? c->Rk[k] : c->N / c->Rk[k]);
     double* tab = nullptr;
-    HIPCK(c, hipMallocAsync((void**)&tab, sizeof(double) * kmax * ell, s));
+    HIPCK(c, ws_alloc((void**)&tab, sizeof(double) * kmax * ell, s));
     hipError_t e = hipSuccess;
     for (int k = 1; k <= d - 1 && e == hipSuccess; ++k) {
       double* Bk = c->Bk + (int64_t)k * ell * ell;
@@ -632,7 +651,7 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
         if (e == hipSuccess) e = adj_gemm(true, false, ell, ell, Ck, 1.0, c->Tk[k], Ck, tab, Ck, 0.0, Bk, ell, s);
       }
     }
-    (void)hipFreeAsync(tab, s);
+    ws_free(tab, s);
     if (e != hipSuccess) return hfail(c, e, "two-sided sketches");
   }
   // (2) factor every sketch (one batched TSQR over all splits); the ranks come
@@ -695,7 +714,7 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
     std::vector<double*> Qp(d - 1);
     hipError_t e = hipSuccess;
     for (int k = 1; k <= d - 1 && e == hipSuccess; ++k) {
-      e = hipMallocAsync((void**)&c->basis[k], sizeof(double) * Mp[k - 1] * r[k], s);
+      e = ws_alloc((void**)&c->basis[k], sizeof(double) * Mp[k - 1] * r[k], s);
       Qp[k - 1] = c->basis[k];
     }
     if (e == hipSuccess) e = basis_form_q_batch(bw, r + 1, Qp.data(), s);
@@ -750,8 +769,8 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   if (c->desc.mid == PSTT2_MID_ONEPASS || c->desc.mid == PSTT2_MID_TWOSIDED) {
     double *Z = nullptr, *A = nullptr;
     const int nm = (int)c->n[m - 1];
-    e = hipMallocAsync((void**)&Z, sizeof(double) * nz * ell, s);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&A, sizeof(double) * r[m] * ell, s);
+    e = ws_alloc((void**)&Z, sizeof(double) * nz * ell, s);
+    if (e == hipSuccess) e = ws_alloc((void**)&A, sizeof(double) * r[m] * ell, s);
     if (c->desc.mid == PSTT2_MID_ONEPASS || m == 1) {
       // Z = (I (x) Q_{m-1})^T Y_R
       if (e == hipSuccess) e = middle_z(Qprev, Rprev, r[m - 1], c->Y, c->R, nm, ell, Z, s);
@@ -762,27 +781,27 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
       // right-hand side I_ell and system matrix A1^T returns M1^T.
       const int rp = r[m - 1];
       double *ptab = nullptr, *a1t = nullptr, *id = nullptr, *m1t = nullptr;
-      if (e == hipSuccess) e = hipMallocAsync((void**)&c->H, sizeof(double) * ell * nm * ell, s);
-      if (e == hipSuccess) e = hipMallocAsync((void**)&ptab, sizeof(double) * Rprev * ell, s);
-      if (e == hipSuccess) e = hipMallocAsync((void**)&a1t, sizeof(double) * rp * ell, s);
-      if (e == hipSuccess) e = hipMallocAsync((void**)&id, sizeof(double) * ell * ell, s);
-      if (e == hipSuccess) e = hipMallocAsync((void**)&m1t, sizeof(double) * ell * rp, s);
+      if (e == hipSuccess) e = ws_alloc((void**)&c->H, sizeof(double) * ell * nm * ell, s);
+      if (e == hipSuccess) e = ws_alloc((void**)&ptab, sizeof(double) * Rprev * ell, s);
+      if (e == hipSuccess) e = ws_alloc((void**)&a1t, sizeof(double) * rp * ell, s);
+      if (e == hipSuccess) e = ws_alloc((void**)&id, sizeof(double) * ell * ell, s);
+      if (e == hipSuccess) e = ws_alloc((void**)&m1t, sizeof(double) * ell * rp, s);
       if (e == hipSuccess) e = kr_table(c->fac, left_chain(c, m - 1), Rprev, ell, ptab, s);
       if (e == hipSuccess) e = middle_z(ptab, Rprev, ell, c->Y, c->R, nm, ell, c->H, s);
       if (e == hipSuccess) e = adj_gemm(true, false, rp, ell, Rprev, 1.0, Qprev, Rprev, ptab, Rprev, 0.0, a1t, rp, s);
       if (e == hipSuccess) e = eye(ell, id, s);
       if (e == hipSuccess) e = middle_ls(id, ell, a1t, rp, ell, m1t, c->flag, s);
       if (e == hipSuccess) e = middle_z(m1t, ell, rp, c->H, (int64_t)ell * nm, nm, ell, Z, s);
-      (void)hipFreeAsync(ptab, s);
-      (void)hipFreeAsync(a1t, s);
-      (void)hipFreeAsync(id, s);
-      (void)hipFreeAsync(m1t, s);
+      ws_free(ptab, s);
+      ws_free(a1t, s);
+      ws_free(id, s);
+      ws_free(m1t, s);
     }
     SketchArgs geo = base_args(c);
     if (e == hipSuccess) e = middle_a(c->basis[m], c->C, r[m], geo, c->prec, A, s);
     if (e == hipSuccess) e = middle_ls(Z, nz, A, r[m], ell, tc.core[m - 1], c->flag, s);
-    (void)hipFreeAsync(Z, s);
-    (void)hipFreeAsync(A, s);
+    ws_free(Z, s);
+    ws_free(A, s);
   } else {
     e = hipMemsetAsync(tc.core[m - 1], 0, sizeof(double) * nz * r[m], s);
   }
@@ -1078,7 +1097,13 @@ pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtyp
   if (!x_dev || !rel_err) return fail(nullptr, PSTT2_EINVAL, "null argument");
   double e2x2[2] = {0, 0};
   double* pin = pinned_scratch();
-  hipError_t e = tt_error_run(cores, x_dev, dtype, pin ? pin : e2x2, (hipStream_t)hip_stream);
+  // tt_error returns only after its stream is idle, so its temporaries can come
+  // from a per-thread, per-device arena that the next call rewinds
+  Arena* ar = error_arena();
+  hipError_t e = ar ? arena_begin(ar, (hipStream_t)hip_stream) : hipSuccess;
+  if (e != hipSuccess) return hfail(nullptr, e, "tt_error");
+  ArenaScope scope(ar);
+  e = tt_error_run(cores, x_dev, dtype, pin ? pin : e2x2, (hipStream_t)hip_stream);
   if (pin) {
     e2x2[0] = pin[0];
     e2x2[1] = pin[1];

@@ -13,6 +13,25 @@
 
 namespace pstt2 {
 
+// ---- device workspace (workspace.hip) ----
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0, need = 0;
+  std::vector<void*> spill;
+};
+// the arena ws_alloc / ws_free use on this host thread (nullptr: none)
+Arena*& current_arena();
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena* a);
+  ~ArenaScope();
+};
+// start a pass: release the last pass's overflow, regrow to what it needed, rewind
+hipError_t arena_begin(Arena* a, hipStream_t s);
+void arena_release(Arena* a, hipStream_t s);
+hipError_t ws_alloc(void** p, size_t bytes, hipStream_t s);
+void ws_free(void* p, hipStream_t s);
+
 constexpr int kMaxSeg = 48;   // slabs per sketch launch
 
 // One run of whole columns of the middle unfolding X_m held in one buffer.

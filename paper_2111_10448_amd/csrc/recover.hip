@@ -419,8 +419,8 @@ struct SvBatch {
 // problem: a round rotates E/2 disjoint column pairs (round-robin ordering,
 // E = ell rounded up to even), four lanes per pair with eight rows each, so a
 // round is a few LDS accesses, two shuffle steps and one rotation per lane.
-// Sweeps end when no pair needed a rotation; the singular values are the
-// final column norms, sorted in decreasing order.
+// Sweeps end when no pair needed a rotation (at most 40); the singular values
+// are the final column norms, sorted in decreasing order.
 __global__ __launch_bounds__(64) void k_jacobi_sv(const SvBatch B, int ell) {
   const double* __restrict__ R = B.R[blockIdx.x];
   const int64_t ldr = B.ldr[blockIdx.x];
@@ -435,6 +435,10 @@ __global__ __launch_bounds__(64) void k_jacobi_sv(const SvBatch B, int ell) {
   __syncthreads();
   const int E = (ell + 1) & ~1;
   const int pr = t >> 2, r0 = (t & 3) * 8;
+  // a pair counts as orthogonal once |u_p . u_q| <= ell eps |u_p| |u_q|, the
+  // rounding level of the dot product itself (a tighter test keeps rotating on
+  // rounding noise and never ends before the sweep cap)
+  const double tol = ell * 2.220446049250313e-16;
   for (int sweep = 0; sweep < 40; ++sweep) {
     int rot = 0;
     for (int rnd = 0; rnd < E - 1; ++rnd) {
@@ -472,7 +476,7 @@ __global__ __launch_bounds__(64) void k_jacobi_sv(const SvBatch B, int ell) {
         aqq += __shfl_xor(aqq, o);
         apq += __shfl_xor(apq, o);
       }
-      if (act && fabs(apq) > 1e-15 * sqrt(app * aqq) && apq != 0.0) {
+      if (act && fabs(apq) > tol * sqrt(app * aqq) && apq != 0.0) {
         const double zeta = (aqq - app) / (2.0 * apq);
         const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + tt * tt);
@@ -524,8 +528,8 @@ struct BasisBatch {
 
 void basis_batch_free(BasisBatch* w) {
   if (!w) return;
-  if (w->ws) (void)hipFreeAsync(w->ws, w->s);
-  if (w->tmp) (void)hipFreeAsync(w->tmp, w->s);
+  if (w->ws) ws_free(w->ws, w->s);
+  if (w->tmp) ws_free(w->tmp, w->s);
   delete w;
 }
 
@@ -574,7 +578,7 @@ hipError_t basis_factor_batch(int n, const double* const* A, const int64_t* M, i
     maxL = std::max(maxL, (int)w->lv[p].size());
     tot += ell * ell + (want_sv ? ell : 0);
   }
-  HCK(hipMallocAsync((void**)&w->ws, sizeof(double) * tot, s));
+  HCK(ws_alloc((void**)&w->ws, sizeof(double) * tot, s));
   double* cur = w->ws;
   w->Qc.resize(n);
   w->sv.assign(n, nullptr);
@@ -671,7 +675,7 @@ hipError_t basis_form_q_batch(BasisBatch* w, const int* r, double* const* Q, hip
     off[p] = tmpsz;
     tmpsz += 2 * maxrows * r[p];
   }
-  if (tmpsz > 0) HCK(hipMallocAsync((void**)&w->tmp, sizeof(double) * tmpsz, s));
+  if (tmpsz > 0) HCK(ws_alloc((void**)&w->tmp, sizeof(double) * tmpsz, s));
   std::vector<const double*> zin(n);
   std::vector<int64_t> ldzi(n, ell);
   for (int p = 0; p < n; ++p) zin[p] = w->Qc[p];   // ell x r (first r columns of Qc, ld ell)
@@ -909,12 +913,12 @@ hipError_t middle_a(const double* Pm, int64_t Cm, int rm, const SketchArgs& geo,
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(MA_BLOCKS, (Cm + MA_TILE - 1) / MA_TILE));
   const int nout = rm * geo.ell;
   double* part = nullptr;
-  hipError_t e = hipMallocAsync((void**)&part, sizeof(double) * nb * nout, s);
+  hipError_t e = ws_alloc((void**)&part, sizeof(double) * nb * nout, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_middle_a_part, dim3(nb), dim3(256), 0, s, Pm, Cm, rm, geo, prec, part);
   hipLaunchKernelGGL(k_middle_a_sum, dim3((nout + 3) / 4), dim3(256), 0, s, part, nb, nout, A);
   e = hipGetLastError();
-  (void)hipFreeAsync(part, s);
+  ws_free(part, s);
   return e;
 }
 

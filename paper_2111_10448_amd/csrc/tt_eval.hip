@@ -70,7 +70,7 @@ hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** R
     tot += Ck * c->r[k];
   }
   double* ws = nullptr;
-  hipError_t e = hipMallocAsync((void**)&ws, sizeof(double) * tot, s);
+  hipError_t e = ws_alloc((void**)&ws, sizeof(double) * tot, s);
   if (e != hipSuccess) return e;
   *base = ws;
   double* cur = ws;
@@ -216,7 +216,7 @@ hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x
   const int gi = (int)((R + 511) / 512);
   const int gj = (int)std::max<int64_t>(1, std::min<int64_t>(C, (4096 + gi - 1) / gi));
   double* part = nullptr;
-  e = hipMallocAsync((void**)&part, sizeof(double) * 2 * ((int64_t)gi * gj + 1), s);
+  e = ws_alloc((void**)&part, sizeof(double) * 2 * ((int64_t)gi * gj + 1), s);
   if (e != hipSuccess) return e;
   if (dtype == PSTT2_F64) e = launch_err((const double*)x, R, C, r, L, Rt, gi, gj, part, s);
   else e = launch_err((const float*)x, R, C, r, L, Rt, gi, gj, part, s);
@@ -224,8 +224,8 @@ hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, gi * gj, part + 2 * (int64_t)gi * gj);
     e = hipMemcpyAsync(e2x2, part + 2 * (int64_t)gi * gj, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
   }
-  hipFreeAsync(part, s);
-  hipFreeAsync(ifb, s);
+  ws_free(part, s);
+  ws_free(ifb, s);
   hipError_t e2 = hipStreamSynchronize(s);
   return e != hipSuccess ? e : e2;
 }
@@ -260,7 +260,7 @@ hipError_t tt_reconstruct_run(const tt_cores* c, void* out, int dtype, int64_t f
                          count, R, r, L, Rt);
     e = hipGetLastError();
   }
-  hipFreeAsync(ifb, s);
+  ws_free(ifb, s);
   hipError_t e2 = hipStreamSynchronize(s);
   return e != hipSuccess ? e : e2;
 }
