@@ -44,6 +44,7 @@ struct pstt2_ctx {
   std::vector<double*> basis;  // Q_k (k < m) or P_k (k >= m)
   Arena arena;                 // recovery workspace: sketches, bases, temporaries
   double* Bk = nullptr;        // two-sided sketches, split k at Bk + k ell^2 (ell x ell)
+  int64_t* chain_dev = nullptr;  // per split: factor offsets of its left / right DRM chains, then n
   double* H = nullptr;         // two-sided middle sketch, (ell n_m) x ell (TWOSIDED only)
   int ranks[PSTT2_MAX_D + 1] = {};
   bool recovered = false;
@@ -431,6 +432,18 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   }
   if ((e = hipMalloc(&c->one, sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(one)");
   if ((e = hipMalloc(&c->Bk, sizeof(double) * (d + 1) * c->ell * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Bk)");
+  {
+    std::vector<int64_t> ch((size_t)(d + 1) * 2 * d + d, 0);
+    for (int k = 1; k <= d - 1; ++k) {
+      const KRChain l = left_chain(c, k), r = right_chain(c, k);
+      for (int j = 0; j < l.cnt; ++j) ch[((size_t)k * 2 + 0) * d + j] = l.off[j];
+      for (int j = 0; j < r.cnt; ++j) ch[((size_t)k * 2 + 1) * d + j] = r.off[j];
+    }
+    for (int q = 0; q < d; ++q) ch[(size_t)(d + 1) * 2 * d + q] = c->n[q];
+    if ((e = hipMalloc(&c->chain_dev, sizeof(int64_t) * ch.size())) != hipSuccess) return bail(e, "hipMalloc(chain)");
+    if ((e = hipMemcpy(c->chain_dev, ch.data(), sizeof(int64_t) * ch.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return bail(e, "hipMemcpy(chain)");
+  }
   const double one = 1.0;
   if ((e = hipMemcpy(c->one, &one, sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "hipMemcpy");
   int rows_per_block = 0, threads = 0, wg_per_cu = 1;
@@ -535,6 +548,7 @@ void pstt2_destroy(pstt2_ctx* c) {
   (void)hipFree(c->piv_dev);
   (void)hipFree(c->one);
   (void)hipFree(c->Bk);
+  (void)hipFree(c->chain_dev);
   (void)hipFree(c->om_tab);
   for (double* p : c->iom_tab) (void)hipFree(p);
   for (double* p : c->iY) (void)hipFree(p);
@@ -633,26 +647,21 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   }
   // two-sided sketches: B_k = Psi_k^T S_k (k < m), B_k = T_k Omega_k (k >= m)
   {
-    int64_t kmax = 0;
-    for (int k = 1; k <= d - 1; ++k) kmax = std::max(kmax, k < m ? c->Rk[k] : c->N / c->Rk[k]);
-    double* tab = nullptr;
-    HIPCK(c, ws_alloc((void**)&tab, sizeof(double) * kmax * ell, s));
-    hipError_t e = hipSuccess;
-    for (int k = 1; k <= d - 1 && e == hipSuccess; ++k) {
-      double* Bk = c->Bk + (int64_t)k * ell * ell;
-      if (k < m) {
-        e = kr_table(c->fac, left_chain(c, k), c->Rk[k], ell, tab, s);
-        if (e == hipSuccess)
-          e = adj_gemm(true, false, ell, ell, c->Rk[k], 1.0, tab, c->Rk[k], c->S[k], c->Rk[k], 0.0, Bk, ell, s);
-      } else {
-        const int64_t Ck = c->N / c->Rk[k];
-        e = kr_table(c->fac, right_chain(c, k), Ck, ell, tab, s);
-        // Tk[k] holds T_k^T (C_k x ell)
-        if (e == hipSuccess) e = adj_gemm(true, false, ell, ell, Ck, 1.0, c->Tk[k], Ck, tab, Ck, 0.0, Bk, ell, s);
-      }
+    TwoSidedBatch tb;
+    std::memset(&tb, 0, sizeof(tb));
+    tb.d = d;
+    tb.ell = ell;
+    tb.fac = c->fac;
+    tb.chain = c->chain_dev;
+    for (int k = 1; k <= d - 1; ++k) {
+      const int p = tb.n++;
+      tb.split[p] = k;
+      tb.right[p] = k >= m;
+      tb.S[p] = k < m ? c->S[k] : c->Tk[k];
+      tb.K[p] = k < m ? c->Rk[k] : c->N / c->Rk[k];
+      tb.out[p] = c->Bk + (int64_t)k * ell * ell;
     }
-    ws_free(tab, s);
-    if (e != hipSuccess) return hfail(c, e, "two-sided sketches");
+    HIPCK(c, two_sided_batch(tb, s));
   }
   // (2) factor every sketch (one batched TSQR over all splits); the ranks come
   // from the descriptor or, in tolerance mode, from the singular values (one

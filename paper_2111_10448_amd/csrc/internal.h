@@ -119,6 +119,23 @@ struct KRChain {
 };
 // out (rows x ell, column-major) = the chain's DRM; rows = prod n[q]
 hipError_t kr_table(const double* fac, const KRChain& ch, int64_t rows, int ell, double* out, hipStream_t s);
+// Two-sided sketches of several splits (recover.hip): entry p is split
+// split[p], operand S[p] (K[p] x ell, column-major) = S_k (right = 0, DRM
+// Psi_k over modes 1..k) or T_k^T (right = 1, DRM Omega_k over modes k+1..d);
+// out[p] receives B_k (ell x ell, column-major).  chain holds the factor
+// offsets of split k's left (slot 0) and right (slot 1) chains at
+// chain[(2 k + slot) d + j], then the d mode sizes.
+struct TwoSidedBatch {
+  int n, d, ell;
+  const double* fac;
+  const int64_t* chain;
+  const double* S[PSTT2_MAX_D];
+  int64_t K[PSTT2_MAX_D];
+  int split[PSTT2_MAX_D], right[PSTT2_MAX_D];
+  double* out[PSTT2_MAX_D];
+  int64_t blk0[PSTT2_MAX_D + 1];
+};
+hipError_t two_sided_batch(TwoSidedBatch& B, hipStream_t s);
 // out (k x k) = identity
 hipError_t eye(int k, double* out, hipStream_t s);
 hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count, int64_t Rprev, int nm,

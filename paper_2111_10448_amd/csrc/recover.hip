@@ -47,8 +47,17 @@ __global__ void k_derive_left(const double* __restrict__ Sin, double* __restrict
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(t / Rk);
     const int64_t row = t % Rk;
+    const double* sp = Sin + (int64_t)c * Rk1 + row;
     double s = 0.0;
-    for (int i = 0; i < nk1; ++i) s += Sin[(int64_t)c * Rk1 + row + Rk * i] * om[i * ell + c];
+    int i = 0;
+    for (; i + 8 <= nk1; i += 8) {   // eight loads in flight, summed in order
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = sp[Rk * (i + u)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u] * om[(i + u) * ell + c];
+    }
+    for (; i < nk1; ++i) s += sp[Rk * i] * om[i * ell + c];
     Sout[(int64_t)c * Rk + row] = s;
   }
 }
@@ -60,8 +69,17 @@ __global__ void k_derive_right(const double* __restrict__ Tin, double* __restric
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
     const int a = (int)(t / Ck);
     const int64_t col = t % Ck;
+    const double* tp = Tin + (int64_t)a * Cprev + (int64_t)nk * col;
     double s = 0.0;
-    for (int i = 0; i < nk; ++i) s += ps[i * ell + a] * Tin[(int64_t)a * Cprev + i + (int64_t)nk * col];
+    int i = 0;
+    for (; i + 8 <= nk; i += 8) {   // eight loads in flight, summed in order
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = tp[i + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += ps[(i + u) * ell + a] * v[u];
+    }
+    for (; i < nk; ++i) s += ps[i * ell + a] * tp[i];
     Tout[(int64_t)a * Ck + col] = s;
   }
 }
@@ -541,13 +559,13 @@ void basis_batch_free(BasisBatch* w) {
 
 // Sketches of up to 16 columns use 1024-row leaves (4 rows per thread); wider
 // ones 512-row leaves, so the registers of a thread stay within 64 values.
-static int leaf_rpt(int ell) { return ell <= 16 ? 4 : 2; }
+static int leaf_rpt(int ell) { return ell <= 24 ? 4 : 2; }
 
 static void launch_leaf(const LeafBatch& B, int64_t nblk, int ell, hipStream_t s) {
   const dim3 g((unsigned)nblk), b(256);
   if (ell <= 8) hipLaunchKernelGGL((k_qr_leaf<8, 4>), g, b, 0, s, B, ell);
   else if (ell <= 16) hipLaunchKernelGGL((k_qr_leaf<16, 4>), g, b, 0, s, B, ell);
-  else if (ell <= 24) hipLaunchKernelGGL((k_qr_leaf<24, 2>), g, b, 0, s, B, ell);
+  else if (ell <= 24) hipLaunchKernelGGL((k_qr_leaf<24, 4>), g, b, 0, s, B, ell);
   else hipLaunchKernelGGL((k_qr_leaf<32, 2>), g, b, 0, s, B, ell);
 }
 
@@ -650,7 +668,8 @@ static void launch_apply(const ApplyBatch& B, int64_t nblk, int rpt, int rmax, i
   const dim3 g((unsigned)nblk), b(256);
   if (rpt == 4) {
     if (rmax <= 8) hipLaunchKernelGGL((k_qr_apply<8, 4>), g, b, 0, s, B, ell);
-    else hipLaunchKernelGGL((k_qr_apply<16, 4>), g, b, 0, s, B, ell);
+    else if (rmax <= 16) hipLaunchKernelGGL((k_qr_apply<16, 4>), g, b, 0, s, B, ell);
+    else hipLaunchKernelGGL((k_qr_apply<24, 4>), g, b, 0, s, B, ell);
   } else {
     if (rmax <= 8) hipLaunchKernelGGL((k_qr_apply<8, 2>), g, b, 0, s, B, ell);
     else if (rmax <= 16) hipLaunchKernelGGL((k_qr_apply<16, 2>), g, b, 0, s, B, ell);
@@ -834,6 +853,96 @@ __global__ void k_eye(int k, double* __restrict__ out) {
 hipError_t eye(int k, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_eye, dim3(1), dim3(256), 0, s, k, out);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Two-sided sketches of every split in two launches.  B_k = Psi_k^T S_k
+// (k < m, operand S_k = X_k Omega_k, R_k rows) or B_k = T_k Omega_k (k >= m,
+// operand T_k^T, C_k rows).  A workgroup takes TS_ROWS rows of one split's
+// operand, forms the matching Khatri-Rao DRM rows from the factors in LDS,
+// and writes the slice's ell x ell partial product; a wavefront per entry then
+// adds a split's slice partials in slice order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int TS_ROWS = 128;
+
+__global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, double* __restrict__ part) {
+  __shared__ double Fs[TS_ROWS][PSTT2_MAX_ELL + 1];
+  __shared__ double Ss[TS_ROWS][PSTT2_MAX_ELL + 1];
+  const int t = threadIdx.x;
+  const int ell = B.ell, d = B.d;
+  const int p = batch_find(B.blk0, B.n, blockIdx.x);
+  const int64_t K = B.K[p];
+  const int64_t r0 = (blockIdx.x - B.blk0[p]) * (int64_t)TS_ROWS;
+  const int k = B.split[p], right = B.right[p];
+  const int q0 = right ? k : 0, cnt = right ? d - k : k;
+  const int64_t* off = B.chain + ((int64_t)k * 2 + right) * d;
+  const int64_t* nmode = B.chain + (int64_t)(d + 1) * 2 * d;
+  const double* __restrict__ S = B.S[p];
+  for (int e = t; e < TS_ROWS * ell; e += 256) {
+    const int r = e % TS_ROWS, u = e / TS_ROWS;
+    const int64_t row = r0 + r;
+    double sv = 0.0, fv = 0.0;
+    if (row < K) {
+      sv = S[(int64_t)u * K + row];
+      int64_t rest = row;
+      fv = 1.0;
+      for (int j = 0; j < cnt; ++j) {
+        const int64_t nq = nmode[q0 + j];
+        const int64_t i = rest % nq;
+        rest /= nq;
+        fv *= B.fac[off[j] + i * ell + u];
+      }
+    }
+    Ss[r][u] = sv;
+    Fs[r][u] = fv;
+  }
+  __syncthreads();
+  const int nout = ell * ell;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int o = t + 256 * q;
+    if (o < nout) {
+      const int u = o % ell, v = o / ell;
+      double acc = 0.0;
+      if (!right) {
+        for (int r = 0; r < TS_ROWS; ++r) acc += Fs[r][u] * Ss[r][v];   // Psi_k(row, u) S_k(row, v)
+      } else {
+        for (int r = 0; r < TS_ROWS; ++r) acc += Ss[r][u] * Fs[r][v];   // T_k(u, col) Omega_k(col, v)
+      }
+      part[(int64_t)blockIdx.x * nout + o] = acc;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_two_sided_sum(const TwoSidedBatch B, const double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int nout = B.ell * B.ell;
+  const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (w >= (int64_t)B.n * nout) return;
+  const int p = (int)(w / nout), o = (int)(w % nout);
+  double s = 0.0;
+  for (int64_t g = B.blk0[p] + lane; g < B.blk0[p + 1]; g += 64) s += part[g * nout + o];
+  s = wave_sum(s);
+  if (lane == 0) B.out[p][o] = s;
+}
+
+hipError_t two_sided_batch(TwoSidedBatch& B, hipStream_t s) {
+  int64_t nblk = 0;
+  for (int p = 0; p < B.n; ++p) {
+    B.blk0[p] = nblk;
+    nblk += std::max<int64_t>(1, (B.K[p] + TS_ROWS - 1) / TS_ROWS);
+  }
+  B.blk0[B.n] = nblk;
+  if (B.n == 0) return hipSuccess;
+  double* part = nullptr;
+  hipError_t e = ws_alloc((void**)&part, sizeof(double) * nblk * B.ell * B.ell, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_two_sided_part, dim3((unsigned)nblk), dim3(256), 0, s, B, part);
+  const int64_t waves = (int64_t)B.n * B.ell * B.ell;
+  hipLaunchKernelGGL(k_two_sided_sum, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, B, part);
+  e = hipGetLastError();
+  ws_free(part, s);
+  return e;
 }
 
 // The value of a DRM entry as the sketch kernel used it: the FP64 product of
