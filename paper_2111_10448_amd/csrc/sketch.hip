@@ -74,7 +74,7 @@ struct Eng<P_F64> {
   using acc = double;
   using accv = d4;
   using part = double;   // partial sums written to HBM
-  static constexpr int KPL = 1, KSTEP = 4, RW = 64, VEC = 2, PAD = 2;
+  static constexpr int KPL = 1, KSTEP = 4, RW = 64, VEC = 2, PAD = 2, NPL = 1;
 };
 template <>
 struct Eng<P_F32> {
@@ -83,28 +83,50 @@ struct Eng<P_F32> {
   using acc = float;
   using accv = f4;
   using part = float;
-  static constexpr int KPL = 1, KSTEP = 4, RW = 128, VEC = 4, PAD = 4;
+  static constexpr int KPL = 1, KSTEP = 4, RW = 128, VEC = 4, PAD = 4, NPL = 1;
 };
 template <>
 struct Eng<P_BF16> {
   using elem = float;
-  using lds_t = uint32_t;  // bf16 in the low half
+  using lds_t = uint32_t;  // bf16 in the low half, converted once when staged
   using acc = float;
   using accv = f4;
   using part = float;
-  static constexpr int KPL = 4, KSTEP = 16, RW = 64, VEC = 4, PAD = 4;
+  static constexpr int KPL = 4, KSTEP = 16, RW = 128, VEC = 4, PAD = 4, NPL = 1;
 };
-// Split BF16: X and the DRM stay FP32 in LDS and are split into three bf16
-// terms when an operand is formed; the six products of order <= 2 are summed.
+// Split BF16: X and the DRM are split into three bf16 terms once, when they
+// are staged in LDS (three planes); the six products of order <= 2 are summed.
 template <>
 struct Eng<P_BF16X3> {
   using elem = float;
-  using lds_t = float;
+  using lds_t = uint16_t;
   using acc = float;
   using accv = f4;
   using part = float;
-  static constexpr int KPL = 4, KSTEP = 16, RW = 64, VEC = 4, PAD = 4;
+  static constexpr int KPL = 4, KSTEP = 16, RW = 64, VEC = 4, PAD = 4, NPL = 3;
 };
+
+// Hardware round-to-nearest-even FP32 -> BF16 of two values (packed, first in
+// the low half), and the exact three-term split of two FP32 values into packed
+// bf16 planes: t0 = bf16(x), t1 = bf16(x - t0), t2 = bf16(x - t0 - t1).
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t cvt2(float a, float b) {
+  const f2v v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf2v));
+}
+__device__ __forceinline__ float lo_f(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float hi_f(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+__device__ __forceinline__ void split3_pk(float a, float b, uint32_t& t0, uint32_t& t1, uint32_t& t2) {
+  t0 = cvt2(a, b);
+  const float ra = a - lo_f(t0), rb = b - hi_f(t0);
+  t1 = cvt2(ra, rb);
+  t2 = cvt2(ra - lo_f(t1), rb - hi_f(t1));
+}
+// four bf16 of one plane at stride st (elements) as an MFMA operand
+__device__ __forceinline__ s4 gather4(const uint16_t* p, int st) {
+  return s4{(short)p[0], (short)p[st], (short)p[2 * st], (short)p[3 * st]};
+}
 
 template <int PREC>
 __device__ __forceinline__ typename Eng<PREC>::lds_t to_lds(typename Eng<PREC>::elem v);
@@ -112,17 +134,11 @@ template <>
 __device__ __forceinline__ double to_lds<P_F64>(double v) { return v; }
 template <>
 __device__ __forceinline__ float to_lds<P_F32>(float v) { return v; }
-template <>
-__device__ __forceinline__ uint32_t to_lds<P_BF16>(float v) { return bf16_rne(v); }
-template <>
-__device__ __forceinline__ float to_lds<P_BF16X3>(float v) { return v; }
 
 // DRM value (FP64 product of factors) converted to the LDS representation.
 template <int PREC>
 __device__ __forceinline__ typename Eng<PREC>::lds_t drm_to_lds(double v) {
   if constexpr (PREC == P_F64) return v;
-  else if constexpr (PREC == P_F32) return (float)v;
-  else if constexpr (PREC == P_BF16) return bf16_rne((float)v);
   else return (float)v;
 }
 
@@ -237,9 +253,10 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
   constexpr int NTH = NWS * 64;          // threads
   constexpr int NRT = (LP * KC + NTH - 1) / NTH;   // T outputs per thread in the reduction
   static_assert(KC * LP / 2 <= NTH, "one Omega pair per thread");
-  __shared__ lds_t Xl[NWS][KC * ST];
+  constexpr int NPL = E::NPL;                // bf16 planes of X and Omega in LDS (1 otherwise)
+  __shared__ __align__(16) lds_t Xl[NWS][NPL * KC * ST];
   __shared__ acc Tred[2][NWS][LP * KC];
-  __shared__ __align__(16) lds_t Om[4][KC * LP];   // 4 buffers: each write is a barrier past the last read
+  __shared__ __align__(16) lds_t Om[4][NPL * KC * LP];   // 4 buffers: each write is a barrier past the last read
 
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -274,7 +291,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
       } else {
         uint32_t p[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) p[v] = drm_to_lds<PREC>(psi_row(A, row0w + 16 * ks + 4 * g4 + v, a));
+        for (int v = 0; v < 4; ++v) p[v] = bf16_rne((float)psi_row(A, row0w + 16 * ks + 4 * g4 + v, a));
         s4 hi, lo;
         unpack4(p[0], p[1], p[2], p[3], hi, lo);
         psiA[ks][mt] = hi;
@@ -305,8 +322,19 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
   auto store_omega = [&](int buf) {
     const int e = 2 * threadIdx.x;
     if (e < KC * LP) {
-      Om[buf][e] = drm_to_lds<PREC>(omv.x);
-      Om[buf][e + 1] = drm_to_lds<PREC>(omv.y);
+      if constexpr (PREC == P_BF16) {
+        Om[buf][e] = bf16_rne((float)omv.x);
+        Om[buf][e + 1] = bf16_rne((float)omv.y);
+      } else if constexpr (X3) {
+        uint32_t t0, t1, t2;
+        split3_pk((float)omv.x, (float)omv.y, t0, t1, t2);
+        *(uint32_t*)&Om[buf][e] = t0;
+        *(uint32_t*)&Om[buf][KC * LP + e] = t1;
+        *(uint32_t*)&Om[buf][2 * KC * LP + e] = t2;
+      } else {
+        Om[buf][e] = drm_to_lds<PREC>(omv.x);
+        Om[buf][e + 1] = drm_to_lds<PREC>(omv.y);
+      }
     }
   };
 
@@ -350,8 +378,20 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     for (int i = 0; i < NLD; ++i) {
       const int cc = i * (64 * VEC / RW) + lane / (RW / VEC);
       const int r = (lane % (RW / VEC)) * VEC;
+      if constexpr (PREC == P_BF16) {
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = to_lds<PREC>(xr[i][v]);
+        for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = bf16_rne(xr[i][v]);
+      } else if constexpr (X3) {
+        uint32_t a0, a1, a2, b0, b1, b2;
+        split3_pk(xr[i][0], xr[i][1], a0, a1, a2);
+        split3_pk(xr[i][2], xr[i][3], b0, b1, b2);
+        *(uint2*)&Xl[w][cc * ST + r] = uint2{a0, b0};
+        *(uint2*)&Xl[w][KC * ST + cc * ST + r] = uint2{a1, b1};
+        *(uint2*)&Xl[w][2 * KC * ST + cc * ST + r] = uint2{a2, b2};
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = to_lds<PREC>(xr[i][v]);
+      }
     }
   };
 
@@ -424,16 +464,16 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
       // six products t_i * t_j with i + j <= 2, smallest first
       s4 b0[NT], b1[NT], b2[NT];
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-        split3x4(om[(4 * g4 + 0) * LP + 16 * nt + l16], om[(4 * g4 + 1) * LP + 16 * nt + l16],
-                 om[(4 * g4 + 2) * LP + 16 * nt + l16], om[(4 * g4 + 3) * LP + 16 * nt + l16], b0[nt], b1[nt],
-                 b2[nt]);
+      for (int nt = 0; nt < NT; ++nt) {
+        const int o = 4 * g4 * LP + 16 * nt + l16;
+        b0[nt] = gather4(om + o, LP);
+        b1[nt] = gather4(om + KC * LP + o, LP);
+        b2[nt] = gather4(om + 2 * KC * LP + o, LP);
+      }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        s4 a0, a1, a2;
-        const int r = 16 * mt + l16;
-        split3x4(xw[(4 * g4 + 0) * ST + r], xw[(4 * g4 + 1) * ST + r], xw[(4 * g4 + 2) * ST + r],
-                 xw[(4 * g4 + 3) * ST + r], a0, a1, a2);
+        const int o = 4 * g4 * ST + 16 * mt + l16;
+        const s4 a0 = gather4(xw + o, ST), a1 = gather4(xw + KC * ST + o, ST), a2 = gather4(xw + 2 * KC * ST + o, ST);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           accv y = yacc[mt][nt];
@@ -478,9 +518,8 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
             tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
         }
       } else if constexpr (X3) {
-        const f4 q = *(const f4*)&xw[l16 * ST + 16 * ks + 4 * g4];
-        s4 b0, b1, b2;
-        split3x4(q.x, q.y, q.z, q.w, b0, b1, b2);
+        const int o = l16 * ST + 16 * ks + 4 * g4;
+        const s4 b0 = *(const s4*)&xw[o], b1 = *(const s4*)&xw[KC * ST + o], b2 = *(const s4*)&xw[2 * KC * ST + o];
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt) {
           accv t = tacc[mt];
