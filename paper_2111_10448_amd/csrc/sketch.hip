@@ -339,8 +339,11 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
   };
 
   // ---- global loads of one chunk (16-byte, coalesced along rows) ----
-  elem xr[NLD][VEC];
-  auto load_chunk = [&](int64_t ci) {
+  // NB register slots: with NB = 2 (sketch size <= 16, where registers allow)
+  // two chunks of X are in flight while one is computed
+  constexpr int NB = LP == 16 ? 2 : 1;
+  elem xr[NB][NLD][VEC];
+  auto load_chunk = [&](int64_t ci, int slot) {
     ChunkInfo ch = info(cx, ci);
     const elem* base = (const elem*)ch.ptr;
 #pragma unroll
@@ -354,43 +357,43 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
         if (colok && row < A.R) {
           if constexpr (VEC == 2) {
             const double2 v = *(const double2*)p;
-            xr[i][0] = v.x;
-            xr[i][1] = v.y;
+            xr[slot][i][0] = v.x;
+            xr[slot][i][1] = v.y;
           } else {
             const float4 v = *(const float4*)p;
-            xr[i][0] = v.x;
-            xr[i][1] = v.y;
-            xr[i][2] = v.z;
-            xr[i][3] = v.w;
+            xr[slot][i][0] = v.x;
+            xr[slot][i][1] = v.y;
+            xr[slot][i][2] = v.z;
+            xr[slot][i][3] = v.w;
           }
         } else {
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) xr[i][v] = 0;
+          for (int v = 0; v < VEC; ++v) xr[slot][i][v] = 0;
         }
       } else {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) xr[i][v] = (colok && row + v < A.R) ? p[v] : (elem)0;
+        for (int v = 0; v < VEC; ++v) xr[slot][i][v] = (colok && row + v < A.R) ? p[v] : (elem)0;
       }
     }
   };
-  auto store_chunk = [&]() {
+  auto store_chunk = [&](int slot) {
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
       const int cc = i * (64 * VEC / RW) + lane / (RW / VEC);
       const int r = (lane % (RW / VEC)) * VEC;
       if constexpr (PREC == P_BF16) {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = bf16_rne(xr[i][v]);
+        for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = bf16_rne(xr[slot][i][v]);
       } else if constexpr (X3) {
         uint32_t a0, a1, a2, b0, b1, b2;
-        split3_pk(xr[i][0], xr[i][1], a0, a1, a2);
-        split3_pk(xr[i][2], xr[i][3], b0, b1, b2);
+        split3_pk(xr[slot][i][0], xr[slot][i][1], a0, a1, a2);
+        split3_pk(xr[slot][i][2], xr[slot][i][3], b0, b1, b2);
         *(uint2*)&Xl[w][cc * ST + r] = uint2{a0, b0};
         *(uint2*)&Xl[w][KC * ST + cc * ST + r] = uint2{a1, b1};
         *(uint2*)&Xl[w][2 * KC * ST + cc * ST + r] = uint2{a2, b2};
       } else {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = to_lds<PREC>(xr[i][v]);
+        for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = to_lds<PREC>(xr[slot][i][v]);
       }
     }
   };
@@ -422,20 +425,28 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     store_omega(0);
     load_omega(cb + 1);
     store_omega(1);
-    load_chunk(cb);
+    load_chunk(cb, 0);
     load_omega(cb + 2);
+    if (NB == 2 && cb + 1 < ce) load_chunk(cb + 1, 1);
   }
 
-  int it = 0;
-  for (int64_t ci = cb; ci < ce; ++ci, ++it) {
+  // one chunk: slot is a constant at every call (the loop below is unrolled by NB)
+  auto chunk_step = [&](int64_t ci, int it, int slot) {
     // (a) stage this chunk in the wave's LDS tile and the Omega rows of chunk
-    //     ci + 2 (both loaded one iteration ago); one barrier per chunk
-    store_chunk();
+    //     ci + 2 (both loaded earlier); one barrier per chunk
+    store_chunk(slot);
     store_omega((it + 2) % 4);
     __syncthreads();
-    // (b) prefetch the next chunk and Omega three chunks ahead
-    if (ci + 1 < ce) load_chunk(ci + 1);
-    load_omega(ci + 3);
+    // (b) prefetch: Omega three chunks ahead, then the chunk NB ahead into the
+    //     slot just staged (loads retire in order, so the Omega rows the next
+    //     step stages never wait for the newest X chunk)
+    if constexpr (NB == 1) {
+      if (ci + 1 < ce) load_chunk(ci + 1, 0);
+      load_omega(ci + 3);
+    } else {
+      load_omega(ci + 3);
+      if (ci + 2 < ce) load_chunk(ci + 2, slot);
+    }
     // (c) finish the previous chunk's left sketch
     if (it >= 1) reduce_t((it - 1) & 1, ci - 1);
     // (d) matrix-core tiles
@@ -544,7 +555,17 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) tr[(16 * mt + acc_row<PREC>(g4, v)) * KC + l16] = tacc[mt][v];
+  };
+
+  int it = 0;
+  int64_t ci = cb;
+  if constexpr (NB == 2) {
+    for (; ci + 1 < ce; ci += 2, it += 2) {
+      chunk_step(ci, it, 0);
+      chunk_step(ci + 1, it + 1, 1);
+    }
   }
+  for (; ci < ce; ++ci, ++it) chunk_step(ci, it, 0);
   __syncthreads();
   if (it >= 1) reduce_t((it - 1) & 1, ce - 1);
 
