@@ -101,7 +101,7 @@ def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 30.0):
 _HOST = {}
 
 
-def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass"):
+def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass", drm="nested"):
     import torch
     import inputs
     import paper_2111_10448_amd as P
@@ -115,11 +115,15 @@ def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass"):
         _HOST.update(name=name, x=x, psi=psi, omega=omega)
         log(f"[bench] {name}: generated {x.nbytes / 1e9:.2f} GB on the host in {time.perf_counter() - t0:.1f} s")
     x, psi, omega = _HOST["x"], _HOST["psi"], _HOST["omega"]
-    fac = inputs.pack_factors(psi, omega, w.d)
+    if drm == "independent":   # the paper's per-split factors
+        ipsi, iomega = inputs.drm_factors_independent(w)
+        fac = inputs.pack_factors_independent(ipsi, iomega, w.d)
+    else:
+        fac = inputs.pack_factors(psi, omega, w.d)
     log(f"[bench] {name} {prec}: timing {steps} steps")
     xg = torch.from_numpy(x).to("cuda:0")
     torch.cuda.synchronize()
-    kw = dict(dtype=w.dtype, prec=prec, mid=mid)
+    kw = dict(dtype=w.dtype, prec=prec, mid=mid, drm=drm)
     if ranks_from is not None:
         kw["ranks"] = ranks_from
     elif w.rank is not None:
@@ -279,14 +283,19 @@ def main():
     }
     if not args.no_variants:
         var = {}
-        for wn, vp, mid in (("c2", "f64", "twosided"), ("c3_f64", "f64", "onepass"), ("c3", "f32", "onepass"),
-                            ("c3", "bf16x3", "onepass"), ("c3", "bf16", "onepass"), ("c4", "f32", "onepass"),
-                            ("c4", "bf16x3", "onepass")):
-            key = f"{wn}_{vp}" if mid == "onepass" else f"{wn}_{vp}_{mid}"
+        for wn, vp, mid, drm in (("c2", "f64", "twosided", "nested"), ("c2", "f64", "onepass", "independent"),
+                                 ("c3_f64", "f64", "onepass", "nested"), ("c3", "f32", "onepass", "nested"),
+                                 ("c3", "bf16x3", "onepass", "nested"), ("c3", "bf16", "onepass", "nested"),
+                                 ("c4", "f32", "onepass", "nested"), ("c4", "bf16x3", "onepass", "nested")):
+            key = f"{wn}_{vp}" + ("" if mid == "onepass" else f"_{mid}") + ("" if drm == "nested" else f"_{drm}")
             try:
-                rv = run_workload(wn, vp, max(3, args.steps // 2), 1, mid=mid)
-                kbv = rv["bytes"] / max(rv["launches_per_step"], 1)
-                var[key] = {"workload": wn, "sketch_arithmetic": vp, "middle_core": mid,
+                rv = run_workload(wn, vp, max(3, args.steps // 2), 1, mid=mid, drm=drm)
+                wv = rv["workload"]
+                # the independent scheme streams X once per pass group (max(m, d - m) groups)
+                groups = max((wv.d + 1) // 2, wv.d - (wv.d + 1) // 2) if drm == "independent" else 1
+                kbv = rv["bytes"] * groups / max(rv["launches_per_step"], 1)
+                var[key] = {"workload": wn, "sketch_arithmetic": vp, "middle_core": mid, "drm": drm,
+                            "sketch_launches_per_step": rv["launches_per_step"],
                            "sketch_kernel_ms": round(rv["kernel_ms"], 4),
                            "sketch_gbs": round(kbv / (rv["kernel_ms"] * 1e-3) / 1e9, 2),
                            "ms_per_step": round(rv["ms_per_step"], 4), "ranks": rv["ranks"],
