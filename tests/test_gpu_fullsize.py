@@ -65,19 +65,23 @@ def _tensor(w):
     return _TENSORS[w.name]
 
 
-def _run(w, prec, slabs=None):
+def _run(w, prec, slabs=None, mid="onepass", drm="nested", extra=None):
     import torch
     import paper_2111_10448_amd as P
     x = _tensor(w)
-    psi, omega = inputs.drm_factors(w)
-    fac = inputs.pack_factors(psi, omega, w.d)
+    if drm == "nested":
+        psi, omega = inputs.drm_factors(w)
+        fac = inputs.pack_factors(psi, omega, w.d)
+    else:
+        psi, omega = inputs.drm_factors_independent(w)
+        fac = inputs.pack_factors_independent(psi, omega, w.d)
     if slabs:
         bounds = inputs.slab_bounds(x.size, w.n[0], slabs)
         xs = [torch.from_numpy(x[f:f + c]).cuda() for f, c in bounds]
         xg = None
     else:
         xg = torch.from_numpy(x).cuda()
-    kw = dict(dtype=w.dtype, prec=prec)
+    kw = dict(dtype=w.dtype, prec=prec, mid=mid, drm=drm)
     if w.rank is not None:
         kw["ranks"] = w.ranks()
     else:
@@ -91,6 +95,8 @@ def _run(w, prec, slabs=None):
     m = O.middle_index(w.d)
     y = ctx.get_sketch(0, m)
     t = ctx.get_sketch(1, m)
+    if extra is not None:
+        extra["B"] = {k: ctx.get_sketch(2, k) for k in range(1, w.d)}
     if slabs:
         xg = torch.cat(xs)
         del xs
@@ -147,3 +153,31 @@ def test_c4_slabs_full_size():
     say(f"    sampled sketch max rel {worst:.2e}, tt_error {err:.3e}, ranks {ranks}")
     assert ranks == [1] + [8] * 7 + [1]
     assert err < 1e-5
+
+
+def test_c2_two_sided_sketches_full_size():
+    """d=6, n=32: B_m against Psi_m^T Y_R formed on the host from the GPU's Y_R, and the error level."""
+    w = inputs.WORKLOADS["c2"]
+    say("[gpu] full size c2 two-sided sketches")
+    ex = {}
+    x, psi, omega, y, t, err, ranks = _run(w, "f64", extra=ex)
+    m = O.middle_index(w.d)
+    psi_m = O.khatri_rao([psi[q] for q in range(m, 0, -1)])      # R_m x ell, first mode fastest
+    om_m = O.khatri_rao([omega[q] for q in range(w.d, m, -1)])   # C_m x ell
+    b_left = psi_m.T @ y                                         # Psi_m^T (X_m Omega_m)
+    b_right = t.T @ om_m                                         # (Psi_m^T X_m) Omega_m
+    e1 = np.linalg.norm(ex["B"][m] - b_left) / np.linalg.norm(b_left)
+    e2 = np.linalg.norm(ex["B"][m] - b_right) / np.linalg.norm(b_right)
+    say(f"    B_m vs Psi^T Y_R {e1:.2e}, vs T_m Omega_m {e2:.2e}")
+    assert e1 < 1e-10 and e2 < 1e-10
+
+
+@pytest.mark.parametrize("mid,drm", [("twosided", "nested"), ("onepass", "independent")])
+def test_c2_exact_rank_variants_full_size(mid, drm):
+    """Noiseless d=6, n=32: the two-sided middle core and the independent DRM scheme recover X to rounding."""
+    w = inputs.WORKLOADS["c2_exact"]
+    say(f"[gpu] full size c2_exact mid={mid} drm={drm}")
+    x, psi, omega, y, t, err, ranks = _run(w, "f64", mid=mid, drm=drm)
+    say(f"    tt_error {err:.3e}, ranks {ranks}")
+    assert ranks == [1] + [10] * 5 + [1]
+    assert err < 1e-11
