@@ -103,8 +103,13 @@ hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** R
 
 // ---- tt_error: one streaming pass over X ----
 // Block = 4 waves; a wave owns 128 consecutive rows (2 per lane) of X_m and
-// walks the block's column range one column at a time.
-template <typename T, int RK>
+// walks the block's column range.  PAIR (R even): a lane's two rows are one
+// aligned 2-element load.  The loop body has no branches: lanes past the last
+// row read a valid row and drop it (their L rows are zero).  Rt comes padded
+// to RK rows with zeros, so a column's RK entries are one contiguous run (wide
+// scalar loads).  Eight columns per step keep
+// eight loads in flight; every lane still adds its columns in increasing order.
+template <typename T, int RK, bool PAIR>
 __global__ __launch_bounds__(256) void k_tt_error(const T* __restrict__ x, int64_t R, int64_t C, int r,
                                                   const double* __restrict__ L, const double* __restrict__ Rt,
                                                   int gi_count, int gj_count, double* __restrict__ part) {
@@ -119,12 +124,12 @@ __global__ __launch_bounds__(256) void k_tt_error(const T* __restrict__ x, int64
     l0[k] = (ok0 && k < r) ? L[(int64_t)k * R + row] : 0.0;
     l1[k] = (ok1 && k < r) ? L[(int64_t)k * R + row + 1] : 0.0;
   }
-  const bool pair = ok1 && ((R & 1) == 0);   // aligned 2-element loads
-  double e2 = 0.0, x2 = 0.0;
-  for (int64_t col = cb; col < ce; ++col) {
-    const T* p = x + col * R + row;
-    double x0 = 0.0, x1 = 0.0;
-    if (pair) {
+  // rows read by this lane (clamped into the matrix; dropped via w0, w1)
+  const int64_t r0c = ok0 ? row : 0, r1c = ok1 ? row + 1 : 0;
+  const double w0 = ok0 ? 1.0 : 0.0, w1 = ok1 ? 1.0 : 0.0;
+  auto load2 = [&](int64_t col, double& x0, double& x1) {
+    if constexpr (PAIR) {
+      const T* p = x + col * R + r0c;
       if constexpr (sizeof(T) == 8) {
         const double2 v = *(const double2*)p;
         x0 = v.x;
@@ -135,20 +140,39 @@ __global__ __launch_bounds__(256) void k_tt_error(const T* __restrict__ x, int64
         x1 = v.y;
       }
     } else {
-      if (ok0) x0 = (double)p[0];
-      if (ok1) x1 = (double)p[1];
+      x0 = (double)x[col * R + r0c];
+      x1 = (double)x[col * R + r1c];
     }
-    const double* rc = Rt + (int64_t)r * col;
+    x0 *= w0;
+    x1 *= w1;
+  };
+  double e2 = 0.0, x2 = 0.0;
+  auto accum = [&](int64_t col, double x0, double x1) {
+    const double* rc = Rt + (int64_t)RK * col;
     double t0 = 0.0, t1 = 0.0;
 #pragma unroll
     for (int k = 0; k < RK; ++k) {
-      const double rv = k < r ? rc[k] : 0.0;
+      const double rv = rc[k];
       t0 += l0[k] * rv;
       t1 += l1[k] * rv;
     }
     const double d0 = x0 - t0, d1 = x1 - t1;
     e2 += d0 * d0 + d1 * d1;
     x2 += x0 * x0 + x1 * x1;
+  };
+  constexpr int U = 8;
+  int64_t col = cb;
+  for (; col + U <= ce; col += U) {
+    double xa[U], xb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) load2(col + u, xa[u], xb[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) accum(col + u, xa[u], xb[u]);
+  }
+  for (; col < ce; ++col) {
+    double a0, a1;
+    load2(col, a0, a1);
+    accum(col, a0, a1);
   }
   __shared__ double red[2][4];
   for (int o = 32; o > 0; o >>= 1) {
@@ -190,17 +214,37 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ pa
   }
 }
 
+// Rt (r x C, column-major) -> Rp (RK x C) with zero rows r..RK-1
+__global__ void k_pad_rt(const double* __restrict__ Rt, int r, int RK, int64_t C, double* __restrict__ Rp) {
+  const int64_t tot = (int64_t)RK * C;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t % RK);
+    Rp[t] = k < r ? Rt[(t / RK) * r + k] : 0.0;
+  }
+}
+
+static int rk_slot(int r) { return r <= 4 ? 4 : r <= 8 ? 8 : r <= 12 ? 12 : r <= 16 ? 16 : r <= 24 ? 24 : 32; }
+
+template <typename T, bool PAIR>
+static hipError_t launch_err_p(const T* x, int64_t R, int64_t C, int r, const double* L, const double* Rt, int gi,
+                               int gj, double* part, hipStream_t s) {
+  dim3 g((unsigned)(gi * gj)), b(256);
+  if (r <= 4) hipLaunchKernelGGL((k_tt_error<T, 4, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else if (r <= 8) hipLaunchKernelGGL((k_tt_error<T, 8, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else if (r <= 12) hipLaunchKernelGGL((k_tt_error<T, 12, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else if (r <= 16) hipLaunchKernelGGL((k_tt_error<T, 16, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else if (r <= 24) hipLaunchKernelGGL((k_tt_error<T, 24, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  else hipLaunchKernelGGL((k_tt_error<T, 32, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch_err(const T* x, int64_t R, int64_t C, int r, const double* L, const double* Rt, int gi,
                              int gj, double* part, hipStream_t s) {
-  dim3 g((unsigned)(gi * gj)), b(256);
-  if (r <= 4) hipLaunchKernelGGL((k_tt_error<T, 4>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else if (r <= 8) hipLaunchKernelGGL((k_tt_error<T, 8>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else if (r <= 12) hipLaunchKernelGGL((k_tt_error<T, 12>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else if (r <= 16) hipLaunchKernelGGL((k_tt_error<T, 16>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else if (r <= 24) hipLaunchKernelGGL((k_tt_error<T, 24>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else hipLaunchKernelGGL((k_tt_error<T, 32>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  return hipGetLastError();
+  // aligned pair loads need an even column length (and an aligned base)
+  const bool pair = (R % 2) == 0 && ((uintptr_t)x % (2 * sizeof(T))) == 0;
+  return pair ? launch_err_p<T, true>(x, R, C, r, L, Rt, gi, gj, part, s)
+              : launch_err_p<T, false>(x, R, C, r, L, Rt, gi, gj, part, s);
 }
 
 hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s) {
@@ -215,16 +259,20 @@ hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x
   const int r = c->r[split];
   const int gi = (int)((R + 511) / 512);
   const int gj = (int)std::max<int64_t>(1, std::min<int64_t>(C, (4096 + gi - 1) / gi));
-  double* part = nullptr;
+  double *part = nullptr, *Rp = nullptr;
+  const int RK = rk_slot(r);
   e = ws_alloc((void**)&part, sizeof(double) * 2 * ((int64_t)gi * gj + 1), s);
+  if (e == hipSuccess) e = ws_alloc((void**)&Rp, sizeof(double) * RK * C, s);
   if (e != hipSuccess) return e;
-  if (dtype == PSTT2_F64) e = launch_err((const double*)x, R, C, r, L, Rt, gi, gj, part, s);
-  else e = launch_err((const float*)x, R, C, r, L, Rt, gi, gj, part, s);
+  hipLaunchKernelGGL(k_pad_rt, dim3(grid_for(RK * C, 256)), dim3(256), 0, s, Rt, r, RK, C, Rp);
+  if (dtype == PSTT2_F64) e = launch_err((const double*)x, R, C, r, L, Rp, gi, gj, part, s);
+  else e = launch_err((const float*)x, R, C, r, L, Rp, gi, gj, part, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, gi * gj, part + 2 * (int64_t)gi * gj);
     e = hipMemcpyAsync(e2x2, part + 2 * (int64_t)gi * gj, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
   }
   ws_free(part, s);
+  ws_free(Rp, s);
   ws_free(ifb, s);
   hipError_t e2 = hipStreamSynchronize(s);
   return e != hipSuccess ? e : e2;
