@@ -452,7 +452,8 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   c->gj_max = std::max(1, c->ncu * wg_per_cu / c->gi);
   const size_t psz = c->prec == PSTT2_P_F64 ? 8 : 4;
   if ((e = hipMalloc(&c->ypart, psz * c->gj_max * c->ell * c->R)) != hipSuccess) return bail(e, "hipMalloc(ypart)");
-  if ((e = hipMalloc(&c->tpart, psz * c->gi * c->ell * c->C)) != hipSuccess) return bail(e, "hipMalloc(tpart)");
+  if ((e = hipMalloc(&c->tpart, psz * (c->gi * c->ell * c->C + kTPartPad))) != hipSuccess)
+    return bail(e, "hipMalloc(tpart)");
   c->L4 = (c->ell + 3) / 4 * 4;
   if ((e = hipMalloc(&c->om_tab, sizeof(double) * c->C * c->L4)) != hipSuccess) return bail(e, "hipMalloc(omega)");
   if ((e = build_omega_table(base_args(c), c->L4, c->om_tab, c->stream)) != hipSuccess)
@@ -927,7 +928,7 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   a.seg[0].ncols = c->C;
   a.seg[0].chunk0 = 0;
   a.ypart = take((int64_t)a.gj_count * rm * c->R, false);
-  a.tpart = take((int64_t)a.gi_count * rm * c->C, false);
+  a.tpart = take((int64_t)a.gi_count * rm * c->C + kTPartPad, false);
   double* U = take(c->R * rm, true);    // Lbar_m = gbar_m Rt^T        (R x r_m)
   double* Vt = take(c->C * rm, true);   // (L_m^T gbar_m)^T           (C x r_m)
   if (e == hipSuccess) e = launch_sketch(PSTT2_P_F64, 0, a, s);

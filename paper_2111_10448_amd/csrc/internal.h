@@ -56,7 +56,7 @@ struct SketchArgs {
   int64_t psi_off[PSTT2_MAX_D];    // offset of psi_q (q = 1..d-1) at index q-1
   int64_t omega_off[PSTT2_MAX_D];  // offset of omega_q (q = 2..d) at index q-1
   void* ypart;       // [gj][c][row], ell columns
-  void* tpart;       // [gi][a][gcol], ell rows, indexed by global column
+  void* tpart;       // [gi][a][gcol], ell rows, indexed by global column; then kTPartPad spare entries
   int64_t C;         // columns of X_m (for the tpart stride)
   const double* om_tab;  // Omega_m(col, c) table, C x L4, FP64
   int32_t L4;            // its row stride: ell rounded up to a multiple of 4
@@ -66,6 +66,10 @@ struct SketchArgs {
 
 // Launch the streaming dual-sketch kernel for the configured precision.
 hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s);
+// Entries after the T partials that the sketch kernels' idle lanes store to (never
+// read): every memory operation in the chunk loop is then unconditional, which
+// lets the compiler wait only for the loads it needs.
+constexpr int64_t kTPartPad = 2048;
 // Build the Omega_m table (C x L4, FP64) from the factors.
 hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream_t s);
 // Per-precision launch geometry: rows of X_m per workgroup, threads per

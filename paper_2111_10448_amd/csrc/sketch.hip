@@ -253,6 +253,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
   constexpr int NTH = NWS * 64;          // threads
   constexpr int NRT = (LP * KC + NTH - 1) / NTH;   // T outputs per thread in the reduction
   static_assert(KC * LP / 2 <= NTH, "one Omega pair per thread");
+  static_assert(sizeof(elem) == 4 && VEC == 4, "FP32 tensors, 16-byte loads of four entries");
   constexpr int NPL = E::NPL;                // bf16 planes of X and Omega in LDS (1 otherwise)
   __shared__ __align__(16) lds_t Xl[NWS][NPL * KC * ST];
   __shared__ acc Tred[2][NWS][LP * KC];
@@ -309,18 +310,36 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
   // ones past L4 are skipped).  Loaded one iteration before they are written
   // to LDS, so waiting for them never waits for the X prefetch (loads retire
   // in order).
+  // NB register slots: with NB = 2 (sketch size <= 16, where registers allow)
+  // two chunks of X are in flight while one is computed.  UNC: every memory
+  // operation of the chunk loop is issued by every lane (addresses clamped
+  // into the data, values zeroed when staged, idle lanes storing to spare
+  // entries), so no branch separates one step's loads and stores from the
+  // next and the loop waits only for the loads it needs.  Measured: a gain
+  // with two chunks in flight, a small loss with one.
+  constexpr int NB = LP == 16 ? 2 : 1;
+  constexpr bool UNC = NB == 2;
   double2 omv;
+  bool omok = true;
   auto load_omega = [&](int64_t ci) {
     const int e = 2 * threadIdx.x;
-    omv = double2{0.0, 0.0};
-    if (e < KC * LP && ci < ce) {
-      ChunkInfo ch = info(co, ci);
+    if constexpr (UNC) {
+      ChunkInfo ch = info(co, ci < ce ? ci : ce - 1);
       const int col = e / LP, c = e % LP;
-      if (col < ch.ncols && c < A.L4) omv = *(const double2*)&A.om_tab[(ch.gcol0 + col) * A.L4 + c];
+      omok = e < KC * LP && ci < ce && col < ch.ncols && c < A.L4;
+      omv = *(const double2*)&A.om_tab[(ch.gcol0 + (omok ? col : 0)) * A.L4 + (omok ? c : 0)];
+    } else {
+      omv = double2{0.0, 0.0};
+      if (e < KC * LP && ci < ce) {
+        ChunkInfo ch = info(co, ci);
+        const int col = e / LP, c = e % LP;
+        if (col < ch.ncols && c < A.L4) omv = *(const double2*)&A.om_tab[(ch.gcol0 + col) * A.L4 + c];
+      }
     }
   };
   auto store_omega = [&](int buf) {
     const int e = 2 * threadIdx.x;
+    if (UNC && !omok) omv = double2{0.0, 0.0};
     if (e < KC * LP) {
       if constexpr (PREC == P_BF16) {
         Om[buf][e] = bf16_rne((float)omv.x);
@@ -339,10 +358,8 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
   };
 
   // ---- global loads of one chunk (16-byte, coalesced along rows) ----
-  // NB register slots: with NB = 2 (sketch size <= 16, where registers allow)
-  // two chunks of X are in flight while one is computed
-  constexpr int NB = LP == 16 ? 2 : 1;
   elem xr[NB][NLD][VEC];
+  bool xok[NB][NLD][ALIGNED ? 1 : VEC];   // loaded entry lies in the matrix
   auto load_chunk = [&](int64_t ci, int slot) {
     ChunkInfo ch = info(cx, ci);
     const elem* base = (const elem*)ch.ptr;
@@ -352,33 +369,45 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
       const int r = (lane % (RW / VEC)) * VEC;
       const int64_t row = row0w + r;
       const bool colok = cc < ch.ncols;
-      const elem* p = base + (ch.lcol0 + cc) * A.R + row;
-      if constexpr (ALIGNED) {
-        if (colok && row < A.R) {
-          if constexpr (VEC == 2) {
-            const double2 v = *(const double2*)p;
-            xr[slot][i][0] = v.x;
-            xr[slot][i][1] = v.y;
-          } else {
-            const float4 v = *(const float4*)p;
-            xr[slot][i][0] = v.x;
-            xr[slot][i][1] = v.y;
-            xr[slot][i][2] = v.z;
-            xr[slot][i][3] = v.w;
-          }
+      const elem* col = base + (ch.lcol0 + (colok ? cc : 0)) * A.R;
+      if constexpr (!UNC) {
+        if constexpr (ALIGNED) {
+          float4 v = float4{0.0f, 0.0f, 0.0f, 0.0f};
+          if (colok && row < A.R) v = *(const float4*)(col + row);
+          xr[slot][i][0] = v.x;
+          xr[slot][i][1] = v.y;
+          xr[slot][i][2] = v.z;
+          xr[slot][i][3] = v.w;
         } else {
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) xr[slot][i][v] = 0;
+          for (int v = 0; v < VEC; ++v) xr[slot][i][v] = (colok && row + v < A.R) ? col[row + v] : (elem)0;
         }
+      } else if constexpr (ALIGNED) {
+        const bool ok = colok && row < A.R;
+        const float4 v = *(const float4*)(col + (ok ? row : 0));
+        xr[slot][i][0] = v.x;
+        xr[slot][i][1] = v.y;
+        xr[slot][i][2] = v.z;
+        xr[slot][i][3] = v.w;
+        xok[slot][i][0] = ok;
       } else {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) xr[slot][i][v] = (colok && row + v < A.R) ? p[v] : (elem)0;
+        for (int v = 0; v < VEC; ++v) {
+          const bool ok = colok && row + v < A.R;
+          xr[slot][i][v] = col[ok ? row + v : 0];
+          xok[slot][i][v] = ok;
+        }
       }
     }
   };
   auto store_chunk = [&](int slot) {
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
+      if constexpr (UNC) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          if (!xok[slot][i][ALIGNED ? 0 : v]) xr[slot][i][v] = (elem)0;
+      }
       const int cc = i * (64 * VEC / RW) + lane / (RW / VEC);
       const int r = (lane % (RW / VEC)) * VEC;
       if constexpr (PREC == P_BF16) {
@@ -398,19 +427,24 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     }
   };
 
-  auto reduce_t = [&](int buf, int64_t ci) {
+  // live = false (before the first chunk) sends every store to the spare entries
+  auto reduce_t = [&](int buf, int64_t ci, bool live) {
     ChunkInfo ch = info(ct, ci);
+    part* tp = (part*)A.tpart;
+    const int64_t spare = (int64_t)A.gi_count * A.ell * A.C;
 #pragma unroll
     for (int q = 0; q < NRT; ++q) {
       const int t = threadIdx.x + NTH * q;
-      if (t < LP * KC) {
-        const int a = t / KC, col = t % KC;
-        acc s = 0;
+      const int tc = t < LP * KC ? t : 0;
+      const int a = tc / KC, col = tc % KC;
+      acc s = 0;
 #pragma unroll
-        for (int ww = 0; ww < NWS; ++ww) s += Tred[buf][ww][a * KC + col];
-        if (a < A.ell && col < ch.ncols)
-          ((part*)A.tpart)[((int64_t)gi * A.ell + a) * A.C + ch.gcol0 + col] = (part)s;
-      }
+      for (int ww = 0; ww < NWS; ++ww) s += Tred[buf][ww][a * KC + col];
+      const bool ok = live && t < LP * KC && a < A.ell && col < ch.ncols;
+      if constexpr (UNC)
+        tp[ok ? ((int64_t)gi * A.ell + a) * A.C + ch.gcol0 + col : spare + t] = (part)s;
+      else if (ok)
+        tp[((int64_t)gi * A.ell + a) * A.C + ch.gcol0 + col] = (part)s;
     }
   };
 
@@ -427,7 +461,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     store_omega(1);
     load_chunk(cb, 0);
     load_omega(cb + 2);
-    if (NB == 2 && cb + 1 < ce) load_chunk(cb + 1, 1);
+    if (NB == 2) load_chunk(cb + 1 < ce ? cb + 1 : ce - 1, 1);
   }
 
   // one chunk: slot is a constant at every call (the loop below is unrolled by NB)
@@ -443,12 +477,12 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     if constexpr (NB == 1) {
       if (ci + 1 < ce) load_chunk(ci + 1, 0);
       load_omega(ci + 3);
-    } else {
+    } else {   // the last chunk again at the end: the loads stay unconditional
       load_omega(ci + 3);
-      if (ci + 2 < ce) load_chunk(ci + 2, slot);
+      load_chunk(ci + 2 < ce ? ci + 2 : ce - 1, slot);
     }
     // (c) finish the previous chunk's left sketch
-    if (it >= 1) reduce_t((it - 1) & 1, ci - 1);
+    if (UNC || it >= 1) reduce_t((it - 1) & 1, it >= 1 ? ci - 1 : ci, it >= 1);
     // (d) matrix-core tiles
     const lds_t* xw = Xl[w];
     const lds_t* om = Om[it % 4];
@@ -567,7 +601,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
   }
   for (; ci < ce; ++ci, ++it) chunk_step(ci, it, 0);
   __syncthreads();
-  if (it >= 1) reduce_t((it - 1) & 1, ce - 1);
+  if (it >= 1) reduce_t((it - 1) & 1, ce - 1, true);
 
   // ---- right-sketch partial of this workgroup ----
   part* yp = (part*)A.ypart;
