@@ -40,11 +40,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+FP64_KERNEL_BEGIN = "// FP64 kernel with the sketch size covered exactly"
+FP64_KERNEL_END = "template <int PREC, int LP>\nstatic hipError_t launch_t("
+
+
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2111_10448_amd", "csrc", "sketch.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+    """Hash of the FP64 sketch kernel's source: the kernel, its launcher and the launch-geometry rule."""
+    with open(os.path.join(ROOT, "paper_2111_10448_amd", "csrc", "sketch.hip")) as f:
+        src = f.read()
+    a, b = src.find(FP64_KERNEL_BEGIN), src.find(FP64_KERNEL_END)
+    text = src[a:b] if 0 <= a < b else src
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def traffic_from_profiles(workload: str, launches_per_step: int):

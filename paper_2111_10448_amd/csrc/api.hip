@@ -43,6 +43,7 @@ struct pstt2_ctx {
   std::vector<double*> Tk;     // Tk[k], k = m+1..d-1, C_k x ell (Tk[m] aliases Tt)
   std::vector<double*> basis;  // Q_k (k < m) or P_k (k >= m)
   Arena arena;                 // recovery workspace: sketches, bases, temporaries
+  Arena varena;                // workspace of pstt2_vjp (rewound at every call)
   double* Bk = nullptr;        // two-sided sketches, split k at Bk + k ell^2 (ell x ell)
   int64_t* chain_dev = nullptr;  // per split: factor offsets of its left / right DRM chains, then n
   double* H = nullptr;         // two-sided middle sketch, (ell n_m) x ell (TWOSIDED only)
@@ -539,6 +540,7 @@ void pstt2_destroy(pstt2_ctx* c) {
   }
   free_recovery(c);
   arena_release(&c->arena, c->stream);
+  arena_release(&c->varena, c->stream);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(c->fac);
   (void)hipFree(c->Y);
@@ -866,21 +868,19 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   const int* r = c->ranks;
   const int64_t* Rk = c->Rk;
   auto Ck = [&](int k) { return c->N / Rk[k]; };
-  std::vector<void*> ws;
-  hipError_t e = hipSuccess;
+  // every temporary comes from the context's adjoint arena (pstt2_vjp returns
+  // only after its stream is idle, so the next call may rewind it)
+  hipError_t e = arena_begin(&c->varena, s);
+  ArenaScope arena_scope(&c->varena);
   auto take = [&](int64_t count, bool zero) -> double* {
     void* p = nullptr;
     if (e != hipSuccess) return nullptr;
-    e = hipMallocAsync(&p, sizeof(double) * std::max<int64_t>(count, 1), s);
+    e = ws_alloc(&p, sizeof(double) * std::max<int64_t>(count, 1), s);
     if (e != hipSuccess) return nullptr;
-    ws.push_back(p);
     if (zero) e = hipMemsetAsync(p, 0, sizeof(double) * std::max<int64_t>(count, 1), s);
     return (double*)p;
   };
-  auto release = [&]() {
-    for (void* p : ws) (void)hipFreeAsync(p, s);
-    ws.clear();
-  };
+  auto release = [&]() {};
 #define VJPCK(call)                        \
   do {                                     \
     if (e == hipSuccess) e = (call);       \
