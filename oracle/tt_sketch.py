@@ -349,7 +349,7 @@ def middle_core_twosided(y_r: np.ndarray, psi_prev: np.ndarray, q_prev: np.ndarr
 
 
 # ----------------------------------------------------------------------------
-# The driver
+# The top-level routine
 # ----------------------------------------------------------------------------
 
 def _clamp_ranks(n, ranks, ell):

@@ -423,7 +423,7 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   {
     // keep stream-ordered workspace in the device's default pool between
     // synchronisations (the recovery and the error pass allocate and free
-    // small buffers every call; returning them to the driver costs ~0.3 ms)
+    // small buffers every call; returning them to the HIP runtime costs ~0.3 ms)
     hipMemPool_t pool = nullptr;
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
