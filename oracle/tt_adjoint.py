@@ -9,18 +9,25 @@ forward pass: each basis is then the thin QR factor (sign-fixed, diag R >= 0)
 of the first r_k pivoted columns of its sketch, which is the leading part of
 the pivoted factor that the forward pass uses (Algorithm PSTT, CPQR step).
 
+Both DRM schemes (nested and independent Khatri-Rao factors) are covered
+through the DRM object, and both one-pass middle-core rules: the rule of
+equation "onepass_final_core" (middle="onepass") and the two-sided rule that
+also sketches the leading outer mode with split (m-1)'s left DRM
+(middle="twosided", oracle.tt_sketch.middle_core_twosided).
+
 Contents
   pstt2_frozen   numpy forward X -> TT cores with given pivots and ranks; every
                  step is a call into oracle.tt_sketch (sketches of Section 3.2,
                  cores by equation "core" and its row mirror, middle core by
-                 equation "onepass_final_core" on the middle unfolding).
+                 equation "onepass_final_core" or the two-sided rule).
   pstt2_vjp      J^T gbar and the gradient of ||X - X~||_F^2, by torch CPU FP64
                  autograd of an independent torch transcription of the same
                  forward pass.
 
 Parity pins (tests/test_oracle_adjoint.py): pstt2_frozen reproduces pstt2's
 cores; pstt2_vjp agrees with central finite differences of pstt2_frozen in
-random directions and, on a 4096-entry tensor, entry by entry.
+random directions and, on a 4096-entry tensor, entry by entry, for each
+middle-core rule and DRM scheme.
 """
 from __future__ import annotations
 
@@ -40,7 +47,8 @@ def _frozen_basis(s: np.ndarray, piv: np.ndarray, r: int) -> np.ndarray:
     return q * sgn[None, :]
 
 
-def pstt2_frozen(x: np.ndarray, n: Sequence[int], drm, ranks: Sequence[int], piv: Dict[int, np.ndarray]):
+def pstt2_frozen(x: np.ndarray, n: Sequence[int], drm, ranks: Sequence[int], piv: Dict[int, np.ndarray],
+                 middle: str = "onepass"):
     """PSTT2-onepass cores of X with the pivots and ranks of an earlier pass held fixed."""
     x = np.asarray(x, dtype=np.float64).reshape(-1)
     n = tuple(int(v) for v in n)
@@ -62,11 +70,16 @@ def pstt2_frozen(x: np.ndarray, n: Sequence[int], drm, ranks: Sequence[int], piv
                         else O.outer_core_right(p[k - 1], p[k], n[k - 1]))
     om = drm.omega_dense(m, d)
     y_r = O.sketch_right_dense(x, n, m, om)
-    cores[m - 1] = O.middle_core_onepass(y_r, om, q[m - 1], p[m], n[m - 1])
+    if middle == "twosided" and m >= 2:
+        cores[m - 1] = O.middle_core_twosided(y_r, drm.psi_dense(m - 1), q[m - 1], om, p[m], n[m - 1])
+    elif middle in ("onepass", "twosided"):
+        cores[m - 1] = O.middle_core_onepass(y_r, om, q[m - 1], p[m], n[m - 1])
+    else:
+        raise ValueError(middle)
     return cores
 
 
-def _torch_forward(xt, n, drm, ranks, piv):
+def _torch_forward(xt, n, drm, ranks, piv, middle="onepass"):
     """Torch transcription of pstt2_frozen (same steps, differentiable in X)."""
     import torch
     d = len(n)
@@ -111,10 +124,21 @@ def _torch_forward(xt, n, drm, ranks, piv):
     ell = om.shape[1]
     rp = q[m - 1].shape[0]
     y3 = fres(y_r, (rp, n[m - 1], ell))
-    z = fres(torch.einsum("ra,rjc->ajc", q[m - 1], y3), (r[m - 1] * n[m - 1], ell))
-    a = p[m].T @ om
-    # G = Z A^+ with A^+ = A^T (A A^T)^{-1} (A has full row rank r_m <= ell)
-    g = torch.linalg.solve(a @ a.T, a @ z.T).T
+    if middle == "twosided" and m >= 2:
+        # H = Y3 x_1 Psi'^T; G = H x_1 (Psi'^T Q)^+ x_3 (Omega^T P)^+, each
+        # pseudo-inverse of a full-column-rank B written as (B^T B)^{-1} B^T
+        psi = t(drm.psi_dense(m - 1))
+        h = torch.einsum("ra,rjc->ajc", psi, y3)
+        b1 = psi.T @ q[m - 1]
+        b3 = om.T @ p[m]
+        w1 = torch.linalg.solve(b1.T @ b1, b1.T)
+        w3 = torch.linalg.solve(b3.T @ b3, b3.T)
+        g = fres(torch.einsum("pa,ajc,qc->pjq", w1, h, w3), (r[m - 1] * n[m - 1], r[m]))
+    else:
+        z = fres(torch.einsum("ra,rjc->ajc", q[m - 1], y3), (r[m - 1] * n[m - 1], ell))
+        a = p[m].T @ om
+        # G = Z A^+ with A^+ = A^T (A A^T)^{-1} (A has full row rank r_m <= ell)
+        g = torch.linalg.solve(a @ a.T, a @ z.T).T
     cores[m - 1] = fres(g, (r[m - 1], n[m - 1], r[m]))
     # X~ by the entry formula, swept left to right (Section 2.2)
     mm = torch.ones((1, 1), dtype=torch.float64)
@@ -125,7 +149,7 @@ def _torch_forward(xt, n, drm, ranks, piv):
 
 
 def pstt2_vjp(x: np.ndarray, n: Sequence[int], drm, ranks: Sequence[int], piv: Dict[int, np.ndarray],
-              gbar: Optional[np.ndarray] = None) -> np.ndarray:
+              gbar: Optional[np.ndarray] = None, middle: str = "onepass") -> np.ndarray:
     """J^T gbar (J = dX~/dX, pivots and ranks frozen), or with gbar None the gradient of ||X - X~||_F^2.
 
     All arrays are flat column-major FP64.
@@ -133,7 +157,7 @@ def pstt2_vjp(x: np.ndarray, n: Sequence[int], drm, ranks: Sequence[int], piv: D
     import torch
     n = tuple(int(v) for v in n)
     xt = torch.tensor(np.asarray(x, dtype=np.float64).reshape(-1), requires_grad=True)
-    xtil = _torch_forward(xt, n, drm, ranks, piv)
+    xtil = _torch_forward(xt, n, drm, ranks, piv, middle)
     if gbar is None:
         loss = torch.sum((xt - xtil) ** 2)
         (gx,) = torch.autograd.grad(loss, xt)
@@ -142,9 +166,9 @@ def pstt2_vjp(x: np.ndarray, n: Sequence[int], drm, ranks: Sequence[int], piv: D
     return gx.detach().numpy().copy()
 
 
-def reconstruct_frozen_torch(x, n, drm, ranks, piv) -> np.ndarray:
+def reconstruct_frozen_torch(x, n, drm, ranks, piv, middle="onepass") -> np.ndarray:
     """X~ from the torch transcription (no gradient): ties the two forward passes together."""
     import torch
     with torch.no_grad():
         xt = torch.as_tensor(np.asarray(x, dtype=np.float64).reshape(-1))
-        return _torch_forward(xt, tuple(int(v) for v in n), drm, ranks, piv).numpy().copy()
+        return _torch_forward(xt, tuple(int(v) for v in n), drm, ranks, piv, middle).numpy().copy()
