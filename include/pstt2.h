@@ -89,7 +89,7 @@ typedef enum { PSTT2_MID_ONEPASS = 0, PSTT2_MID_TWOPASS = 1, PSTT2_MID_TWOSIDED 
  *                pass forms one right sketch per split k <= m and one left
  *                sketch per split k >= m (d products per tile), each slab read
  *                once per pair of them.
- * The adjoint (pstt2_vjp) covers NESTED. */
+ * The adjoint (pstt2_vjp) covers both. */
 typedef enum { PSTT2_DRM_NESTED = 0, PSTT2_DRM_INDEPENDENT = 1 } pstt2_drm;
 
 typedef struct {
@@ -166,11 +166,14 @@ pstt2_status pstt2_middle_pass(pstt2_ctx* ctx, tt_cores* cores, const void* x_de
 /* Vector-Jacobian product of the one-pass map X -> X~ (the cores returned by
  * the last pstt2_recover of this context, reconstructed by the entry formula
  * of Section 2.2), with the pivots and ranks of that recovery held fixed.
- * X~ depends on X only through the two sketches of the middle unfolding, so
+ * NESTED: X~ depends on X only through the two sketches of the middle
+ * unfolding, so
  *   J^T gbar = Ybar Omega_m^T + Psi_m Tbar_m,
  * where (Ybar, Tbar_m) are the cotangents of Y_R and T_m obtained by running
- * the recovery (least squares, outer cores, QR of the pivoted sketch columns,
- * derived sketches) backwards in FP64 on the GPU.
+ * the recovery (least squares or the two-sided pseudo-inverse products, outer
+ * cores, QR of the pivoted sketch columns, derived sketches) backwards in FP64
+ * on the GPU.  INDEPENDENT: the same with one such pair of terms per pass
+ * group, each with the factors that group sketched with.
  *   gbar_dev != NULL: gx_dev = J^T gbar (gbar and gx have X's shape and dtype);
  *                     x_dev is not read and may be NULL.
  *   gbar_dev == NULL: gx_dev = gradient of ||X - X~||_F^2 with respect to X,
@@ -178,8 +181,7 @@ pstt2_status pstt2_middle_pass(pstt2_ctx* ctx, tt_cores* cores, const void* x_de
  *                     tensor that was sketched.
  * gx_dev is caller-owned device memory of N entries of the context's dtype.
  * Uses stream-ordered device workspace (about 8 N bytes).  sync.
- * Errors: ESTATE (no successful pstt2_recover; a two-pass or two-sided middle core;
- *         the independent DRM scheme),
+ * Errors: ESTATE (no successful pstt2_recover; a two-pass middle core),
  * EINVAL (null pointers, cores not from this context), ENOMEM, EDEVICE. */
 pstt2_status pstt2_vjp(pstt2_ctx* ctx, const tt_cores* cores, const void* x_dev, const void* gbar_dev,
                        void* gx_dev);

@@ -222,8 +222,9 @@ class PSTT2:
         self._keep.append(x)
 
     def vjp(self, tt: "TT", x=None, gbar=None):
-        """J^T gbar for X~ = the one-pass approximation (pivots and ranks of the last
-        recover held fixed); with gbar None, the gradient of ||X - X~||_F^2 (needs x).
+        """J^T gbar for X~ = the one-pass approximation (either one-pass middle-core
+        rule, either DRM scheme; pivots and ranks of the last recover held fixed);
+        with gbar None, the gradient of ||X - X~||_F^2 (needs x).
         Returns a flat CUDA tensor of the context's dtype."""
         torch = _torch()
         ref = gbar if gbar is not None else x
@@ -337,15 +338,19 @@ def _make_function():
     class PSTT2Reconstruct(torch.autograd.Function):
         """X -> X~ (PSTT2-onepass then the entry formula) with the hand-written adjoint.
 
-        forward(x, n, ell, factors, prec, ranks, eps, rmax): x is a flat column-major
-        CUDA tensor; returns X~ in x's dtype.  backward runs pstt2_vjp with the
+        forward(x, n, ell, factors, prec, ranks, eps, rmax, mid, drm): x is a flat
+        column-major CUDA tensor; mid is "onepass" or "twosided", drm "nested" or
+        "independent"; returns X~ in x's dtype.  backward runs pstt2_vjp with the
         forward pass's pivots and ranks held fixed; gradients flow to x only.
         """
 
         @staticmethod
-        def forward(ctx, x, n, ell, factors, prec=None, ranks=None, eps=None, rmax=0):
+        def forward(ctx, x, n, ell, factors, prec=None, ranks=None, eps=None, rmax=0, mid="onepass",
+                    drm="nested"):
+            if mid == "twopass":
+                raise ValueError("the differentiable path covers the one-pass middle cores (onepass, twosided)")
             dtype = "f64" if _dtype_code(x) == L.F64 else "f32"
-            p = PSTT2(n, ell, factors, dtype=dtype, prec=prec, ranks=ranks, eps=eps, rmax=rmax)
+            p = PSTT2(n, ell, factors, dtype=dtype, prec=prec, ranks=ranks, eps=eps, rmax=rmax, mid=mid, drm=drm)
             xf = x.detach().reshape(-1)
             p.sketch(xf)
             tt = p.recover()
@@ -358,7 +363,7 @@ def _make_function():
             gx = ctx.pstt2.vjp(ctx.tt, gbar=gout.contiguous().reshape(-1))
             ctx.tt.free()
             ctx.pstt2.close()
-            return gx.view_as(gout), None, None, None, None, None, None, None
+            return gx.view_as(gout), None, None, None, None, None, None, None, None, None
 
     return PSTT2Reconstruct
 
@@ -376,6 +381,7 @@ def __getattr__(name):
 
 
 def pstt2_reconstruct(x, n: Sequence[int], ell: int, factors: np.ndarray, *, prec: Optional[str] = None,
-                      ranks: Optional[Sequence[int]] = None, eps: Optional[float] = None, rmax: int = 0):
+                      ranks: Optional[Sequence[int]] = None, eps: Optional[float] = None, rmax: int = 0,
+                      mid: str = "onepass", drm: str = "nested"):
     """Differentiable X~ = PSTT2-onepass approximation of x (see PSTT2Reconstruct)."""
-    return __getattr__("PSTT2Reconstruct").apply(x, list(n), int(ell), factors, prec, ranks, eps, rmax)
+    return __getattr__("PSTT2Reconstruct").apply(x, list(n), int(ell), factors, prec, ranks, eps, rmax, mid, drm)

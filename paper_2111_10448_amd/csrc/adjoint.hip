@@ -430,8 +430,10 @@ __global__ void k_derive_right_adj(const double* __restrict__ Tbk, double* __res
 }
 
 // ---- B3: gx(row, col) = sum_c Ybar(row, c) Omega(col, c) + sum_a Psi(row, a) Tbar(col, a)
-//                         [ + 2 (x - X~) for the fused loss ] ----
+//                         [ + 2 (x - X~) for the fused loss ] [ + gx for ACC ] ----
 // Block = 256 threads = 256 consecutive rows; columns in groups of 16 staged in LDS.
+// A null Yb or Tbt drops that term (a pass group of the independent scheme
+// with only one side); ACC adds into gx (the later groups).
 struct AdjOutArgs {
   int64_t R, C;
   int ell, r, L4, prec, m;
@@ -457,7 +459,7 @@ __device__ __forceinline__ double psi_prod(const AdjOutArgs& A, int64_t row, int
   return v;
 }
 
-template <typename T, bool FUSED>
+template <typename T, bool FUSED, bool ACC>
 __global__ __launch_bounds__(256) void k_adj_out(const AdjOutArgs A, const T* __restrict__ x, T* __restrict__ gx) {
   constexpr int MX = PSTT2_MAX_ELL, CB = 16;
   __shared__ double om[CB][MX], tb[CB][MX], rt[CB][MX];
@@ -465,11 +467,12 @@ __global__ __launch_bounds__(256) void k_adj_out(const AdjOutArgs A, const T* __
   const int64_t gj = blockIdx.x / ((A.R + 255) / 256);
   const int64_t row = gi * 256 + threadIdx.x;
   const bool ok = row < A.R;
+  const bool hy = A.Yb != nullptr, ht = A.Tbt != nullptr;
   double yb[MX], ps[MX], lr[MX];
 #pragma unroll
   for (int c = 0; c < MX; ++c) {
-    yb[c] = (ok && c < A.ell) ? A.Yb[(int64_t)c * A.R + row] : 0.0;
-    ps[c] = (ok && c < A.ell) ? drm_eff(psi_prod(A, row, c), A.prec) : 0.0;
+    yb[c] = (hy && ok && c < A.ell) ? A.Yb[(int64_t)c * A.R + row] : 0.0;
+    ps[c] = (ht && ok && c < A.ell) ? drm_eff(psi_prod(A, row, c), A.prec) : 0.0;
     lr[c] = (FUSED && ok && c < A.r) ? A.L[(int64_t)c * A.R + row] : 0.0;
   }
   const int64_t cb = gj * A.C / A.gj, ce = (gj + 1) * A.C / A.gj;
@@ -479,8 +482,8 @@ __global__ __launch_bounds__(256) void k_adj_out(const AdjOutArgs A, const T* __
       const int j = t / MX, c = t % MX;
       const int64_t col = c0 + j;
       const bool cok = col < ce;
-      om[j][c] = (cok && c < A.ell) ? drm_eff(A.om_tab[col * A.L4 + c], A.prec) : 0.0;
-      tb[j][c] = (cok && c < A.ell) ? A.Tbt[(int64_t)c * A.C + col] : 0.0;
+      om[j][c] = (hy && cok && c < A.ell) ? drm_eff(A.om_tab[col * A.L4 + c], A.prec) : 0.0;
+      tb[j][c] = (ht && cok && c < A.ell) ? A.Tbt[(int64_t)c * A.C + col] : 0.0;
       rt[j][c] = (FUSED && cok && c < A.r) ? A.Rt[c + (int64_t)A.r * col] : 0.0;
     }
     __syncthreads();
@@ -494,6 +497,7 @@ __global__ __launch_bounds__(256) void k_adj_out(const AdjOutArgs A, const T* __
       }
       const int64_t f = (c0 + j) * A.R + row;
       if (FUSED) s += 2.0 * ((double)x[f] - xt);
+      if (ACC) s += (double)gx[f];
       gx[f] = (T)s;
     }
   }
@@ -590,7 +594,7 @@ hipError_t adj_derive_right(const double* Tbk, double* Tbp, int64_t Ck, int nk, 
 }
 
 hipError_t adj_out(int dtype, const SketchArgs& g, int prec, const double* Yb, const double* Tbt, const double* L,
-                   const double* Rt, int r, const void* x, void* gx, hipStream_t s) {
+                   const double* Rt, int r, const void* x, void* gx, bool acc, hipStream_t s) {
   AdjOutArgs A;
   std::memset(&A, 0, sizeof(A));
   A.R = g.R;
@@ -614,12 +618,21 @@ hipError_t adj_out(int dtype, const SketchArgs& g, int prec, const double* Yb, c
   A.gj = (int)std::max<int64_t>(1, std::min<int64_t>(g.C, (4096 + gi - 1) / gi));
   const dim3 grid((unsigned)(gi * A.gj)), block(256);
   const bool fused = L != nullptr;
+  if (fused && acc) return hipErrorInvalidValue;   // the loss term enters once, in the first group
   if (dtype == PSTT2_F64) {
-    if (fused) hipLaunchKernelGGL((k_adj_out<double, true>), grid, block, 0, s, A, (const double*)x, (double*)gx);
-    else hipLaunchKernelGGL((k_adj_out<double, false>), grid, block, 0, s, A, (const double*)x, (double*)gx);
+    if (fused)
+      hipLaunchKernelGGL((k_adj_out<double, true, false>), grid, block, 0, s, A, (const double*)x, (double*)gx);
+    else if (acc)
+      hipLaunchKernelGGL((k_adj_out<double, false, true>), grid, block, 0, s, A, (const double*)x, (double*)gx);
+    else
+      hipLaunchKernelGGL((k_adj_out<double, false, false>), grid, block, 0, s, A, (const double*)x, (double*)gx);
   } else {
-    if (fused) hipLaunchKernelGGL((k_adj_out<float, true>), grid, block, 0, s, A, (const float*)x, (float*)gx);
-    else hipLaunchKernelGGL((k_adj_out<float, false>), grid, block, 0, s, A, (const float*)x, (float*)gx);
+    if (fused)
+      hipLaunchKernelGGL((k_adj_out<float, true, false>), grid, block, 0, s, A, (const float*)x, (float*)gx);
+    else if (acc)
+      hipLaunchKernelGGL((k_adj_out<float, false, true>), grid, block, 0, s, A, (const float*)x, (float*)gx);
+    else
+      hipLaunchKernelGGL((k_adj_out<float, false, false>), grid, block, 0, s, A, (const float*)x, (float*)gx);
   }
   return hipGetLastError();
 }

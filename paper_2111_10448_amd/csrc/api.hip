@@ -856,8 +856,7 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   if (!c || !cores || !gx_dev) return fail(c, PSTT2_EINVAL, "null argument");
   if (!gbar_dev && !x_dev) return fail(c, PSTT2_EINVAL, "x_dev is needed for the fused loss (gbar_dev == NULL)");
   if (!c->recovered) return fail(c, PSTT2_ESTATE, "pstt2_vjp needs a successful pstt2_recover first");
-  if (c->desc.mid != PSTT2_MID_ONEPASS) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the one-pass middle core only");
-  if (c->indep) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the nested DRM scheme only");
+  if (c->desc.mid == PSTT2_MID_TWOPASS) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the one-pass middle cores only");
   const int d = c->d, m = c->m, ell = c->ell;
   if (cores->d != d) return fail(c, PSTT2_EINVAL, "cores do not match the context");
   for (int k = 0; k < d; ++k)
@@ -969,15 +968,60 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   double* A = take((int64_t)rm * ell, false);
   double* Zb = take(p * ell, false);
   double* Ab = take((int64_t)rm * ell, false);
-  VJPCK(middle_z(Qprev, Rprev, rprev, c->Y, c->R, nm, ell, Z, s));
+  // two-sided rule (d >= 3): Z = (I (x) M1) H with H = (I (x) Psi')^T Y_R and
+  // M1 = (Psi'^T Q_{m-1})^+; rebuilt here as the recovery built it
+  const bool two = c->desc.mid == PSTT2_MID_TWOSIDED && m >= 2;
+  double *ptab = nullptr, *a1t = nullptr, *m1t = nullptr;
+  if (!two) {
+    VJPCK(middle_z(Qprev, Rprev, rprev, c->Y, c->R, nm, ell, Z, s));
+  } else {
+    ptab = take(Rprev * ell, false);
+    a1t = take((int64_t)rprev * ell, false);
+    m1t = take((int64_t)ell * rprev, false);
+    double* id = take((int64_t)ell * ell, false);
+    VJPCK(kr_table(c->fac, left_chain(c, m - 1), Rprev, ell, ptab, s));
+    VJPCK(adj_gemm(true, false, rprev, ell, Rprev, 1.0, Qprev, Rprev, ptab, Rprev, 0.0, a1t, rprev, s));
+    VJPCK(eye(ell, id, s));
+    VJPCK(middle_ls(id, ell, a1t, rprev, ell, m1t, c->flag, s));
+    VJPCK(middle_z(m1t, ell, rprev, c->H, (int64_t)ell * nm, nm, ell, Z, s));
+  }
   SketchArgs geo = base_args(c);
   VJPCK(middle_a(c->basis[m], c->C, rm, geo, c->prec, A, s));
   VJPCK(adj_ls(cores->core[m - 1], Gb[m - 1], Z, A, p, rm, ell, Zb, Ab, s));
   double* Yb = take(c->R * ell, true);
-  if (m >= 2)
-    VJPCK(adj_gemm(false, true, Rprev, rprev, (int64_t)nm * ell, 1.0, c->Y, Rprev, Zb, rprev, 1.0, Qb[m - 1], Rprev,
-                   s));
-  VJPCK(adj_gemm(false, false, Rprev, (int64_t)nm * ell, rprev, 1.0, Qprev, Rprev, Zb, rprev, 1.0, Yb, Rprev, s));
+  if (!two) {
+    if (m >= 2)
+      VJPCK(adj_gemm(false, true, Rprev, rprev, (int64_t)nm * ell, 1.0, c->Y, Rprev, Zb, rprev, 1.0, Qb[m - 1],
+                     Rprev, s));
+    VJPCK(adj_gemm(false, false, Rprev, (int64_t)nm * ell, rprev, 1.0, Qprev, Rprev, Zb, rprev, 1.0, Yb, Rprev, s));
+  } else {
+    // Z3(p, j, c) = sum_a M1^T(a, p) H3(a, j, c):
+    //   Hbar = M1^T Zbar and M1^T-bar = H Zbar^T, with H as ell x (n_m ell), Zbar as r_{m-1} x (n_m ell)
+    const int64_t w = (int64_t)nm * ell;
+    double* Hb = take((int64_t)ell * w, false);
+    double* M1b = take((int64_t)ell * rprev, false);   // cotangent of M1^T
+    VJPCK(adj_gemm(false, false, ell, w, rprev, 1.0, m1t, ell, Zb, rprev, 0.0, Hb, ell, s));
+    VJPCK(adj_gemm(false, true, ell, rprev, w, 1.0, c->H, ell, Zb, rprev, 0.0, M1b, ell, s));
+    // pseudo-inverse of the full-column-rank A1 = Psi'^T Q (ell x r), W = A1^+ = (A1^T A1)^{-1} A1^T:
+    //   dW = -W dA1 W + (A1^T A1)^{-1} dA1^T (I - A1 W), so with (A1^T A1)^{-1} = W W^T
+    //   A1bar = -W^T Wbar W^T + (I - A1 W) Wbar^T W W^T.
+    // In M1^T = W^T and its cotangent Mb = Wbar^T:  T1 = Mb^T M1^T, T2 = M1 M1^T,
+    //   A1bar = -M1^T T1 + Mb T2 - A1 (T1^T T2).
+    const int rp = rprev;
+    double* T1 = take((int64_t)rp * rp, false);
+    double* T2 = take((int64_t)rp * rp, false);
+    double* T4 = take((int64_t)rp * rp, false);
+    double* A1b = take((int64_t)ell * rp, false);
+    VJPCK(adj_gemm(true, false, rp, rp, ell, 1.0, M1b, ell, m1t, ell, 0.0, T1, rp, s));
+    VJPCK(adj_gemm(true, false, rp, rp, ell, 1.0, m1t, ell, m1t, ell, 0.0, T2, rp, s));
+    VJPCK(adj_gemm(true, false, rp, rp, rp, 1.0, T1, rp, T2, rp, 0.0, T4, rp, s));
+    VJPCK(adj_gemm(false, false, ell, rp, rp, -1.0, m1t, ell, T1, rp, 0.0, A1b, ell, s));
+    VJPCK(adj_gemm(false, false, ell, rp, rp, 1.0, M1b, ell, T2, rp, 1.0, A1b, ell, s));
+    VJPCK(adj_gemm(true, false, ell, rp, rp, -1.0, a1t, rp, T4, rp, 1.0, A1b, ell, s));
+    // A1 = Psi'^T Q_{m-1}: Qbar_{m-1} += Psi' A1bar;  H = (I (x) Psi')^T Y_R: Ybar += (I (x) Psi') Hbar
+    VJPCK(adj_gemm(false, false, Rprev, rp, ell, 1.0, ptab, Rprev, A1b, ell, 1.0, Qb[m - 1], Rprev, s));
+    VJPCK(adj_gemm(false, false, Rprev, w, ell, 1.0, ptab, Rprev, Hb, ell, 1.0, Yb, Rprev, s));
+  }
   VJPCK(adj_pbar(c->om_tab, c->L4, c->C, rm, ell, c->prec, Ab, Qb[m], s));
   for (int k = m - 1; k >= 2; --k) {
     const int64_t nr = c->n[k - 1] * r[k];
@@ -1008,14 +1052,52 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
     VJPCK(adj_qr(left ? c->S[k] : c->Tk[k], c->basis[k], Qb[k], Mk, ell, r[k], c->piv_dev + (int64_t)k * ell,
                  left ? Sb[k] : Tb[k], s));
   }
-  for (int k = 1; k <= m - 1; ++k)
-    VJPCK(adj_derive_left(Sb[k], Sb[k + 1], Rk[k], (int)c->n[k], ell, c->fac + c->omega_off[k], s));
-  for (int k = d - 1; k >= m + 1; --k)
-    VJPCK(adj_derive_right(Tb[k], Tb[k - 1], Ck(k), (int)c->n[k - 1], ell, c->fac + c->psi_off[k - 1], s));
-  // ---- B3: gx = Ybar Omega_m^T + Psi_m Tbar_m  (+ 2 (X - X~)) ----
   const bool fused = gbar_dev == nullptr;
-  VJPCK(adj_out(c->dtype, geo, c->prec, Yb, Tb[m], fused ? Lm : nullptr, fused ? Rtm : nullptr, rm, x_dev, gx_dev,
-                s));
+  if (!c->indep) {
+    for (int k = 1; k <= m - 1; ++k)
+      VJPCK(adj_derive_left(Sb[k], Sb[k + 1], Rk[k], (int)c->n[k], ell, c->fac + c->omega_off[k], s));
+    for (int k = d - 1; k >= m + 1; --k)
+      VJPCK(adj_derive_right(Tb[k], Tb[k - 1], Ck(k), (int)c->n[k - 1], ell, c->fac + c->psi_off[k - 1], s));
+    // ---- B3: gx = Ybar Omega_m^T + Psi_m Tbar_m  (+ 2 (X - X~)) ----
+    VJPCK(adj_out(c->dtype, geo, c->prec, Yb, Tb[m], fused ? Lm : nullptr, fused ? Rtm : nullptr, rm, x_dev, gx_dev,
+                  false, s));
+  } else {
+    // independent scheme: split k's sketch was contracted from its own sketch
+    // of X_m with its own factors, so its cotangent runs back up that chain
+    // alone, to the cotangent of X_m Omega_m^(k) (k < m) or of
+    // (Psi_m^(k)T X_m)^T (k > m)
+    std::vector<double*> iYb(d + 1, nullptr), iTb(d + 1, nullptr);
+    for (int k = 1; k < m; ++k) {
+      const double* cur = Sb[k];
+      for (int q = k + 1; q <= m; ++q) {   // undo the contraction of mode q: R_{q-1} -> R_q rows
+        double* nxt = take(Rk[q] * ell, true);
+        VJPCK(adj_derive_left(cur, nxt, Rk[q - 1], (int)c->n[q - 1], ell, c->fac + c->iom_off[k][q - 1], s));
+        cur = nxt;
+      }
+      iYb[k] = (double*)cur;
+    }
+    for (int k = m + 1; k <= d - 1; ++k) {
+      const double* cur = Tb[k];
+      for (int q = k; q >= m + 1; --q) {   // undo the contraction of mode q: C_q -> C_{q-1} columns
+        double* nxt = take(Ck(q - 1) * ell, true);
+        VJPCK(adj_derive_right(cur, nxt, Ck(q), (int)c->n[q - 1], ell, c->fac + c->ipsi_off[k][q - 1], s));
+        cur = nxt;
+      }
+      iTb[k] = (double*)cur;
+    }
+    // ---- B3, one launch per pass group (the factor sets the sketch pass
+    //      paired): gx = sum_g Ybar_g Omega_m^(g)T + Psi_m^(g) Tbar_g (+ 2 (X - X~)) ----
+    for (int g = 0; g < pass_groups(c); ++g) {
+      double *yd = nullptr, *td = nullptr;
+      const SketchArgs ga = group_args(c, g, &yd, &td);
+      const int kr = g + 1, kl = m + g;
+      const double* yg = kr < m ? iYb[kr] : (kr == m ? Yb : nullptr);
+      const double* tg = kl == m ? Tb[m] : (kl <= d - 1 ? iTb[kl] : nullptr);
+      const bool first = g == 0;
+      VJPCK(adj_out(c->dtype, ga, c->prec, yg, tg, fused && first ? Lm : nullptr, fused && first ? Rtm : nullptr,
+                    rm, x_dev, gx_dev, !first, s));
+    }
+  }
 #undef VJPCK
   release();
   int hflag = 0;

@@ -168,7 +168,7 @@ hipError_t adj_derive_left(const double* Sbk, double* Sbk1, int64_t Rk, int nk1,
 hipError_t adj_derive_right(const double* Tbk, double* Tbp, int64_t Ck, int nk, int ell, const double* ps,
                             hipStream_t s);
 hipError_t adj_out(int dtype, const SketchArgs& g, int prec, const double* Yb, const double* Tbt, const double* L,
-                   const double* Rt, int r, const void* x, void* gx, hipStream_t s);
+                   const double* Rt, int r, const void* x, void* gx, bool acc, hipStream_t s);
 
 // TT evaluation (tt_eval.hip).
 hipError_t tt_interfaces(const tt_cores* c, int split, double** L, double** Rt, double** base, hipStream_t s);

@@ -134,6 +134,12 @@ def test_twopass_middle_core():
     ctx, tt, xg = gpu_run(x, w, fac, "f64", middle="twopass")
     out = compare(ctx, tt, xg, x, w, ref, "f64", check_cores=True)
     say(f"    {out}")
+    # the adjoint covers the one-pass middle cores only
+    import paper_2111_10448_amd as P
+    from paper_2111_10448_amd import _lib as L
+    with pytest.raises(P.PSTT2Error) as e:
+        ctx.vjp(tt, x=xg)
+    assert e.value.status == L.ESTATE
     ctx.close()
 
 
