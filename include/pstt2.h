@@ -143,6 +143,29 @@ pstt2_status pstt2_sketch(pstt2_ctx* ctx, const void* x_dev, int64_t first, int6
 pstt2_status pstt2_sketch_slabs(pstt2_ctx* ctx, int32_t nslabs, const void* const* xs_dev,
                                 const int64_t* firsts, const int64_t* counts);
 
+/* Tensors given by a formula of their indices: the streaming setting of
+ * Section 4.2, where each sub-tensor comes from a function of its indices and
+ * the whole tensor is never stored.  The kernels evaluate the entries in place
+ * of loading them.
+ *   HILBERT  X(i_1, ..., i_d) = 1 / (1 - d + i_1 + ... + i_d), 1 <= i_q <= n_q
+ *            (the Hilbert tensor of Section 4.3 and Table 1), evaluated in
+ *            FP64: the reciprocal of the integer index sum, correctly rounded. */
+typedef enum { PSTT2_FN_HILBERT = 0 } pstt2_fn_kind;
+typedef struct {
+  pstt2_fn_kind kind;
+} pstt2_fn;
+
+/* Stream the entries [first, first + count) of the tensor fn (flat
+ * column-major, the context's mode sizes) into the sketches, as pstt2_sketch
+ * does for a slab in memory.  Needs a context with dtype F64 and prec F64.
+ * first and count must be multiples of R_m = n_1...n_m (whole columns of the
+ * middle unfolding X_m); the same coverage rules as pstt2_sketch apply, and
+ * slabs from memory and from fn may be mixed.  The library builds small index
+ * tables (R_m + C_m int32 and sum_q n_q doubles) on first use and keeps them
+ * with the context.  async.  Errors: EINVAL (kind, dtype / prec, alignment,
+ * range), ESTATE (overlap, after recover), EDEVICE. */
+pstt2_status pstt2_sketch_fn(pstt2_ctx* ctx, const pstt2_fn* fn, int64_t first, int64_t count);
+
 /* Recover the TT cores from the accumulated sketches: derive every split's
  * sketch and its two-sided sketch B_k = Psi_k^T X_k Omega_k (ell x ell; as
  * Psi_k^T S_k for k < m and T_k Omega_k for k >= m, FP64 DRM entries), bases
@@ -222,6 +245,11 @@ void pstt2_destroy(pstt2_ctx* ctx);
  * trial).  cores may point at caller memory.  sync.  Errors: EINVAL, EDEVICE. */
 pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* rel_err,
                       void* hip_stream);
+
+/* The same for the tensor fn (see pstt2_fn), evaluated in FP64 inside the
+ * pass instead of read from memory; the mode sizes are the cores'.  sync.
+ * Errors: EINVAL, ENUMERIC, EDEVICE. */
+pstt2_status tt_error_fn(const tt_cores* cores, const pstt2_fn* fn, double* rel_err, void* hip_stream);
 
 /* Write entries [first, first + count) of X~ (flat column-major, entry formula
  * of Section 2.2) to x_out_dev in the given dtype.  sync.  Errors: EINVAL, EDEVICE. */

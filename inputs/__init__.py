@@ -43,6 +43,7 @@ class Workload:
     eps: Optional[float] = None  # tolerance (tolerance mode)
     rmax: int = 0              # rank cap in tolerance mode
     nslabs: int = 1            # number of contiguous slabs the tensor is delivered in
+    rank_list: tuple = ()      # per-split target ranks r_1..r_{d-1} (overrides rank)
 
     @property
     def d(self) -> int:
@@ -58,13 +59,14 @@ class Workload:
 
     def ranks(self) -> Optional[List[int]]:
         """Target ranks r_1..r_{d-1} in fixed-rank mode, clamped to the unfolding sizes."""
-        if self.rank is None:
+        if self.rank is None and not self.rank_list:
             return None
         out = []
         for k in range(1, self.d):
             rk = int(np.prod(self.n[:k]))
             ck = int(np.prod(self.n[k:]))
-            out.append(min(self.rank, rk, ck, self.ell))
+            want = self.rank_list[k - 1] if self.rank_list else self.rank
+            out.append(min(want, rk, ck, self.ell))
         return out
 
 
@@ -96,6 +98,17 @@ WORKLOADS = {
     "c4_small": Workload("c4_small", 13, (6, 5, 7, 6, 5, 6, 4, 5), "f32", "tt", tt_rank=4, noise=1e-4,
                          ell=8, rank=4, nslabs=7),
     "c5_small": Workload("c5_small", 14, (20, 17, 19, 21), "f32", "tt", tt_rank=6, noise=1e-3, ell=12, rank=6),
+    # Table 1 (Section 4.3): Hilbert tensors of order 3, 5 and 9 with the printed TT
+    # ranks (6.59 GB, 60.8 GB and 38.4 GB in FP64).  Sketch size 32 (the library's
+    # largest): oversampling 7 to 20.  The GPU evaluates them inside its kernels.
+    "t1_d3": Workload("t1_d3", 21, (960,) * 3, "f64", "hilbert", ell=32, rank_list=(25, 25)),
+    "t1_d5": Workload("t1_d5", 22, (96,) * 5, "f64", "hilbert", ell=32, rank_list=(17, 18, 18, 17)),
+    "t1_d9": Workload("t1_d9", 23, (12,) * 9, "f64", "hilbert", ell=32,
+                      rank_list=(12, 18, 18, 19, 19, 18, 18, 12)),
+    # scaled-down Hilbert twins (ragged modes) that the oracle finishes in seconds
+    "t1_small3": Workload("t1_small3", 24, (61, 47, 53), "f64", "hilbert", ell=16, rank_list=(8, 8)),
+    "t1_small5": Workload("t1_small5", 25, (13, 11, 12, 9, 10), "f64", "hilbert", ell=14,
+                          rank_list=(6, 7, 7, 6)),
 }
 
 
@@ -173,6 +186,23 @@ def hilbert_tensor(n: Sequence[int]) -> np.ndarray:
     for i in range(n[d - 1]):
         np.divide(1.0, inner + (i + 1) - d + 1, out=out[i * blk:(i + 1) * blk])
     return out
+
+
+def hilbert_entries(n: Sequence[int], m: int, rows, cols) -> np.ndarray:
+    """Entries X_m(rows[i], cols[j]) of the Hilbert tensor's m-th unfolding (rows: flat
+    indices over modes 1..m, cols: over modes m+1..d), from the formula, as an FP64
+    len(rows) x len(cols) array."""
+    def index_sum(f, modes):
+        f = np.asarray(f, dtype=np.int64).copy()
+        s = np.zeros(f.shape, dtype=np.int64)
+        for nq in modes:
+            s += f % nq + 1
+            f //= nq
+        return s
+    d = len(n)
+    sr = index_sum(rows, n[:m])
+    sc = index_sum(cols, n[m:])
+    return 1.0 / (sr[:, None] + sc[None, :] - d + 1).astype(np.float64)
 
 
 def add_noise(x: np.ndarray, rng: np.random.Generator, sigma: float, chunk: int = 1 << 24) -> None:

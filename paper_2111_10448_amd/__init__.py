@@ -21,7 +21,7 @@ import numpy as np
 from . import _lib as L
 from ._lib import PSTT2Error  # noqa: F401
 
-__all__ = ["PSTT2", "TT", "PSTT2Error", "decompose", "tt_error", "tt_reconstruct", "version", "cores_struct",
+__all__ = ["PSTT2", "TT", "PSTT2Error", "decompose", "tt_error", "tt_error_fn", "tt_reconstruct", "version", "cores_struct",
            "PSTT2Reconstruct", "pstt2_reconstruct"]
 
 
@@ -105,6 +105,10 @@ class TT:
 
     def error(self, x) -> float:
         return tt_error(self, x, stream=self._stream)
+
+    def error_fn(self, fn: str = "hilbert") -> float:
+        """Relative error against a tensor given by a formula (see PSTT2.sketch_fn)."""
+        return tt_error_fn(self, fn, stream=self._stream)
 
     def reconstruct(self, first: int = 0, count: Optional[int] = None, dtype=None):
         return tt_reconstruct(self, first, count, dtype, stream=self._stream)
@@ -194,6 +198,17 @@ class PSTT2:
         self._keep.append(x)
         L.check(L.lib().pstt2_sketch(self._c(), ctypes.c_void_p(x.data_ptr()), int(first), int(x.numel())),
                 self._ctx)
+
+    def sketch_fn(self, fn: str = "hilbert", first: int = 0, count: Optional[int] = None) -> None:
+        """Stream entries [first, first + count) of a tensor given by a formula of its
+        indices, evaluated inside the kernel ("hilbert": 1 / (1 - d + i_1 + ... + i_d)).
+        first and count are multiples of n_1...n_m; count defaults to the rest (async)."""
+        if fn not in L.FN:
+            raise ValueError(f"unknown tensor function {fn!r}")
+        if count is None:
+            count = int(np.prod(self.n)) - int(first)
+        f = L.Fn(L.FN[fn])
+        L.check(L.lib().pstt2_sketch_fn(self._c(), ctypes.byref(f), int(first), int(count)), self._ctx)
 
     def sketch_slabs(self, xs: Sequence, firsts: Sequence[int]) -> None:
         """Stream several slabs in one launch (async)."""
@@ -299,6 +314,18 @@ def tt_error(tt, x, stream=None) -> float:
     out = ctypes.c_double()
     L.check(L.lib().tt_error(ctypes.byref(cs), ctypes.c_void_p(x.data_ptr()), _dtype_code(x), ctypes.byref(out),
                              ctypes.c_void_p(_stream_handle(stream))))
+    return out.value
+
+
+def tt_error_fn(tt, fn: str = "hilbert", stream=None) -> float:
+    """||X - X~||_F / ||X||_F for a tensor given by a formula, evaluated inside the pass."""
+    if fn not in L.FN:
+        raise ValueError(f"unknown tensor function {fn!r}")
+    cs = tt.struct() if isinstance(tt, TT) else tt
+    out = ctypes.c_double()
+    f = L.Fn(L.FN[fn])
+    L.check(L.lib().tt_error_fn(ctypes.byref(cs), ctypes.byref(f), ctypes.byref(out),
+                                ctypes.c_void_p(_stream_handle(stream))))
     return out.value
 
 

@@ -21,6 +21,7 @@ F64, F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 MID = {"onepass": 0, "twopass": 1, "twosided": 2}
 DRM = {"nested": 0, "independent": 1}
+FN = {"hilbert": 0}
 
 
 class Desc(ctypes.Structure):
@@ -48,6 +49,10 @@ class TTCores(ctypes.Structure):
         ("owned", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
+
+
+class Fn(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int)]
 
 
 class PSTT2Error(RuntimeError):
@@ -84,6 +89,8 @@ def lib():
     L.pstt2_destroy.restype = None
     L.tt_error.argtypes = [ctypes.POINTER(TTCores), vp, st, ctypes.POINTER(ctypes.c_double), vp]
     L.tt_reconstruct.argtypes = [ctypes.POINTER(TTCores), vp, st, i64, i64, vp]
+    L.pstt2_sketch_fn.argtypes = [vp, ctypes.POINTER(Fn), i64, i64]
+    L.tt_error_fn.argtypes = [ctypes.POINTER(TTCores), ctypes.POINTER(Fn), ctypes.POINTER(ctypes.c_double), vp]
     L.tt_cores_copy.argtypes = [ctypes.POINTER(TTCores), ctypes.POINTER(TTCores), vp]
     L.tt_cores_free.argtypes = [ctypes.POINTER(TTCores)]
     L.tt_cores_free.restype = None
@@ -93,7 +100,7 @@ def lib():
     L.pstt2_version.restype = ctypes.c_char_p
     for f in ("pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
               "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_reset", "tt_error", "tt_reconstruct", "tt_cores_copy",
-              "pstt2_profile", "pstt2_profile_read"):
+              "pstt2_profile", "pstt2_profile_read", "pstt2_sketch_fn", "tt_error_fn"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -108,5 +115,5 @@ def check(status: int, ctx=None) -> None:
 # Every symbol include/pstt2.h declares.
 EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
            "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_profile", "pstt2_profile_read", "pstt2_reset",
-           "pstt2_destroy", "tt_error", "tt_reconstruct",
+           "pstt2_destroy", "tt_error", "tt_reconstruct", "pstt2_sketch_fn", "tt_error_fn",
            "tt_cores_copy", "tt_cores_free", "pstt2_last_error", "pstt2_version"]

@@ -16,7 +16,7 @@ static thread_local std::string g_tls_err;
 void pstt2_set_tls_error(const std::string& msg) { g_tls_err = msg; }
 
 namespace pstt2 {
-hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s);
+hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s, int fn);
 hipError_t tt_reconstruct_run(const tt_cores* c, void* out, int dtype, int64_t first, int64_t count, hipStream_t s);
 }
 
@@ -65,6 +65,10 @@ struct pstt2_ctx {
   double* sinkT = nullptr;
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_pool;
+  // index tables of the Hilbert tensor (pstt2_sketch_fn), built on first use
+  double* fn_rec = nullptr;
+  int32_t* fn_row = nullptr;
+  int32_t* fn_col = nullptr;
   std::string err;
 };
 
@@ -222,6 +226,8 @@ SketchArgs group_args(const pstt2_ctx* c, int g, double** Ydst, double** Tdst) {
   return a;
 }
 
+pstt2_status launch_segs(pstt2_ctx* c, const SketchArgs& ga, const std::vector<Seg>& segs, double* Yd, double* Td);
+
 pstt2_status run_slabs(pstt2_ctx* c, const std::vector<Piece>& ps) {
   const int esz = c->dtype == PSTT2_F64 ? 8 : 4;
   const int64_t R = c->R;
@@ -252,6 +258,16 @@ pstt2_status run_slabs(pstt2_ctx* c, const std::vector<Piece>& ps) {
     const SketchArgs ga = group_args(c, g, &Yd, &Td);
     for (const Edge& ed : edges)
       HIPCK(c, launch_partial_col(c->dtype, ed.x, ed.r0, ed.r1, ed.col, ga, Yd, Td, c->stream));
+    const pstt2_status st = launch_segs(c, ga, segs, Yd, Td);
+    if (st != PSTT2_OK) return st;
+  }
+  return PSTT2_OK;
+}
+
+// One pass group over runs of whole columns: up to kMaxSeg runs per launch of
+// the streaming kernel, then the fixed-order reduction of its partials.
+pstt2_status launch_segs(pstt2_ctx* c, const SketchArgs& ga, const std::vector<Seg>& segs, double* Yd, double* Td) {
+  {
     for (size_t s0 = 0; s0 < segs.size(); s0 += kMaxSeg) {
       SketchArgs a = ga;
       const size_t s1 = std::min(segs.size(), s0 + kMaxSeg);
@@ -558,6 +574,9 @@ void pstt2_destroy(pstt2_ctx* c) {
   for (double* p : c->iT) (void)hipFree(p);
   (void)hipFree(c->sinkY);
   (void)hipFree(c->sinkT);
+  (void)hipFree(c->fn_rec);
+  (void)hipFree(c->fn_row);
+  (void)hipFree(c->fn_col);
   delete c;
 }
 
@@ -569,6 +588,51 @@ pstt2_status pstt2_sketch(pstt2_ctx* c, const void* x_dev, int64_t first, int64_
   if (st != PSTT2_OK) return st;
   st = run_slabs(c, {Piece{x_dev, first, count}});
   if (st != PSTT2_OK) return st;
+  add_cover(c, first, count);
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_sketch_fn(pstt2_ctx* c, const pstt2_fn* fn, int64_t first, int64_t count) {
+  if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
+  if (!fn) return fail(c, PSTT2_EINVAL, "null function");
+  if (fn->kind != PSTT2_FN_HILBERT) return fail(c, PSTT2_EINVAL, "unknown tensor function");
+  if (c->dtype != PSTT2_F64 || c->prec != PSTT2_P_F64)
+    return fail(c, PSTT2_EINVAL, "tensor functions need an FP64 context with FP64 sketches");
+  if (c->recovered) return fail(c, PSTT2_ESTATE, "sketch after recover: call pstt2_reset first");
+  if (first % c->R != 0 || count % c->R != 0)
+    return fail(c, PSTT2_EINVAL, "first/count must be multiples of n_1...n_m (whole columns of X_m)");
+  pstt2_status st = check_range(c, first, count);
+  if (st != PSTT2_OK) return st;
+  if (count == 0) return PSTT2_OK;
+  hipError_t e = hipSuccess;
+  if (!c->fn_rec) {
+    double* rec = nullptr;
+    int32_t *row_t = nullptr, *col_t = nullptr;
+    e = hipMalloc(&rec, sizeof(double) * hilbert_rec_len(c->n, c->d));
+    if (e == hipSuccess) e = hipMalloc(&row_t, sizeof(int32_t) * c->R);
+    if (e == hipSuccess) e = hipMalloc(&col_t, sizeof(int32_t) * c->C);
+    if (e == hipSuccess) e = hilbert_tables(c->n, c->d, c->m, c->R, c->C, rec, row_t, col_t, c->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(rec);
+      (void)hipFree(row_t);
+      (void)hipFree(col_t);
+      return hfail(c, e, "Hilbert tables");
+    }
+    c->fn_rec = rec;
+    c->fn_row = row_t;
+    c->fn_col = col_t;
+  }
+  const std::vector<Seg> segs{Seg{nullptr, first / c->R, count / c->R, 0}};
+  for (int g = 0; g < pass_groups(c); ++g) {
+    double *Yd = nullptr, *Td = nullptr;
+    SketchArgs ga = group_args(c, g, &Yd, &Td);
+    ga.fn = 1;
+    ga.fn_rec = c->fn_rec;
+    ga.fn_row = c->fn_row;
+    ga.fn_col = c->fn_col;
+    st = launch_segs(c, ga, segs, Yd, Td);
+    if (st != PSTT2_OK) return st;
+  }
   add_cover(c, first, count);
   return PSTT2_OK;
 }
@@ -1183,10 +1247,8 @@ static pstt2_status check_cores(const tt_cores* t) {
   return PSTT2_OK;
 }
 
-pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* rel_err, void* hip_stream) {
-  pstt2_status st = check_cores(cores);
-  if (st != PSTT2_OK) return st;
-  if (!x_dev || !rel_err) return fail(nullptr, PSTT2_EINVAL, "null argument");
+static pstt2_status error_common(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, int fn,
+                                 double* rel_err, void* hip_stream) {
   double e2x2[2] = {0, 0};
   double* pin = pinned_scratch();
   // tt_error returns only after its stream is idle, so its temporaries can come
@@ -1195,7 +1257,7 @@ pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtyp
   hipError_t e = ar ? arena_begin(ar, (hipStream_t)hip_stream) : hipSuccess;
   if (e != hipSuccess) return hfail(nullptr, e, "tt_error");
   ArenaScope scope(ar);
-  e = tt_error_run(cores, x_dev, dtype, pin ? pin : e2x2, (hipStream_t)hip_stream);
+  e = tt_error_run(cores, x_dev, dtype, pin ? pin : e2x2, (hipStream_t)hip_stream, fn);
   if (pin) {
     e2x2[0] = pin[0];
     e2x2[1] = pin[1];
@@ -1204,6 +1266,21 @@ pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtyp
   *rel_err = e2x2[1] > 0 ? std::sqrt(e2x2[0] / e2x2[1]) : (e2x2[0] > 0 ? INFINITY : 0.0);
   if (!std::isfinite(*rel_err)) return fail(nullptr, PSTT2_ENUMERIC, "non-finite error");
   return PSTT2_OK;
+}
+
+pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* rel_err, void* hip_stream) {
+  pstt2_status st = check_cores(cores);
+  if (st != PSTT2_OK) return st;
+  if (!x_dev || !rel_err) return fail(nullptr, PSTT2_EINVAL, "null argument");
+  return error_common(cores, x_dev, dtype, 0, rel_err, hip_stream);
+}
+
+pstt2_status tt_error_fn(const tt_cores* cores, const pstt2_fn* fn, double* rel_err, void* hip_stream) {
+  pstt2_status st = check_cores(cores);
+  if (st != PSTT2_OK) return st;
+  if (!fn || !rel_err) return fail(nullptr, PSTT2_EINVAL, "null argument");
+  if (fn->kind != PSTT2_FN_HILBERT) return fail(nullptr, PSTT2_EINVAL, "unknown tensor function");
+  return error_common(cores, nullptr, PSTT2_F64, 1, rel_err, hip_stream);
 }
 
 pstt2_status tt_reconstruct(const tt_cores* cores, void* x_out_dev, pstt2_dtype dtype, int64_t first, int64_t count,

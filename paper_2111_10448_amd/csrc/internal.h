@@ -62,7 +62,25 @@ struct SketchArgs {
   int32_t L4;            // its row stride: ell rounded up to a multiple of 4
   const double* psi_tab; // optional Psi(row, a) table, R x L4 (else products of the factors)
   Seg seg[kMaxSeg];
+  // Tensor given by a formula (FP64 kernel only): 0 = X read from the
+  // segments; 1 = Hilbert tensor, X(row, col) = fn_rec[fn_row[row] + fn_col[col]]
+  int32_t fn;
+  const double* fn_rec;   // 1/k, k = 0 .. 1 + sum_q (n_q - 1) (entry 0 unused)
+  const int32_t* fn_row;  // 1 + digit sum of each row of X_m (0-based mode indices)
+  const int32_t* fn_col;  // digit sum of each column of X_m
 };
+
+// Index tables of the Hilbert tensor X(i) = 1 / (1 - d + i_1 + ... + i_d)
+// (1-based i) on the split X_m = rows (modes 1..m) x columns (modes m+1..d):
+// X(row, col) = rec[row_t[row] + col_t[col]].  rec holds 2 + sum (n_q - 1)
+// entries, row_t R and col_t C.
+hipError_t hilbert_tables(const int64_t* n, int d, int m, int64_t R, int64_t C, double* rec, int32_t* row_t,
+                          int32_t* col_t, hipStream_t s);
+inline int64_t hilbert_rec_len(const int64_t* n, int d) {
+  int64_t k = 2;
+  for (int q = 0; q < d; ++q) k += n[q] - 1;
+  return k;
+}
 
 // Launch the streaming dual-sketch kernel for the configured precision.
 hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s);

@@ -636,7 +636,9 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
 constexpr int NWF = 4;
 constexpr int F64_WG_PER_CU = 2;
 
-template <int L4, bool ALIGNED, bool SEG1>
+// FN: the tensor is the Hilbert tensor, evaluated from the index tables in
+// place of the loads of X (one launch segment, no memory behind it).
+template <int L4, bool ALIGNED, bool SEG1, bool FN>
 __global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const SketchArgs A) {
   constexpr int RW = 64;
   constexpr int ST = RW + 2;
@@ -697,6 +699,13 @@ __global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const Sk
   };
 
   double xr[NLD][2];
+  // FN: index-table entries of this lane's two rows (fixed for the launch)
+  int fr0 = 0, fr1 = 0;
+  if constexpr (FN) {
+    const int64_t row = row0w + (lane & 31) * 2;
+    fr0 = row < A.R ? A.fn_row[row] : 0;
+    fr1 = row + 1 < A.R ? A.fn_row[row + 1] : 0;
+  }
   auto load_chunk = [&](int64_t ci) {
     ChunkInfo ch = info(cx, ci);
     const double* base = (const double*)ch.ptr;
@@ -707,7 +716,11 @@ __global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const Sk
       const int64_t row = row0w + r;
       const bool colok = cc < ch.ncols;
       const double* p = base + (ch.lcol0 + cc) * A.R + row;
-      if constexpr (ALIGNED) {
+      if constexpr (FN) {
+        const int fc = colok ? A.fn_col[ch.gcol0 + cc] : 0;
+        xr[i][0] = (colok && row < A.R) ? A.fn_rec[fr0 + fc] : 0.0;
+        xr[i][1] = (colok && row + 1 < A.R) ? A.fn_rec[fr1 + fc] : 0.0;
+      } else if constexpr (ALIGNED) {
         if (colok && row < A.R) {
           const double2 v = *(const double2*)p;
           xr[i][0] = v.x;
@@ -858,12 +871,15 @@ template <int L4>
 static hipError_t launch_f64(const SketchArgs& a, bool aligned, hipStream_t s) {
   dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(NWF * 64);
   const bool seg1 = a.nseg == 1 && a.seg[0].chunk0 == 0;
-  if (aligned) {
-    if (seg1) hipLaunchKernelGGL((k_sketch_f64<L4, true, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_sketch_f64<L4, true, false>), grid, block, 0, s, a);
+  if (a.fn) {
+    if (!seg1 || a.fn != 1 || !a.fn_rec || !a.fn_row || !a.fn_col) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_sketch_f64<L4, true, true, true>), grid, block, 0, s, a);
+  } else if (aligned) {
+    if (seg1) hipLaunchKernelGGL((k_sketch_f64<L4, true, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_sketch_f64<L4, true, false, false>), grid, block, 0, s, a);
   } else {
-    if (seg1) hipLaunchKernelGGL((k_sketch_f64<L4, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_sketch_f64<L4, false, false>), grid, block, 0, s, a);
+    if (seg1) hipLaunchKernelGGL((k_sketch_f64<L4, false, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_sketch_f64<L4, false, false, false>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }
@@ -915,6 +931,7 @@ static hipError_t launch_t(const SketchArgs& a, bool aligned, hipStream_t s) {
 }
 
 hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s) {
+  if (a.fn && prec != P_F64) return hipErrorInvalidValue;
   // 16-byte loads need every column (and segment start) 16-byte aligned.
   const int esz = prec == P_F64 ? 8 : 4;
   bool aligned = ((a.R * esz) % 16) == 0;

@@ -109,10 +109,19 @@ hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** R
 // to RK rows with zeros, so a column's RK entries are one contiguous run (wide
 // scalar loads).  Eight columns per step keep
 // eight loads in flight; every lane still adds its columns in increasing order.
-template <typename T, int RK, bool PAIR>
+// FN: X is the Hilbert tensor, X(row, col) = fn_rec[fn_row[row] + fn_col[col]],
+// evaluated in place of the loads.
+struct FnTabs {
+  const double* rec;
+  const int32_t* row;
+  const int32_t* col;
+};
+
+template <typename T, int RK, bool PAIR, bool FN>
 __global__ __launch_bounds__(256) void k_tt_error(const T* __restrict__ x, int64_t R, int64_t C, int r,
                                                   const double* __restrict__ L, const double* __restrict__ Rt,
-                                                  int gi_count, int gj_count, double* __restrict__ part) {
+                                                  int gi_count, int gj_count, double* __restrict__ part,
+                                                  const FnTabs fn) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int gi = blockIdx.x % gi_count, gj = blockIdx.x / gi_count;
   const int64_t row = (int64_t)gi * 512 + w * 128 + 2 * lane;
@@ -127,8 +136,17 @@ __global__ __launch_bounds__(256) void k_tt_error(const T* __restrict__ x, int64
   // rows read by this lane (clamped into the matrix; dropped via w0, w1)
   const int64_t r0c = ok0 ? row : 0, r1c = ok1 ? row + 1 : 0;
   const double w0 = ok0 ? 1.0 : 0.0, w1 = ok1 ? 1.0 : 0.0;
+  int fr0 = 0, fr1 = 0;
+  if constexpr (FN) {
+    fr0 = fn.row[r0c];
+    fr1 = fn.row[r1c];
+  }
   auto load2 = [&](int64_t col, double& x0, double& x1) {
-    if constexpr (PAIR) {
+    if constexpr (FN) {
+      const int fc = fn.col[col];
+      x0 = fn.rec[fr0 + fc];
+      x1 = fn.rec[fr1 + fc];
+    } else if constexpr (PAIR) {
       const T* p = x + col * R + r0c;
       if constexpr (sizeof(T) == 8) {
         const double2 v = *(const double2*)p;
@@ -225,16 +243,19 @@ __global__ void k_pad_rt(const double* __restrict__ Rt, int r, int RK, int64_t C
 
 static int rk_slot(int r) { return r <= 4 ? 4 : r <= 8 ? 8 : r <= 12 ? 12 : r <= 16 ? 16 : r <= 24 ? 24 : 32; }
 
-template <typename T, bool PAIR>
+template <typename T, bool PAIR, bool FN>
 static hipError_t launch_err_p(const T* x, int64_t R, int64_t C, int r, const double* L, const double* Rt, int gi,
-                               int gj, double* part, hipStream_t s) {
+                               int gj, double* part, const FnTabs& fn, hipStream_t s) {
   dim3 g((unsigned)(gi * gj)), b(256);
-  if (r <= 4) hipLaunchKernelGGL((k_tt_error<T, 4, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else if (r <= 8) hipLaunchKernelGGL((k_tt_error<T, 8, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else if (r <= 12) hipLaunchKernelGGL((k_tt_error<T, 12, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else if (r <= 16) hipLaunchKernelGGL((k_tt_error<T, 16, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else if (r <= 24) hipLaunchKernelGGL((k_tt_error<T, 24, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
-  else hipLaunchKernelGGL((k_tt_error<T, 32, PAIR>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part);
+  if (r <= 4) hipLaunchKernelGGL((k_tt_error<T, 4, PAIR, FN>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part, fn);
+  else if (r <= 8) hipLaunchKernelGGL((k_tt_error<T, 8, PAIR, FN>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part, fn);
+  else if (r <= 12)
+    hipLaunchKernelGGL((k_tt_error<T, 12, PAIR, FN>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part, fn);
+  else if (r <= 16)
+    hipLaunchKernelGGL((k_tt_error<T, 16, PAIR, FN>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part, fn);
+  else if (r <= 24)
+    hipLaunchKernelGGL((k_tt_error<T, 24, PAIR, FN>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part, fn);
+  else hipLaunchKernelGGL((k_tt_error<T, 32, PAIR, FN>), g, b, 0, s, x, R, C, r, L, Rt, gi, gj, part, fn);
   return hipGetLastError();
 }
 
@@ -243,11 +264,13 @@ static hipError_t launch_err(const T* x, int64_t R, int64_t C, int r, const doub
                              int gj, double* part, hipStream_t s) {
   // aligned pair loads need an even column length (and an aligned base)
   const bool pair = (R % 2) == 0 && ((uintptr_t)x % (2 * sizeof(T))) == 0;
-  return pair ? launch_err_p<T, true>(x, R, C, r, L, Rt, gi, gj, part, s)
-              : launch_err_p<T, false>(x, R, C, r, L, Rt, gi, gj, part, s);
+  const FnTabs none{nullptr, nullptr, nullptr};
+  return pair ? launch_err_p<T, true, false>(x, R, C, r, L, Rt, gi, gj, part, none, s)
+              : launch_err_p<T, false, false>(x, R, C, r, L, Rt, gi, gj, part, none, s);
 }
 
-hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s) {
+// x == nullptr: the Hilbert tensor (fn != 0), evaluated from its index tables
+hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s, int fn) {
   const int d = c->d;
   const int split = (d + 1) / 2;
   double *L = nullptr, *Rt = nullptr, *ifb = nullptr;
@@ -259,13 +282,21 @@ hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x
   const int r = c->r[split];
   const int gi = (int)((R + 511) / 512);
   const int gj = (int)std::max<int64_t>(1, std::min<int64_t>(C, (4096 + gi - 1) / gi));
-  double *part = nullptr, *Rp = nullptr;
+  double *part = nullptr, *Rp = nullptr, *rec = nullptr;
+  int32_t *row_t = nullptr, *col_t = nullptr;
   const int RK = rk_slot(r);
   e = ws_alloc((void**)&part, sizeof(double) * 2 * ((int64_t)gi * gj + 1), s);
   if (e == hipSuccess) e = ws_alloc((void**)&Rp, sizeof(double) * RK * C, s);
+  if (fn) {
+    if (e == hipSuccess) e = ws_alloc((void**)&rec, sizeof(double) * hilbert_rec_len(c->n, d), s);
+    if (e == hipSuccess) e = ws_alloc((void**)&row_t, sizeof(int32_t) * R, s);
+    if (e == hipSuccess) e = ws_alloc((void**)&col_t, sizeof(int32_t) * C, s);
+    if (e == hipSuccess) e = hilbert_tables(c->n, d, split, R, C, rec, row_t, col_t, s);
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pad_rt, dim3(grid_for(RK * C, 256)), dim3(256), 0, s, Rt, r, RK, C, Rp);
-  if (dtype == PSTT2_F64) e = launch_err((const double*)x, R, C, r, L, Rp, gi, gj, part, s);
+  if (fn) e = launch_err_p<double, false, true>(nullptr, R, C, r, L, Rp, gi, gj, part, FnTabs{rec, row_t, col_t}, s);
+  else if (dtype == PSTT2_F64) e = launch_err((const double*)x, R, C, r, L, Rp, gi, gj, part, s);
   else e = launch_err((const float*)x, R, C, r, L, Rp, gi, gj, part, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, gi * gj, part + 2 * (int64_t)gi * gj);
@@ -273,6 +304,9 @@ hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x
   }
   ws_free(part, s);
   ws_free(Rp, s);
+  if (rec) ws_free(rec, s);
+  if (row_t) ws_free(row_t, s);
+  if (col_t) ws_free(col_t, s);
   ws_free(ifb, s);
   hipError_t e2 = hipStreamSynchronize(s);
   return e != hipSuccess ? e : e2;

@@ -34,7 +34,7 @@ def setup(w, n=None, ell=None):
 def oracle_run(x, w, psi, omega, middle="onepass", drm="nested"):
     x64 = np.asarray(x, dtype=np.float64)
     drm = O.NestedKR(psi, omega) if drm == "nested" else O.IndependentKR(psi, omega)
-    if w.rank is not None:
+    if w.ranks() is not None:
         ref = O.pstt2(x64, w.n, drm, ranks=w.ranks(), middle=middle)
     else:
         ref = O.pstt2(x64, w.n, drm, eps=w.eps, rmax=w.rmax, middle=middle)
@@ -49,7 +49,7 @@ def gpu_run(x, w, fac, prec, slabs=None, middle="onepass", batched=False, ranks=
     kw = dict(dtype=w.dtype, prec=prec, mid=middle, drm=drm)
     if ranks is not None:
         kw["ranks"] = list(ranks)
-    elif w.rank is not None:
+    elif w.ranks() is not None:
         kw["ranks"] = w.ranks()
     else:
         kw["eps"] = w.eps

@@ -39,7 +39,7 @@ def test_enums_match_header():
     src = open(os.path.join(ROOT, "include", "pstt2.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     vals = {k: int(v) for k, v in re.findall(r"(PSTT2_\w+)\s*=\s*(-?\d+)", src)}
-    for table, prefix in ((L.MID, "PSTT2_MID_"), (L.DRM, "PSTT2_DRM_")):
+    for table, prefix in ((L.MID, "PSTT2_MID_"), (L.DRM, "PSTT2_DRM_"), (L.FN, "PSTT2_FN_")):
         names = {k[len(prefix):].lower(): v for k, v in vals.items() if k.startswith(prefix)}
         assert names == table, (prefix, names, table)
     assert vals["PSTT2_MID_TWOSIDED"] == 2
@@ -53,6 +53,7 @@ def test_struct_layouts_match_header():
     # d, pad, n[32], r[33], pad, core[32], owned, pad, stream
     assert ctypes.sizeof(L.TTCores) == 4 + 4 + 256 + 132 + 4 + 256 + 4 + 4 + 8
     assert L.TTCores.core.offset == 400 and L.TTCores.stream.offset == 664
+    assert ctypes.sizeof(L.Fn) == 4
 
 
 @pytest.mark.parametrize("field,value,msg", [
