@@ -15,6 +15,9 @@ Prints one JSON line.  `value` is whole-step throughput (bytes of X per step
 time; X is read twice per step: sketch and error).  `roofline` covers the
 dominant kernel (the streaming sketch), timed with HIP events on the stream it
 runs on.  `cpu_baseline` times the CPU FP64 oracle on a bounded sub-tensor.
+Unless --no-variants: the two-sided middle core, the independent DRM scheme,
+the precision study, the 64-slab stream, the adjoint, and Table 1's Hilbert
+tensors evaluated inside the kernels (never stored).
 """
 from __future__ import annotations
 
@@ -189,6 +192,50 @@ def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass", drm=
     return res
 
 
+def run_function(name, steps, warmup):
+    """Table 1's Hilbert tensors, evaluated inside the kernels (never stored): reset,
+    sketch, recover and the error pass against the same formula."""
+    import torch
+    import inputs
+    import paper_2111_10448_amd as P
+
+    w = inputs.WORKLOADS[name]
+    psi, omega = inputs.drm_factors(w)
+    fac = inputs.pack_factors(psi, omega, w.d)
+    ctx = P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", ranks=w.ranks())
+    log(f"[bench] {name}: Hilbert tensor n={w.n[0]}^{w.d}, timing {steps} steps")
+    t_err = 0.0
+    for it in range(warmup + steps):
+        if it == warmup:
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            ctx.profile_read()
+            t0 = time.perf_counter()
+        ctx.reset()
+        ctx.sketch_fn("hilbert")
+        tt = ctx.recover()
+        a = time.perf_counter()
+        err = tt.error_fn("hilbert")
+        if it >= warmup:
+            t_err += time.perf_counter() - a
+        ranks = tt.ranks
+        tt.free()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, launches = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    kms /= max(launches, 1)
+    flops = 4.0 * w.ell * w.numel
+    return {"workload": f"{name}: Hilbert tensor d={w.d} n={w.n[0]} ({w.numel} entries, "
+                        f"{8 * w.numel / 2**30:.2f} GiB in FP64, never stored), Table 1 ranks, sketch size {w.ell}",
+            "ranks": ranks, "tt_rel_error": err, "ms_per_step": round((t1 - t0) * 1e3 / steps, 4),
+            "sketch_kernel_ms": round(kms, 4), "error_pass_ms": round(t_err * 1e3 / steps, 4),
+            "sketch_entries_per_s": round(w.numel / (kms * 1e-3), 1),
+            "sketch_fp64_tflops": round(flops / (kms * 1e-3) / 1e12, 2),
+            "sketch_fp64_frac": round(flops / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+
+
 def run_adjoint(steps, warmup):
     """Forward PSTT2 + X~ and the hand-written gradient of ||X - X~||_F^2 on the d=4, n=48 FP32 tensor."""
     import torch
@@ -237,7 +284,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the two-sided middle core, the precision study (1/sum tensor in FP64, FP32, "
-                         "split BF16, BF16), the 64-slab stream and the adjoint")
+                         "split BF16, BF16), the 64-slab stream, the adjoint and Table 1's Hilbert tensors")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a 2 GiB device copy (counter calibration under rocprofv3) and exit")
     args = ap.parse_args()
@@ -313,6 +360,13 @@ def main():
             record["adjoint"] = run_adjoint(max(3, args.steps // 2), 1)
         except Exception as e:
             record["adjoint"] = {"error": str(e)}
+        t1 = {}
+        for wn in ("t1_d3", "t1_d5", "t1_d9"):
+            try:
+                t1[wn] = run_function(wn, max(3, args.steps // 2), 1)
+            except Exception as e:
+                t1[wn] = {"error": str(e)}
+        record["table1_hilbert"] = t1
     if not args.no_cpu_baseline:
         record["cpu_baseline"] = cpu_baseline(r["x"], w, r["psi"], r["omega"])
     print(json.dumps(record), flush=True)
