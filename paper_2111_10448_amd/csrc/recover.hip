@@ -798,30 +798,83 @@ hipError_t core_right(const double* Pprev, int64_t Cprev, int rprev, const doubl
 }
 
 // Z(a + rp i, c) = sum_{row < Rp} Qprev(row, a) Y(row + Rp i, c);  Z is (rp nm) x ell.
+// Z(a + rp i, c) = sum_row Qp(row, a) Y(row + Rp i, c): for each i a small
+// (rp x Rp)(Rp x ell) product.  A workgroup owns one i and a contiguous share
+// of the rows, stages 64-row tiles of Qp and of Y's slice in LDS and keeps up to
+// four of the rp x ell outputs per thread in registers across the tiles; with
+// nsplit > 1 shares it writes partials that k_sum_splits adds in a fixed order.
 __global__ __launch_bounds__(256) void k_middle_z(const double* __restrict__ Qp, int64_t Rp, int rp,
                                                   const double* __restrict__ Y, int64_t Rm, int nm, int ell,
-                                                  double* __restrict__ Z) {
+                                                  int nsplit, double* __restrict__ out) {
+  constexpr int MX = PSTT2_MAX_ELL, TR = 64;
+  __shared__ double Qs[TR][MX + 1], Ys[TR][MX + 1];
+  const int i = (int)(blockIdx.x % nm);
+  const int sp = (int)(blockIdx.x / nm);
+  const int64_t r0 = sp * Rp / nsplit, r1 = (sp + 1) * Rp / nsplit;
+  const int nout = rp * ell;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t base = r0; base < r1; base += TR) {
+    const int nr = (int)(r1 - base < TR ? r1 - base : TR);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TR * MX; e += blockDim.x) {
+      const int r = e % TR, j = e / TR;
+      Qs[r][j] = (r < nr && j < rp) ? Qp[(int64_t)j * Rp + base + r] : 0.0;
+      Ys[r][j] = (r < nr && j < ell) ? Y[(int64_t)j * Rm + base + r + Rp * i] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int o = threadIdx.x + 256 * k;
+      if (o < nout) {
+        const int a = o % rp, c = o / rp;
+        double sum = acc[k];
+        for (int r = 0; r < nr; ++r) sum += Qs[r][a] * Ys[r][c];
+        acc[k] = sum;
+      }
+    }
+  }
   const int64_t nz = (int64_t)rp * nm;
-  const int64_t tot = nz * ell;
-  const int lane = threadIdx.x & 63;
-  for (int64_t t = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; t < tot;
-       t += ((int64_t)gridDim.x * blockDim.x) >> 6) {
-    const int64_t rho = t % nz;
-    const int c = (int)(t / nz);
-    const int a = (int)(rho % rp);
-    const int i = (int)(rho / rp);
-    double s = 0.0;
-    for (int64_t row = lane; row < Rp; row += 64) s += Qp[(int64_t)a * Rp + row] * Y[(int64_t)c * Rm + row + Rp * i];
-    s = wave_sum(s);
-    if (lane == 0) Z[t] = s;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int o = threadIdx.x + 256 * k;
+    if (o < nout) {
+      const int a = o % rp, c = o / rp;
+      out[sp * nz * ell + a + (int64_t)rp * i + nz * c] = acc[k];
+    }
+  }
+}
+
+__global__ void k_sum_splits(const double* __restrict__ part, int nsplit, int64_t n, double* __restrict__ out) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double sum = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) sum += part[sp * n + t];
+    out[t] = sum;
   }
 }
 
 hipError_t middle_z(const double* Qprev, int64_t Rprev, int rprev, const double* Y, int64_t Rm, int nm, int ell,
                     double* Z, hipStream_t s) {
-  const int64_t tot = (int64_t)rprev * nm * ell;
-  hipLaunchKernelGGL(k_middle_z, dim3(waves_grid(tot)), dim3(256), 0, s, Qprev, Rprev, rprev, Y, Rm, nm, ell, Z);
-  return hipGetLastError();
+  if (rprev * ell > 1024 || rprev > PSTT2_MAX_ELL || ell > PSTT2_MAX_ELL) return hipErrorInvalidValue;
+  // enough workgroups to spread over the chip: split the rows when n_m is small
+  const int64_t want = (256 + nm - 1) / nm;
+  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(want, (Rprev + 255) / 256));
+  const int64_t n = (int64_t)rprev * nm * ell;
+  double* part = Z;
+  if (nsplit > 1) {
+    hipError_t e = ws_alloc((void**)&part, sizeof(double) * n * nsplit, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_middle_z, dim3((unsigned)(nm * nsplit)), dim3(256), 0, s, Qprev, Rprev, rprev, Y, Rm, nm, ell,
+                     nsplit, part);
+  hipError_t e = hipGetLastError();
+  if (nsplit > 1) {
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_sum_splits, dim3(grid_for(n, 256)), dim3(256), 0, s, part, nsplit, n, Z);
+      e = hipGetLastError();
+    }
+    ws_free(part, s);
+  }
+  return e;
 }
 
 __global__ void k_kr_table(const double* __restrict__ fac, const KRChain ch, int64_t rows, int ell,
@@ -1066,7 +1119,7 @@ __global__ __launch_bounds__(256) void k_middle_ls(const double* __restrict__ Z,
   for (int k = 0; k < rm; ++k) {
     if (t < rm) fcol[t] = Aug[t][k];
     __syncthreads();
-    if (t == 0 && !(fcol[k] > 1e-26 * dmax)) atomicOr(flag, 2);
+    if (t == 0 && blockIdx.x == 0 && !(fcol[k] > 1e-26 * dmax)) atomicOr(flag, 2);
     if (t < 2 * rm) {
       const double pk = Aug[k][t] / fcol[k];
       Aug[k][t] = pk;
@@ -1082,19 +1135,27 @@ __global__ __launch_bounds__(256) void k_middle_ls(const double* __restrict__ Z,
     Bm[c][b] = sum;
   }
   __syncthreads();
-  // G(rho, b) = sum_c Z(rho, c) Bm(c, b): consecutive threads take consecutive rows
-  for (int64_t o = t; o < nz * rm; o += blockDim.x) {
-    const int64_t rho = o % nz;
-    const int b = (int)(o / nz);
-    double sum = 0.0;
-    for (int c = 0; c < ell; ++c) sum += Z[(int64_t)c * nz + rho] * Bm[c][b];
-    G[o] = sum;
+  // G(rho, b) = sum_c Z(rho, c) Bm(c, b): every workgroup forms the same small
+  // Bm (identical arithmetic) and applies it to its own rows of Z, one row per
+  // thread (its ell entries read once, consecutive threads on consecutive rows)
+  for (int64_t rho = blockIdx.x * (int64_t)blockDim.x + t; rho < nz; rho += (int64_t)gridDim.x * blockDim.x) {
+    double z[MX];
+#pragma unroll
+    for (int c = 0; c < MX; ++c) z[c] = c < ell ? Z[(int64_t)c * nz + rho] : 0.0;
+    for (int b = 0; b < rm; ++b) {
+      double sum = 0.0;
+#pragma unroll
+      for (int c = 0; c < MX; ++c)
+        if (c < ell) sum += z[c] * Bm[c][b];
+      G[rho + nz * b] = sum;
+    }
   }
 }
 
 hipError_t middle_ls(const double* Z, int64_t nz, const double* A, int rm, int ell, double* G, int* flag,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_middle_ls, dim3(1), dim3(256), 0, s, Z, nz, A, rm, ell, G, flag);
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nz + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_middle_ls, dim3(nb), dim3(256), 0, s, Z, nz, A, rm, ell, G, flag);
   return hipGetLastError();
 }
 

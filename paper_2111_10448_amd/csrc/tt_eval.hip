@@ -20,18 +20,26 @@ static unsigned grid_for(int64_t n, int bs) {
 }
 
 // L_k(row + R_{k-1} i, b) = sum_a L_{k-1}(row, a) G_k(a, i, b)
+// One thread per row of L_k: its rp entries of L_{k-1} are read once and kept
+// in registers for all rk outputs (consecutive threads on consecutive rows).
 __global__ void k_left_iface(const double* __restrict__ Lp, int64_t Rp, int rp, const double* __restrict__ G, int nk,
                              int rk, double* __restrict__ L) {
+  constexpr int MX = PSTT2_MAX_ELL;
   const int64_t Rk = Rp * nk;
-  const int64_t tot = Rk * rk;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t rr = t % Rk;
-    const int b = (int)(t / Rk);
+  for (int64_t rr = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; rr < Rk; rr += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = rr % Rp;
     const int i = (int)(rr / Rp);
-    double s = 0.0;
-    for (int a = 0; a < rp; ++a) s += Lp[(int64_t)a * Rp + row] * G[a + (int64_t)rp * (i + (int64_t)nk * b)];
-    L[t] = s;
+    double lp[MX];
+#pragma unroll
+    for (int a = 0; a < MX; ++a) lp[a] = a < rp ? Lp[(int64_t)a * Rp + row] : 0.0;
+    for (int b = 0; b < rk; ++b) {
+      const double* g = G + (int64_t)rp * (i + (int64_t)nk * b);
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < MX; ++a)
+        if (a < rp) s += lp[a] * g[a];
+      L[rr + Rk * b] = s;
+    }
   }
 }
 
@@ -80,8 +88,8 @@ hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** R
     const int nk = (int)c->n[k];
     double* Ln = cur;
     cur += Rp * nk * c->r[k + 1];
-    hipLaunchKernelGGL(k_left_iface, dim3(grid_for(Rp * nk * c->r[k + 1], 256)), dim3(256), 0, s, L, Rp, c->r[k],
-                       c->core[k], nk, c->r[k + 1], Ln);
+    hipLaunchKernelGGL(k_left_iface, dim3(grid_for(Rp * nk, 256)), dim3(256), 0, s, L, Rp, c->r[k], c->core[k], nk,
+                       c->r[k + 1], Ln);
     L = Ln;
     Rp *= nk;
   }
