@@ -179,6 +179,23 @@ pstt2_status pstt2_sketch_fn(pstt2_ctx* ctx, const pstt2_fn* fn, int64_t first, 
  * ENUMERIC (non-finite sketch, rank-deficient least-squares system), ENOMEM, EDEVICE. */
 pstt2_status pstt2_recover(pstt2_ctx* ctx, tt_cores* out);
 
+/* Tolerance mode with a certificate.  The eps rule reads the ranks off the
+ * sketches, and its bound is probabilistic; Section 4.1 measures the error of
+ * every trial.  This call recovers, measures ||X - X~||_F / ||X||_F in a
+ * second pass over X (x_dev, the tensor that was sketched, in the context's
+ * dtype) or over the tensor function fn (give exactly one), and while the
+ * error exceeds eps recovers again from the same sketches (no new pass for
+ * them), with the rule's tolerance halved until at least one rank grows.  It
+ * stops when the error is at most eps, after max_tries recoveries, or when
+ * every rank is at its cap (rmax, ell - 2, the unfolding's size): then only a
+ * larger sketch size can help.  *out receives the last recovery's cores and
+ * *rel_err its measured error, which the caller compares with eps; the ranks
+ * are in out->r.  sync.  Errors: EINVAL (arguments), ESTATE (fixed-rank or
+ * two-pass context, or not every entry streamed), and those of pstt2_recover
+ * and tt_error. */
+pstt2_status pstt2_recover_certified(pstt2_ctx* ctx, const void* x_dev, const pstt2_fn* fn, int32_t max_tries,
+                                     tt_cores* out, double* rel_err);
+
 /* Two-pass middle core (equation "PSTT2_final_core"): add the contribution of a
  * slab of X to out->core[m-1] of the cores returned by pstt2_recover.  Same slab
  * rules as pstt2_sketch.  async.  Errors: ESTATE (context not in two-pass mode or

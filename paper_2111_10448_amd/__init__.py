@@ -230,6 +230,26 @@ class PSTT2:
         self._keep = []
         return TT(cs, self._stream)
 
+    def recover_certified(self, x=None, fn: Optional[str] = None, max_tries: int = 8):
+        """Tolerance mode: recover, measure the error against x (or the tensor function
+        fn), and recover again from the same sketches with a tighter rank rule while it
+        exceeds eps.  Returns (TT, relative error)."""
+        if (x is None) == (fn is None):
+            raise ValueError("give exactly one of x and fn")
+        if x is not None:
+            _check_dev(x)
+        fp = None
+        if fn is not None:
+            if fn not in L.FN:
+                raise ValueError(f"unknown tensor function {fn!r}")
+            fp = ctypes.byref(L.Fn(L.FN[fn]))
+        cs = L.TTCores()
+        err = ctypes.c_double()
+        L.check(L.lib().pstt2_recover_certified(self._c(), ctypes.c_void_p(x.data_ptr() if x is not None else 0), fp,
+                                                int(max_tries), ctypes.byref(cs), ctypes.byref(err)), self._ctx)
+        self._keep = []
+        return TT(cs, self._stream), err.value
+
     def middle_pass(self, tt: TT, x, first: int = 0) -> None:
         _check_dev(x)
         L.check(L.lib().pstt2_middle_pass(self._c(), ctypes.byref(tt.struct()), ctypes.c_void_p(x.data_ptr()),

@@ -90,6 +90,8 @@ def lib():
     L.tt_error.argtypes = [ctypes.POINTER(TTCores), vp, st, ctypes.POINTER(ctypes.c_double), vp]
     L.tt_reconstruct.argtypes = [ctypes.POINTER(TTCores), vp, st, i64, i64, vp]
     L.pstt2_sketch_fn.argtypes = [vp, ctypes.POINTER(Fn), i64, i64]
+    L.pstt2_recover_certified.argtypes = [vp, vp, ctypes.POINTER(Fn), i32, ctypes.POINTER(TTCores),
+                                          ctypes.POINTER(ctypes.c_double)]
     L.tt_error_fn.argtypes = [ctypes.POINTER(TTCores), ctypes.POINTER(Fn), ctypes.POINTER(ctypes.c_double), vp]
     L.tt_cores_copy.argtypes = [ctypes.POINTER(TTCores), ctypes.POINTER(TTCores), vp]
     L.tt_cores_free.argtypes = [ctypes.POINTER(TTCores)]
@@ -100,7 +102,7 @@ def lib():
     L.pstt2_version.restype = ctypes.c_char_p
     for f in ("pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
               "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_reset", "tt_error", "tt_reconstruct", "tt_cores_copy",
-              "pstt2_profile", "pstt2_profile_read", "pstt2_sketch_fn", "tt_error_fn"):
+              "pstt2_profile", "pstt2_profile_read", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -115,5 +117,5 @@ def check(status: int, ctx=None) -> None:
 # Every symbol include/pstt2.h declares.
 EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
            "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_profile", "pstt2_profile_read", "pstt2_reset",
-           "pstt2_destroy", "tt_error", "tt_reconstruct", "pstt2_sketch_fn", "tt_error_fn",
+           "pstt2_destroy", "tt_error", "tt_reconstruct", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified",
            "tt_cores_copy", "tt_cores_free", "pstt2_last_error", "pstt2_version"]

@@ -65,6 +65,10 @@ struct pstt2_ctx {
   double* sinkT = nullptr;
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_pool;
+  // tolerance mode: factor applied to eps by the rank rule (pstt2_recover_certified)
+  // and the singular values of the last recovery's R factors, [k * ell + i]
+  double eps_scale = 1.0;
+  std::vector<double> sv_last;
   // index tables of the Hilbert tensor (pstt2_sketch_fn), built on first use
   double* fn_rec = nullptr;
   int32_t* fn_row = nullptr;
@@ -322,6 +326,19 @@ __global__ void k_transpose_last(const double* P, int64_t rows, int r, double* G
 }
 
 // smallest r with sum_{i>r} sigma_i^2 <= eps^2/(d-1) * sum sigma_i^2, at least 1
+int tolerance_rank(const double* s, int ell, double eps, int d);
+
+// Rank of split k in tolerance mode: the eps rule on its singular values,
+// capped at rmax, at ell - 2 and at the unfolding's size.
+int rank_from_rule(const pstt2_ctx* c, int k, const double* sv, double eps) {
+  const int ell = c->ell;
+  const int64_t cap = std::min<int64_t>({c->Rk[k], c->N / c->Rk[k], (int64_t)ell});
+  int rmax = c->desc.rmax > 0 ? c->desc.rmax : ell;
+  rmax = std::min(rmax, std::max(1, ell - 2));
+  const int rr = tolerance_rank(sv + (size_t)k * ell, ell, eps, c->d);
+  return (int)std::min<int64_t>({(int64_t)rr, (int64_t)rmax, cap});
+}
+
 int tolerance_rank(const double* s, int ell, double eps, int d) {
   double tot = 0.0;
   for (int i = 0; i < ell; ++i) tot += s[i] * s[i];
@@ -774,17 +791,10 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   }
   for (int k = 1; k <= d - 1; ++k) {
     const int64_t cap = std::min<int64_t>({c->Rk[k], c->N / c->Rk[k], (int64_t)ell});
-    int rk;
-    if (!tol) {
-      rk = (int)std::min<int64_t>(c->desc.ranks[k - 1], cap);
-    } else {
-      int rmax = c->desc.rmax > 0 ? c->desc.rmax : ell;
-      rmax = std::min(rmax, std::max(1, ell - 2));
-      const int rr = tolerance_rank(sv.data() + (size_t)k * ell, ell, c->desc.eps, d);
-      rk = (int)std::min<int64_t>({(int64_t)rr, (int64_t)rmax, cap});
-    }
-    r[k] = rk;
+    r[k] = tol ? rank_from_rule(c, k, sv.data(), c->desc.eps * c->eps_scale)
+               : (int)std::min<int64_t>(c->desc.ranks[k - 1], cap);
   }
+  if (tol) c->sv_last = sv;
   // (3) bases
   {
     std::vector<double*> Qp(d - 1);
@@ -899,6 +909,59 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   }
   *out = tc;
   c->recovered = true;
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_recover_certified(pstt2_ctx* c, const void* x_dev, const pstt2_fn* fn, int32_t max_tries,
+                                     tt_cores* out, double* rel_err) {
+  if (!c || !out || !rel_err) return fail(c, PSTT2_EINVAL, "null argument");
+  if ((x_dev == nullptr) == (fn == nullptr)) return fail(c, PSTT2_EINVAL, "give exactly one of x_dev and fn");
+  if (fn && fn->kind != PSTT2_FN_HILBERT) return fail(c, PSTT2_EINVAL, "unknown tensor function");
+  if (c->desc.ranks[0] > 0) return fail(c, PSTT2_ESTATE, "certified recovery needs a tolerance-mode context");
+  if (c->desc.mid == PSTT2_MID_TWOPASS) return fail(c, PSTT2_ESTATE, "certified recovery covers the one-pass cores");
+  if (max_tries < 1) return fail(c, PSTT2_EINVAL, "max_tries must be >= 1");
+  const int d = c->d;
+  double scale = 1.0, err = INFINITY;
+  tt_cores best;
+  std::memset(&best, 0, sizeof(best));
+  bool have = false;
+  pstt2_status st = PSTT2_OK;
+  for (int t = 0; t < max_tries; ++t) {
+    c->eps_scale = scale;
+    tt_cores tc;
+    std::memset(&tc, 0, sizeof(tc));
+    st = pstt2_recover(c, &tc);
+    if (st != PSTT2_OK) break;
+    double e = 0.0;
+    st = x_dev ? tt_error(&tc, x_dev, (pstt2_dtype)c->dtype, &e, c->stream) : tt_error_fn(&tc, fn, &e, c->stream);
+    if (st != PSTT2_OK) {
+      c->err = g_tls_err;
+      tt_cores_free(&tc);
+      break;
+    }
+    if (have) tt_cores_free(&best);
+    best = tc;
+    have = true;
+    err = e;
+    if (e <= c->desc.eps) break;
+    // tighten the rule until some rank grows (the singular values do not depend
+    // on eps, so the next recovery takes exactly these ranks); stop when every
+    // rank sits at its cap: then only a larger sketch size helps
+    bool grew = false;
+    for (int j = 0; j < 64 && !grew; ++j) {
+      scale *= 0.5;
+      for (int k = 1; k <= d - 1 && !grew; ++k)
+        grew = rank_from_rule(c, k, c->sv_last.data(), c->desc.eps * scale) > c->ranks[k];
+    }
+    if (!grew) break;
+  }
+  c->eps_scale = 1.0;
+  if (st != PSTT2_OK) {
+    if (have) tt_cores_free(&best);
+    return st;
+  }
+  *out = best;
+  *rel_err = err;
   return PSTT2_OK;
 }
 

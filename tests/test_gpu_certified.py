@@ -1,0 +1,111 @@
+"""GPU parity of the certified tolerance mode (pstt2_recover_certified).
+
+The eps rule reads the ranks off the sketches' singular values and its bound
+is probabilistic: on the pinned tensors below it misses eps by 2.5x to 4x.  The
+certified call measures the error and recovers again from the same sketches
+with the rule's tolerance halved until some rank grows.  The same policy is
+run here on the oracle (its own sketches, its own rank rule, its fixed-rank
+PSTT2 at each step), and the two must end at the same ranks, the same X~ and
+the same error.
+"""
+import numpy as np
+import pytest
+
+import inputs
+from oracle import tt_sketch as O
+
+from gpu_common import compare, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_policy(x, w, drm, eps, max_tries):
+    n, d = w.n, w.d
+    m = O.middle_index(d)
+    base = O.pstt2(x, n, drm, eps=eps, rmax=w.rmax)
+    sks = [base["S"][k] if k < m else base["T"][k].T for k in range(1, d)]
+    cap = w.rmax if w.rmax > 0 else w.ell
+    cap = min(cap, max(1, w.ell - 2))
+
+    def ranks_at(e):
+        return O._clamp_ranks(n, [O.rank_from_tolerance(sk, e, d, cap) for sk in sks], w.ell)
+
+    scale, tries = 1.0, 0
+    while True:
+        r = ranks_at(eps * scale)
+        ref = O.pstt2(x, n, drm, ranks=r)
+        err = O.tt_error(x, ref["cores"])
+        tries += 1
+        if err <= eps or tries == max_tries:
+            break
+        grew = False
+        for _ in range(64):
+            scale *= 0.5
+            if any(a > b for a, b in zip(ranks_at(eps * scale), r)):
+                grew = True
+                break
+        if not grew:
+            break
+    return r, err, tries, ref
+
+
+@pytest.mark.parametrize("name,eps,source,certified", [
+    ("c5_fd", 0.1, "memory", True),         # first try: ranks (5, 6, 5), error 0.25
+    ("t1_small5", 1e-4, "hilbert", True),   # first try: error 4.5e-4
+    ("t1_small3", 3e-6, "hilbert", True),
+    ("c5_fd", 1e-4, "memory", False),       # below the noise floor: stops with every rank at its cap
+])
+def test_certified_tolerance_mode_matches_oracle_policy(name, eps, source, certified):
+    import dataclasses
+    import torch
+    import paper_2111_10448_amd as P
+    w = dataclasses.replace(inputs.WORKLOADS[name], eps=eps, rmax=0, rank=None, rank_list=())
+    say(f"[gpu] certified tolerance mode {name} eps={eps:g} ({source})")
+    x = inputs.make_tensor(w).astype(np.float64)
+    psi, om = inputs.drm_factors(w)
+    drm = O.NestedKR(psi, om)
+    fac = inputs.pack_factors(psi, om, w.d)
+    r_ref, e_ref, tries, ref = _oracle_policy(x, w, drm, eps, 8)
+    xg = torch.from_numpy(x).cuda()
+    ctx = P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", eps=eps, rmax=0)
+    if source == "memory":
+        ctx.sketch(xg)
+        tt, err = ctx.recover_certified(x=xg, max_tries=8)
+    else:
+        ctx.sketch_fn(source)
+        tt, err = ctx.recover_certified(fn=source, max_tries=8)
+    say(f"    oracle: {tries} recoveries, ranks {r_ref}, error {e_ref:.3e}; GPU ranks {tt.ranks[1:-1]}, "
+        f"error {err:.3e}")
+    assert tries >= 2
+    assert tt.ranks == [1] + list(r_ref) + [1]
+    assert abs(err - e_ref) <= 1e-8 * e_ref
+    assert (err <= eps) == certified
+    ref["drm"] = drm
+    out = compare(ctx, tt, xg, x, w, ref, "f64")
+    say(f"    X~ parity {out['Xt']:.2e}")
+    tt.free()
+    ctx.close()
+
+
+def test_certified_refuses_fixed_rank_and_bad_arguments():
+    import paper_2111_10448_amd as P
+    from paper_2111_10448_amd import _lib as L
+    w = inputs.WORKLOADS["c5_fd"]
+    say("[gpu] certified mode argument checks")
+    x = inputs.make_tensor(w)
+    psi, om = inputs.drm_factors(w)
+    fac = inputs.pack_factors(psi, om, w.d)
+    import torch
+    xg = torch.from_numpy(x).cuda()
+    with P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", ranks=w.ranks()) as ctx:
+        ctx.sketch(xg)
+        with pytest.raises(P.PSTT2Error) as e:
+            ctx.recover_certified(x=xg)
+        assert e.value.status == L.ESTATE
+    with P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", eps=1e-2) as ctx:
+        ctx.sketch(xg)
+        with pytest.raises(ValueError):
+            ctx.recover_certified(x=xg, fn="hilbert")
+        with pytest.raises(P.PSTT2Error) as e:
+            ctx.recover_certified(x=xg, max_tries=0)
+        assert e.value.status == L.EINVAL
