@@ -110,7 +110,7 @@ def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 30.0):
 _HOST = {}
 
 
-def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass", drm="nested"):
+def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass", drm="nested", algo="pstt2"):
     import torch
     import inputs
     import paper_2111_10448_amd as P
@@ -132,7 +132,7 @@ def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass", drm=
     log(f"[bench] {name} {prec}: timing {steps} steps")
     xg = torch.from_numpy(x).to("cuda:0")
     torch.cuda.synchronize()
-    kw = dict(dtype=w.dtype, prec=prec, mid=mid, drm=drm)
+    kw = dict(dtype=w.dtype, prec=prec, mid=mid, drm=drm, algo=algo)
     if ranks_from is not None:
         kw["ranks"] = ranks_from
     elif w.rank is not None:
@@ -336,18 +336,24 @@ def main():
     }
     if not args.no_variants:
         var = {}
-        for wn, vp, mid, drm in (("c2", "f64", "twosided", "nested"), ("c2", "f64", "onepass", "independent"),
-                                 ("c3_f64", "f64", "onepass", "nested"), ("c3", "f32", "onepass", "nested"),
-                                 ("c3", "bf16x3", "onepass", "nested"), ("c3", "bf16", "onepass", "nested"),
-                                 ("c4", "f32", "onepass", "nested"), ("c4", "bf16x3", "onepass", "nested")):
-            key = f"{wn}_{vp}" + ("" if mid == "onepass" else f"_{mid}") + ("" if drm == "nested" else f"_{drm}")
+        for wn, vp, mid, drm, algo in (("c2", "f64", "twosided", "nested", "pstt2"),
+                                       ("c2", "f64", "onepass", "independent", "pstt2"),
+                                       ("c2", "f64", "onepass", "nested", "pstt"),
+                                       ("c3_f64", "f64", "onepass", "nested", "pstt2"),
+                                       ("c3", "f32", "onepass", "nested", "pstt2"),
+                                       ("c3", "bf16x3", "onepass", "nested", "pstt2"),
+                                       ("c3", "bf16", "onepass", "nested", "pstt2"),
+                                       ("c4", "f32", "onepass", "nested", "pstt2"),
+                                       ("c4", "bf16x3", "onepass", "nested", "pstt2")):
+            key = (f"{wn}_{vp}" + ("" if mid == "onepass" else f"_{mid}") + ("" if drm == "nested" else f"_{drm}")
+                   + ("" if algo == "pstt2" else f"_{algo}"))
             try:
-                rv = run_workload(wn, vp, max(3, args.steps // 2), 1, mid=mid, drm=drm)
+                rv = run_workload(wn, vp, max(3, args.steps // 2), 1, mid=mid, drm=drm, algo=algo)
                 wv = rv["workload"]
                 # the independent scheme streams X once per pass group (max(m, d - m) groups)
                 groups = max((wv.d + 1) // 2, wv.d - (wv.d + 1) // 2) if drm == "independent" else 1
                 kbv = rv["bytes"] * groups / max(rv["launches_per_step"], 1)
-                var[key] = {"workload": wn, "sketch_arithmetic": vp, "middle_core": mid, "drm": drm,
+                var[key] = {"workload": wn, "sketch_arithmetic": vp, "middle_core": mid, "drm": drm, "algorithm": algo,
                             "sketch_launches_per_step": rv["launches_per_step"],
                            "sketch_kernel_ms": round(rv["kernel_ms"], 4),
                            "sketch_gbs": round(kbv / (rv["kernel_ms"] * 1e-3) / 1e9, 2),

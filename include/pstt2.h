@@ -92,6 +92,20 @@ typedef enum { PSTT2_MID_ONEPASS = 0, PSTT2_MID_TWOPASS = 1, PSTT2_MID_TWOSIDED 
  * The adjoint (pstt2_vjp) covers both. */
 typedef enum { PSTT2_DRM_NESTED = 0, PSTT2_DRM_INDEPENDENT = 1 } pstt2_drm;
 
+/* Algorithm.
+ *   PSTT2  two-sided (default): column bases Q_k for k < m = ceil(d/2), row
+ *          bases P_k for k >= m, and a middle core (see pstt2_mid).
+ *   PSTT   one-sided (Algorithm PSTT): column bases Q_1..Q_{d-1} of every
+ *          unfolding, cores by equation "core", and the last core either from
+ *          the extra left sketch T_{d-1} = Psi_{d-1}^T X_{d-1} by the one-pass
+ *          rule G_d = (Psi_{d-1}^T Q_{d-1})^+ T_{d-1} (mid ONEPASS, PSTT-onepass,
+ *          equation "onepass_final_core") or by a second pass
+ *          G_d = Q_{d-1}^T X_{d-1} (mid TWOPASS, pstt2_middle_pass).  The pass
+ *          sketches the split d-1, so the right sketch is R_{d-1} x ell
+ *          (N / n_d rows: the one-sided method's storage cost, Section 4.3).
+ *          TWOSIDED is refused; pstt2_vjp reports ESTATE. */
+typedef enum { PSTT2_ALGO_PSTT2 = 0, PSTT2_ALGO_PSTT = 1 } pstt2_algo;
+
 typedef struct {
   int32_t d;                  /* order, 2 <= d <= PSTT2_MAX_D */
   int64_t n[PSTT2_MAX_D];     /* mode sizes n_1..n_d in n[0..d-1], each >= 1 */
@@ -108,6 +122,7 @@ typedef struct {
                                  omega_2..omega_d.  INDEPENDENT: for split k = 1..d-1 in turn,
                                  psi^(k)_1..psi^(k)_k then omega^(k)_{k+1}..omega^(k)_d */
   pstt2_drm drm;              /* factor scheme */
+  pstt2_algo algo;            /* two-sided PSTT2 (0) or one-sided PSTT */
 } pstt2_desc;
 
 /* A tensor train.  Core k (0-based) is r[k] x n[k] x r[k+1], column-major

@@ -157,7 +157,7 @@ class PSTT2:
 
     def __init__(self, n: Sequence[int], ell: int, factors: np.ndarray, *, dtype: str = "f64",
                  prec: Optional[str] = None, ranks: Optional[Sequence[int]] = None, eps: Optional[float] = None,
-                 rmax: int = 0, mid: str = "onepass", drm: str = "nested", stream=None):
+                 rmax: int = 0, mid: str = "onepass", drm: str = "nested", algo: str = "pstt2", stream=None):
         self.n = [int(v) for v in n]
         self.d = len(self.n)
         self.ell = int(ell)
@@ -172,6 +172,7 @@ class PSTT2:
         desc.prec = L.PREC[prec]
         desc.mid = L.MID[mid]
         desc.drm = L.DRM[drm]
+        desc.algo = L.ALGO[algo]
         if ranks is not None:
             for k, v in enumerate(ranks):
                 desc.ranks[k] = int(v)

@@ -22,6 +22,7 @@ PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 MID = {"onepass": 0, "twopass": 1, "twosided": 2}
 DRM = {"nested": 0, "independent": 1}
 FN = {"hilbert": 0}
+ALGO = {"pstt2": 0, "pstt": 1}
 
 
 class Desc(ctypes.Structure):
@@ -37,6 +38,7 @@ class Desc(ctypes.Structure):
         ("ell", ctypes.c_int32),
         ("drm_factors", ctypes.POINTER(ctypes.c_double)),
         ("drm", ctypes.c_int),
+        ("algo", ctypes.c_int),
     ]
 
 

@@ -56,6 +56,7 @@ struct pstt2_ctx {
   // right splits k < m, the extra sketches of X_m, and sinks for pass groups
   // with only one side
   bool indep = false;
+  bool pstt = false;   // one-sided Algorithm PSTT: the pass sketches split d-1
   int64_t ipsi_off[PSTT2_MAX_D + 1][PSTT2_MAX_D] = {};  // [split k][mode q-1]
   int64_t iom_off[PSTT2_MAX_D + 1][PSTT2_MAX_D] = {};
   std::vector<double*> iom_tab;   // [k], k < m
@@ -380,6 +381,9 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
     return fail(nullptr, PSTT2_EINVAL, "bad mid");
   if (!desc->drm_factors) return fail(nullptr, PSTT2_EINVAL, "drm_factors is required");
   if (desc->drm != PSTT2_DRM_NESTED && desc->drm != PSTT2_DRM_INDEPENDENT) return fail(nullptr, PSTT2_EINVAL, "bad drm");
+  if (desc->algo != PSTT2_ALGO_PSTT2 && desc->algo != PSTT2_ALGO_PSTT) return fail(nullptr, PSTT2_EINVAL, "bad algo");
+  if (desc->algo == PSTT2_ALGO_PSTT && desc->mid == PSTT2_MID_TWOSIDED)
+    return fail(nullptr, PSTT2_EINVAL, "the one-sided algorithm has no two-sided middle core");
   const bool tol = desc->ranks[0] <= 0;
   if (tol && !(desc->eps > 0.0 && desc->eps < 1.0)) return fail(nullptr, PSTT2_EINVAL, "tolerance mode needs 0 < eps < 1");
   int64_t N = 1;
@@ -397,7 +401,9 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   c->desc = *desc;
   c->stream = (hipStream_t)hip_stream;
   c->d = d;
-  c->m = (d + 1) / 2;
+  // the pass sketches the middle split (PSTT2) or the last split (PSTT)
+  c->m = desc->algo == PSTT2_ALGO_PSTT ? d - 1 : (d + 1) / 2;
+  c->pstt = desc->algo == PSTT2_ALGO_PSTT;
   c->ell = desc->ell;
   c->lp = desc->ell <= 16 ? 16 : 32;
   c->prec = desc->prec;
@@ -739,10 +745,11 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
     tb.chain = c->chain_dev;
     for (int k = 1; k <= d - 1; ++k) {
       const int p = tb.n++;
+      const bool col = k < m || c->pstt;   // operand S_k (PSTT: S_{d-1} = Y)
       tb.split[p] = k;
-      tb.right[p] = k >= m;
-      tb.S[p] = k < m ? c->S[k] : c->Tk[k];
-      tb.K[p] = k < m ? c->Rk[k] : c->N / c->Rk[k];
+      tb.right[p] = !col;
+      tb.S[p] = col ? c->S[k] : c->Tk[k];
+      tb.K[p] = col ? c->Rk[k] : c->N / c->Rk[k];
       tb.out[p] = c->Bk + (int64_t)k * ell * ell;
     }
     HIPCK(c, two_sided_batch(tb, s));
@@ -755,8 +762,9 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   std::vector<int64_t> Mp(d - 1);
   std::vector<int*> pivp(d - 1);
   for (int k = 1; k <= d - 1; ++k) {
-    Ap[k - 1] = k < m ? c->S[k] : c->Tk[k];
-    Mp[k - 1] = k < m ? c->Rk[k] : c->N / c->Rk[k];
+    const bool col = k < m || c->pstt;   // column basis Q_k from S_k, else row basis P_k from T_k
+    Ap[k - 1] = col ? c->S[k] : c->Tk[k];
+    Mp[k - 1] = col ? c->Rk[k] : c->N / c->Rk[k];
     pivp[k - 1] = c->piv_dev + (int64_t)k * ell;
   }
   BasisBatch* bw = nullptr;
@@ -832,13 +840,56 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
     return hfail(c, e, w);
   };
   hipError_t e = hipSuccess;
-  for (int k = 1; k <= m - 1 && e == hipSuccess; ++k) {
+  // column-basis cores G_1 .. G_{m-1} (PSTT: G_1 .. G_{d-1})
+  const int kl_end = c->pstt ? d - 1 : m - 1;
+  for (int k = 1; k <= kl_end && e == hipSuccess; ++k) {
     if (k == 1)
       e = hipMemcpyAsync(tc.core[0], c->basis[1], sizeof(double) * c->n[0] * r[1], hipMemcpyDeviceToDevice, s);
     else
       e = core_left(c->basis[k - 1], c->Rk[k - 1], r[k - 1], c->basis[k], (int)c->n[k - 1], r[k], tc.core[k - 1], s);
   }
-  for (int k = m + 1; k <= d && e == hipSuccess; ++k) {
+  if (c->pstt) {
+    if (e != hipSuccess) return cfail(e, "cores");
+    // last core G_d (r_{d-1} x n_d).  One pass: G_d = (Psi^T Q)^+ T with
+    // Psi = Psi_{d-1}, Q = Q_{d-1} and T = T_{d-1} = Psi^T X_{d-1} (kept
+    // transposed, n_d x ell): G_d^T = T^T A (A^T A)^{-1} with A = Psi^T Q
+    // (ell x r), i.e. the least-squares kernel with right-hand side T^T and
+    // system matrix A^T.  Two pass: zero here, pstt2_middle_pass adds Q^T X_{d-1}.
+    const int rl = r[d - 1];
+    const int64_t nd = c->n[d - 1];
+    if (c->desc.mid == PSTT2_MID_TWOPASS) {
+      e = hipMemsetAsync(tc.core[d - 1], 0, sizeof(double) * rl * nd, s);
+    } else {
+      double *A = nullptr, *At = nullptr, *Gt = nullptr;
+      e = ws_alloc((void**)&A, sizeof(double) * ell * ell, s);
+      if (e == hipSuccess) e = ws_alloc((void**)&At, sizeof(double) * rl * ell, s);
+      if (e == hipSuccess) e = ws_alloc((void**)&Gt, sizeof(double) * nd * rl, s);
+      if (e == hipSuccess) {
+        TwoSidedBatch tb;
+        std::memset(&tb, 0, sizeof(tb));
+        tb.d = d;
+        tb.ell = ell;
+        tb.fac = c->fac;
+        tb.chain = c->chain_dev;
+        tb.n = 1;
+        tb.split[0] = d - 1;
+        tb.right[0] = 0;
+        tb.S[0] = c->basis[d - 1];
+        tb.scols[0] = rl;
+        tb.K[0] = c->Rk[d - 1];
+        tb.out[0] = A;   // ell x ell, columns >= r zero
+        e = two_sided_batch(tb, s);
+      }
+      if (e == hipSuccess) e = adj_transpose(A, ell, rl, At, s);
+      if (e == hipSuccess) e = middle_ls(c->Tt, nd, At, rl, ell, Gt, c->flag, s);
+      if (e == hipSuccess) e = adj_transpose(Gt, nd, rl, tc.core[d - 1], s);
+      ws_free(A, s);
+      ws_free(At, s);
+      ws_free(Gt, s);
+    }
+    if (e != hipSuccess) return cfail(e, "last core");
+  }
+  for (int k = m + 1; k <= d && e == hipSuccess && !c->pstt; ++k) {
     if (k == d) {
       const int64_t rows = c->n[d - 1];
       hipLaunchKernelGGL(k_transpose_last, dim3(64), dim3(256), 0, s, c->basis[d - 1], rows, r[d - 1], tc.core[d - 1]);
@@ -852,7 +903,9 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   const double* Qprev = m >= 2 ? c->basis[m - 1] : c->one;
   const int64_t Rprev = c->Rk[m - 1];
   const int64_t nz = (int64_t)r[m - 1] * c->n[m - 1];
-  if (c->desc.mid == PSTT2_MID_ONEPASS || c->desc.mid == PSTT2_MID_TWOSIDED) {
+  if (c->pstt) {
+    // every core is formed above
+  } else if (c->desc.mid == PSTT2_MID_ONEPASS || c->desc.mid == PSTT2_MID_TWOSIDED) {
     double *Z = nullptr, *A = nullptr;
     const int nm = (int)c->n[m - 1];
     e = ws_alloc((void**)&Z, sizeof(double) * nz * ell, s);
@@ -972,6 +1025,13 @@ pstt2_status pstt2_middle_pass(pstt2_ctx* c, tt_cores* cores, const void* x_dev,
   if (first < 0 || count < 0 || first + count > c->N) return fail(c, PSTT2_EINVAL, "slab range outside the tensor");
   if (first % c->n[0] != 0 || count % c->n[0] != 0) return fail(c, PSTT2_EINVAL, "slab must hold whole mode-1 fibres");
   const int m = c->m;
+  if (c->pstt) {
+    // last core of the one-sided algorithm: G_d(a, i) += sum_row Q_{d-1}(row, a) X(row + R_{d-1} i)
+    const int d = c->d;
+    HIPCK(c, middle_twopass(c->dtype, x_dev, first, count, c->Rk[d - 1], (int)c->n[d - 1], 1, c->basis[d - 1],
+                            c->ranks[d - 1], c->one, 1, cores->core[d - 1], c->stream));
+    return PSTT2_OK;
+  }
   const double* Qprev = m >= 2 ? c->basis[m - 1] : c->one;
   HIPCK(c, middle_twopass(c->dtype, x_dev, first, count, c->Rk[m - 1], (int)c->n[m - 1], c->C, Qprev,
                           c->ranks[m - 1], c->basis[m], c->ranks[m], cores->core[m - 1], c->stream));
@@ -984,6 +1044,7 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   if (!gbar_dev && !x_dev) return fail(c, PSTT2_EINVAL, "x_dev is needed for the fused loss (gbar_dev == NULL)");
   if (!c->recovered) return fail(c, PSTT2_ESTATE, "pstt2_vjp needs a successful pstt2_recover first");
   if (c->desc.mid == PSTT2_MID_TWOPASS) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the one-pass middle cores only");
+  if (c->pstt) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the two-sided algorithm only");
   const int d = c->d, m = c->m, ell = c->ell;
   if (cores->d != d) return fail(c, PSTT2_EINVAL, "cores do not match the context");
   for (int k = 0; k < d; ++k)

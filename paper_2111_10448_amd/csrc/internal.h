@@ -154,6 +154,7 @@ struct TwoSidedBatch {
   const double* S[PSTT2_MAX_D];
   int64_t K[PSTT2_MAX_D];
   int split[PSTT2_MAX_D], right[PSTT2_MAX_D];
+  int scols[PSTT2_MAX_D];   // columns of S (0: ell; fewer: the rest of the product is zero)
   double* out[PSTT2_MAX_D];
   int64_t blk0[PSTT2_MAX_D + 1];
 };

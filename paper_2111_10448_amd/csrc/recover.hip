@@ -931,12 +931,13 @@ __global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, d
   const int64_t* off = B.chain + ((int64_t)k * 2 + right) * d;
   const int64_t* nmode = B.chain + (int64_t)(d + 1) * 2 * d;
   const double* __restrict__ S = B.S[p];
+  const int sc = B.scols[p] > 0 ? B.scols[p] : ell;
   for (int e = t; e < TS_ROWS * ell; e += 256) {
     const int r = e % TS_ROWS, u = e / TS_ROWS;
     const int64_t row = r0 + r;
     double sv = 0.0, fv = 0.0;
     if (row < K) {
-      sv = S[(int64_t)u * K + row];
+      sv = u < sc ? S[(int64_t)u * K + row] : 0.0;
       int64_t rest = row;
       fv = 1.0;
       for (int j = 0; j < cnt; ++j) {

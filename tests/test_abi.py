@@ -39,7 +39,7 @@ def test_enums_match_header():
     src = open(os.path.join(ROOT, "include", "pstt2.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     vals = {k: int(v) for k, v in re.findall(r"(PSTT2_\w+)\s*=\s*(-?\d+)", src)}
-    for table, prefix in ((L.MID, "PSTT2_MID_"), (L.DRM, "PSTT2_DRM_"), (L.FN, "PSTT2_FN_")):
+    for table, prefix in ((L.MID, "PSTT2_MID_"), (L.DRM, "PSTT2_DRM_"), (L.FN, "PSTT2_FN_"), (L.ALGO, "PSTT2_ALGO_")):
         names = {k[len(prefix):].lower(): v for k, v in vals.items() if k.startswith(prefix)}
         assert names == table, (prefix, names, table)
     assert vals["PSTT2_MID_TWOSIDED"] == 2
@@ -50,6 +50,7 @@ def test_struct_layouts_match_header():
     from paper_2111_10448_amd import _lib as L
     assert ctypes.sizeof(L.Desc) == 440
     assert L.Desc.eps.offset == 408 and L.Desc.drm_factors.offset == 424 and L.Desc.drm.offset == 432
+    assert L.Desc.algo.offset == 436
     # d, pad, n[32], r[33], pad, core[32], owned, pad, stream
     assert ctypes.sizeof(L.TTCores) == 4 + 4 + 256 + 132 + 4 + 256 + 4 + 4 + 8
     assert L.TTCores.core.offset == 400 and L.TTCores.stream.offset == 664
