@@ -32,6 +32,17 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+
+// Two 4-element bf16 operands as one 8-element operand of the 16x16x32 bf16
+// matrix instruction.  Both operands of a product are joined the same way, so
+// element v of lane l pairs the same K index in A and B whatever order the
+// hardware assigns to the 32 K slots.
+__device__ __forceinline__ b8 join8(s4 lo, s4 hi) {
+  const s8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(b8, v);
+}
 
 enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 
@@ -555,37 +566,56 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     accv tacc[NT];
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt) tacc[mt] = accv{0, 0, 0, 0};
+    if constexpr (X3) {
+      // split BF16: two 16-row K steps per 16x16x32 instruction (rows
+      // 32j + 4 g4 + v and 32j + 16 + 4 g4 + v in the two halves of an
+      // operand), half the instructions of the 16x16x16 form.  (Plain BF16
+      // keeps 16x16x16: its matrix cores are mostly idle, and pairing there
+      // only adds register pressure.)
+      static_assert(KT % 2 == 0, "pairs of 16-row K steps");
 #pragma unroll
-    for (int ks = 0; ks < KT; ++ks) {
-      if constexpr (E::KPL == 1) {
-        const lds_t b = xw[l16 * ST + 4 * ks + g4];
+      for (int j = 0; j < KT / 2; ++j) {
+        const int ka = 2 * j, kb = 2 * j + 1;
+        {
+          const int oa = l16 * ST + 16 * ka + 4 * g4, ob = l16 * ST + 16 * kb + 4 * g4;
+          const b8 b0 = join8(*(const s4*)&xw[oa], *(const s4*)&xw[ob]);
+          const b8 b1 = join8(*(const s4*)&xw[KC * ST + oa], *(const s4*)&xw[KC * ST + ob]);
+          const b8 b2 = join8(*(const s4*)&xw[2 * KC * ST + oa], *(const s4*)&xw[2 * KC * ST + ob]);
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) {
-          if constexpr (PREC == P_F64)
-            tacc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
-          else
-            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
+          for (int mt = 0; mt < NT; ++mt) {
+            const b8 pA = join8(psiA[ka][mt], psiA[kb][mt]);
+            const b8 pM = join8(psiM[ka][mt], psiM[kb][mt]);
+            const b8 pL = join8(psiL[ka][mt], psiL[kb][mt]);
+            accv t = tacc[mt];
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pL, b0, t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pM, b1, t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pA, b2, t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pM, b0, t, 0, 0, 0);
+            t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pA, b1, t, 0, 0, 0);
+            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pA, b0, t, 0, 0, 0);
+          }
         }
-      } else if constexpr (X3) {
-        const int o = l16 * ST + 16 * ks + 4 * g4;
-        const s4 b0 = *(const s4*)&xw[o], b1 = *(const s4*)&xw[KC * ST + o], b2 = *(const s4*)&xw[2 * KC * ST + o];
+      }
+    } else {
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) {
-          accv t = tacc[mt];
-          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiL[ks][mt], b0, t, 0, 0, 0);
-          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiM[ks][mt], b1, t, 0, 0, 0);
-          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], b2, t, 0, 0, 0);
-          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiM[ks][mt], b0, t, 0, 0, 0);
-          t = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], b1, t, 0, 0, 0);
-          tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], b0, t, 0, 0, 0);
+      for (int ks = 0; ks < KT; ++ks) {
+        if constexpr (E::KPL == 1) {
+          const lds_t b = xw[l16 * ST + 4 * ks + g4];
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt) {
+            if constexpr (PREC == P_F64)
+              tacc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
+            else
+              tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
+          }
+        } else {
+          const u4 q = *(const u4*)&xw[l16 * ST + 16 * ks + 4 * g4];
+          s4 bh, bl;
+          unpack4(q.x, q.y, q.z, q.w, bh, bl);
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt)
+            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], bh, tacc[mt], 0, 0, 0);
         }
-      } else {
-        const u4 q = *(const u4*)&xw[l16 * ST + 16 * ks + 4 * g4];
-        s4 bh, bl;
-        unpack4(q.x, q.y, q.z, q.w, bh, bl);
-#pragma unroll
-        for (int mt = 0; mt < NT; ++mt)
-          tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], bh, tacc[mt], 0, 0, 0);
       }
     }
     __builtin_amdgcn_s_setprio(0);
