@@ -34,6 +34,7 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef short s8 __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
 
 // Two 4-element bf16 operands as one 8-element operand of the 16x16x32 bf16
 // matrix instruction.  Both operands of a product are joined the same way, so
@@ -137,6 +138,12 @@ __device__ __forceinline__ void split3_pk(float a, float b, uint32_t& t0, uint32
 // four bf16 of one plane at stride st (elements) as an MFMA operand
 __device__ __forceinline__ s4 gather4(const uint16_t* p, int st) {
   return s4{(short)p[0], (short)p[st], (short)p[2 * st], (short)p[3 * st]};
+}
+// eight of them (the 32-deep and 32x32x16 instruction operands)
+__device__ __forceinline__ b8 gather8(const uint16_t* p, int st) {
+  const s8 v = {(short)p[0],      (short)p[st],     (short)p[2 * st], (short)p[3 * st],
+                (short)p[4 * st], (short)p[5 * st], (short)p[6 * st], (short)p[7 * st]};
+  return __builtin_bit_cast(b8, v);
 }
 
 template <int PREC>
@@ -459,11 +466,21 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     }
   };
 
-  accv yacc[MT][NT];
+  // Split BF16 at sketch size 32: the right sketch runs on 32x32x16 bf16 tiles
+  // (32 rows x all 32 sketch columns x the chunk's 16 columns per
+  // instruction).  Accumulator element v of lane l sits at row
+  // 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32 of the tile.
+  constexpr bool W32 = X3 && LP == 32 && MT % 2 == 0;
+  accv yacc[W32 ? 1 : MT][NT];
+  f16v y32[W32 ? MT / 2 : 1];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+  for (int mt = 0; mt < (W32 ? 1 : MT); ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) yacc[mt][nt] = accv{0, 0, 0, 0};
+#pragma unroll
+  for (int h = 0; h < (W32 ? MT / 2 : 1); ++h)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) y32[h][v] = 0.0f;
 
   if (cb < ce) {
     load_omega(cb);
@@ -519,6 +536,23 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
               yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nt], yacc[mt][nt], 0, 0, 0);
           }
         }
+      }
+    } else if constexpr (W32) {
+      // six products t_i * t_j with i + j <= 2, smallest first; K index
+      // 8 (l / 32) + j of both operands is chunk column 8 (l / 32) + j
+      const int ob = 8 * (lane >> 5) * LP + (lane & 31);
+      const b8 w0 = gather8(om + ob, LP), w1 = gather8(om + KC * LP + ob, LP), w2 = gather8(om + 2 * KC * LP + ob, LP);
+#pragma unroll
+      for (int h = 0; h < MT / 2; ++h) {
+        const int o = 8 * (lane >> 5) * ST + 32 * h + (lane & 31);
+        const b8 a0 = gather8(xw + o, ST), a1 = gather8(xw + KC * ST + o, ST), a2 = gather8(xw + 2 * KC * ST + o, ST);
+        f16v y = y32[h];
+        y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, w0, y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, w1, y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, w2, y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, w0, y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, w1, y, 0, 0, 0);
+        y32[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, w0, y, 0, 0, 0);
       }
     } else if constexpr (X3) {
       // six products t_i * t_j with i + j <= 2, smallest first
@@ -640,16 +674,27 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
 
   // ---- right-sketch partial of this workgroup ----
   part* yp = (part*)A.ypart;
+  if constexpr (W32) {
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+    for (int h = 0; h < MT / 2; ++h)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = row0w + 16 * mt + acc_row<PREC>(g4, v);
-        const int c = 16 * nt + l16;
-        if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = (part)yacc[mt][nt][v];
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0w + 32 * h + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+        const int c = lane & 31;
+        if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = (part)y32[h][v];
       }
+  } else {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = row0w + 16 * mt + acc_row<PREC>(g4, v);
+          const int c = 16 * nt + l16;
+          if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = (part)yacc[mt][nt][v];
+        }
+  }
 }
 
 // ---------------------------------------------------------------------------
