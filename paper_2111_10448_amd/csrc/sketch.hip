@@ -706,15 +706,19 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
 // Output layouts: 16x16x4 element v of lane l at (4v + l/16, l%16); 4x4x4
 // block b = (l/4)%4 at (l/16, l%4) of that block.
 // ---------------------------------------------------------------------------
-// FP64 workgroups have 4 waves (256 rows) and two of them share a CU, so one
-// workgroup's matrix-core work overlaps the other's barrier and load phases.
-constexpr int NWF = 4;
-constexpr int F64_WG_PER_CU = 2;
+// FP64 workgroups: for ell (rounded to 4) <= 28, 4 waves (256 rows) and two
+// workgroups per CU, so one workgroup's matrix-core work overlaps the other's
+// barrier and load phases (measured 8% faster at ell = 20 than one 8-wave
+// workgroup).  For ell = 32 two such workgroups no longer fit in LDS, and one
+// 8-wave workgroup (two waves per SIMD) beats one 4-wave workgroup by 7%.
+constexpr int nwf_for(int L4) { return L4 > 28 ? 8 : 4; }
+constexpr int f64_wg_per_cu(int L4) { return L4 > 28 ? 1 : 2; }
 
 // FN: the tensor is the Hilbert tensor, evaluated from the index tables in
 // place of the loads of X (one launch segment, no memory behind it).
 template <int L4, bool ALIGNED, bool SEG1, bool FN>
-__global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const SketchArgs A) {
+__global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_f64(const SketchArgs A) {
+  constexpr int NWF = nwf_for(L4);
   constexpr int RW = 64;
   constexpr int ST = RW + 2;
   constexpr int NQ = L4 / 16;          // 16-wide tiles
@@ -944,7 +948,7 @@ __global__ __launch_bounds__(NWF * 64, F64_WG_PER_CU) void k_sketch_f64(const Sk
 
 template <int L4>
 static hipError_t launch_f64(const SketchArgs& a, bool aligned, hipStream_t s) {
-  dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(NWF * 64);
+  dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(nwf_for(L4) * 64);
   const bool seg1 = a.nseg == 1 && a.seg[0].chunk0 == 0;
   if (a.fn) {
     if (!seg1 || a.fn != 1 || !a.fn_rec || !a.fn_row || !a.fn_col) return hipErrorInvalidValue;
@@ -979,12 +983,12 @@ hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream
 }
 
 void sketch_geometry(int prec, int ell, int* rows_per_block, int* threads, int* wg_per_cu) {
-  *threads = prec == P_F64 ? NWF * 64 : NWS * 64;
-  // FP64: two workgroups fit in a CU's LDS while ell (rounded to 4) <= 28;
-  // the FP32-family kernels always fit two
-  *wg_per_cu = (prec != P_F64 || (ell + 3) / 4 * 4 <= 28) ? 2 : 1;
+  const int L4 = (ell + 3) / 4 * 4;
+  *threads = prec == P_F64 ? nwf_for(L4) * 64 : NWS * 64;
+  // FP64: see nwf_for; the FP32-family kernels always fit two workgroups
+  *wg_per_cu = prec == P_F64 ? f64_wg_per_cu(L4) : 2;
   switch (prec) {
-    case P_F64: *rows_per_block = NWF * Eng<P_F64>::RW; break;
+    case P_F64: *rows_per_block = nwf_for(L4) * Eng<P_F64>::RW; break;
     case P_F32: *rows_per_block = NWS * Eng<P_F32>::RW; break;
     case P_BF16: *rows_per_block = NWS * Eng<P_BF16>::RW; break;
     default: *rows_per_block = NWS * Eng<P_BF16X3>::RW; break;
