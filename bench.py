@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--prec", default=None)
+    ap.add_argument("--algo", default="pstt2", choices=["pstt2", "pstt"],
+                    help="two-sided PSTT2 (default) or the one-sided PSTT for the main line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the two-sided middle core, the precision study (1/sum tensor in FP64, FP32, "
@@ -306,7 +308,7 @@ def main():
     name = args.workload
     w = inputs.WORKLOADS[name]
     prec = args.prec or ("f64" if w.dtype == "f64" else "f32")
-    r = run_workload(name, prec, args.steps, args.warmup)
+    r = run_workload(name, prec, args.steps, args.warmup, algo=args.algo)
     w = r["workload"]
     value = r["bytes"] / (r["ms_per_step"] * 1e-3) / 1e9
     kb = r["bytes"] / r["launches_per_step"] if r["launches_per_step"] else r["bytes"]

@@ -178,6 +178,18 @@ __device__ __forceinline__ double psi_row(const SketchArgs& A, int64_t row, int 
   if (row >= A.R || a >= A.ell) return 0.0;
   if (A.psi_tab) return A.psi_tab[row * A.L4 + a];
   double v = 1.0;
+  if (A.R <= 0xffffffffLL) {
+    // 32-bit index arithmetic (a few instructions per division instead of the
+    // 64-bit sequence): the workgroup prologue forms 32 of these rows per lane
+    uint32_t r = (uint32_t)row;
+    for (int q = 1; q <= A.m; ++q) {
+      const uint32_t nq = (uint32_t)A.n[q - 1];
+      const uint32_t iq = r % nq;
+      r /= nq;
+      v *= A.fac[A.psi_off[q - 1] + (int64_t)iq * A.ell + a];
+    }
+    return v;
+  }
   int64_t r = row;
   for (int q = 1; q <= A.m; ++q) {
     int64_t nq = A.n[q - 1];
