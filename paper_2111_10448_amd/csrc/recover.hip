@@ -938,13 +938,23 @@ __global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, d
     double sv = 0.0, fv = 0.0;
     if (row < K) {
       sv = u < sc ? S[(int64_t)u * K + row] : 0.0;
-      int64_t rest = row;
       fv = 1.0;
-      for (int j = 0; j < cnt; ++j) {
-        const int64_t nq = nmode[q0 + j];
-        const int64_t i = rest % nq;
-        rest /= nq;
-        fv *= B.fac[off[j] + i * ell + u];
+      if (K <= 0xffffffffLL) {   // 32-bit index arithmetic (far fewer instructions per division)
+        uint32_t rest = (uint32_t)row;
+        for (int j = 0; j < cnt; ++j) {
+          const uint32_t nq = (uint32_t)nmode[q0 + j];
+          const uint32_t i = rest % nq;
+          rest /= nq;
+          fv *= B.fac[off[j] + (int64_t)i * ell + u];
+        }
+      } else {
+        int64_t rest = row;
+        for (int j = 0; j < cnt; ++j) {
+          const int64_t nq = nmode[q0 + j];
+          const int64_t i = rest % nq;
+          rest /= nq;
+          fv *= B.fac[off[j] + i * ell + u];
+        }
       }
     }
     Ss[r][u] = sv;

@@ -49,6 +49,45 @@ __global__ void k_reduce_t(const P* __restrict__ tp, const SketchArgs A, double*
   }
 }
 
+// Few T entries and many row blocks (a very tall X_m with few columns, as in
+// the one-sided algorithm's pass at split d-1): one thread per entry would add
+// ~1e5 partials serially.  Then the row blocks are cut into nsplit contiguous
+// groups, each group summed in increasing g into its own partial, and the
+// group partials added in increasing group order (deterministic, as the split
+// depends only on the shapes).
+template <typename P>
+__global__ void k_reduce_t_split(const P* __restrict__ tp, const SketchArgs A, int seg, int nsplit,
+                                 double* __restrict__ out) {
+  const int64_t gc0 = A.seg[seg].gcol0, ncols = A.seg[seg].ncols;
+  const int ell = A.ell, gi = A.gi_count;
+  const int64_t C = A.C, st = (int64_t)ell * C;
+  const int64_t tot = ncols * ell;
+  const int sp = blockIdx.y;
+  const int g0 = (int)((int64_t)sp * gi / nsplit), g1 = (int)((int64_t)(sp + 1) * gi / nsplit);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(i / ncols);
+    const int64_t col = gc0 + i % ncols;
+    const P* p = tp + (int64_t)a * C + col;
+    double sum = 0.0;
+    for (int g = g0; g < g1; ++g) sum += (double)p[(int64_t)g * st];
+    out[(int64_t)sp * tot + i] = sum;
+  }
+}
+
+__global__ void k_reduce_t_join(const double* __restrict__ part, const SketchArgs A, int seg, int nsplit,
+                                double* __restrict__ Tt, int* flag) {
+  const int64_t gc0 = A.seg[seg].gcol0, ncols = A.seg[seg].ncols;
+  const int64_t C = A.C, tot = ncols * A.ell;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(i / ncols);
+    const int64_t col = gc0 + i % ncols;
+    double sum = Tt[(int64_t)a * C + col];
+    for (int sp = 0; sp < nsplit; ++sp) sum += part[(int64_t)sp * tot + i];
+    Tt[(int64_t)a * C + col] = sum;
+    if (!isfinite(sum)) atomicOr(flag, 1);
+  }
+}
+
 hipError_t launch_reduce(int prec, const SketchArgs& a, double* Y, double* Tt, int* flag, hipStream_t s) {
   const int bs = 256;
   const int64_t ny = a.R * a.ell;
@@ -59,9 +98,29 @@ hipError_t launch_reduce(int prec, const SketchArgs& a, double* Y, double* Tt, i
   else
     hipLaunchKernelGGL(k_reduce_y<float>, dim3(gy), dim3(bs), 0, s, (const float*)a.ypart, a.gj_count, a.R,
                        a.ell, Y, flag);
-  if (a.nseg > 0) {
-    int64_t nt = 0;
-    for (int i = 0; i < a.nseg; ++i) nt = std::max<int64_t>(nt, a.seg[i].ncols * a.ell);
+  int64_t nt = 0;
+  for (int i = 0; i < a.nseg; ++i) nt = std::max<int64_t>(nt, a.seg[i].ncols * a.ell);
+  if (a.nseg > 0 && nt < 16384 && a.gi_count >= 4096) {
+    // two-level sum (see k_reduce_t_split), one segment at a time
+    const int nsplit = (int)std::min<int64_t>(a.gi_count / 256, std::max<int64_t>(1, 65536 / std::max<int64_t>(nt, 1)));
+    double* part = nullptr;
+    hipError_t e = ws_alloc((void**)&part, sizeof(double) * nsplit * nt, s);
+    if (e != hipSuccess) return e;
+    for (int sg = 0; sg < a.nseg && e == hipSuccess; ++sg) {
+      const int64_t tot = a.seg[sg].ncols * a.ell;
+      const unsigned gx = (unsigned)std::max<int64_t>(1, (tot + bs - 1) / bs);
+      if (prec == PSTT2_P_F64)
+        hipLaunchKernelGGL(k_reduce_t_split<double>, dim3(gx, (unsigned)nsplit), dim3(bs), 0, s,
+                           (const double*)a.tpart, a, sg, nsplit, part);
+      else
+        hipLaunchKernelGGL(k_reduce_t_split<float>, dim3(gx, (unsigned)nsplit), dim3(bs), 0, s,
+                           (const float*)a.tpart, a, sg, nsplit, part);
+      hipLaunchKernelGGL(k_reduce_t_join, dim3(gx), dim3(bs), 0, s, part, a, sg, nsplit, Tt, flag);
+      e = hipGetLastError();
+    }
+    ws_free(part, s);
+    if (e != hipSuccess) return e;
+  } else if (a.nseg > 0) {
     const unsigned gt = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nt + bs - 1) / bs, 4096));
     if (prec == PSTT2_P_F64)
       hipLaunchKernelGGL(k_reduce_t<double>, dim3(gt, (unsigned)a.nseg), dim3(bs), 0, s, (const double*)a.tpart, a,
