@@ -193,8 +193,10 @@ def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass", drm=
 
 
 def run_function(name, steps, warmup):
-    """Table 1's Hilbert tensors, evaluated inside the kernels (never stored): reset,
-    sketch, recover and the error pass against the same formula."""
+    """Tensors given by a formula, never stored: Table 1's Hilbert tensors (evaluated
+    inside the sketch and error kernels) or the Gaussian bumps of Section 4.4
+    (evaluated into workspace chunks of columns that the memory kernels stream).
+    Reset, sketch, recover and the error pass against the same formula."""
     import torch
     import inputs
     import paper_2111_10448_amd as P
@@ -202,9 +204,10 @@ def run_function(name, steps, warmup):
     w = inputs.WORKLOADS[name]
     psi, omega = inputs.drm_factors(w)
     fac = inputs.pack_factors(psi, omega, w.d)
+    fn = P.GaussBumps(inputs.gauss_centers(w), w.gamma) if w.kind == "gauss" else "hilbert"
     ctx = P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", ranks=w.ranks())
-    log(f"[bench] {name}: Hilbert tensor n={w.n[0]}^{w.d}, timing {steps} steps")
-    t_err = 0.0
+    log(f"[bench] {name}: {w.kind} tensor n={w.n[0]}^{w.d}, timing {steps} steps")
+    t_err = t_sk = 0.0
     for it in range(warmup + steps):
         if it == warmup:
             torch.cuda.synchronize()
@@ -212,10 +215,14 @@ def run_function(name, steps, warmup):
             ctx.profile_read()
             t0 = time.perf_counter()
         ctx.reset()
-        ctx.sketch_fn("hilbert")
+        a = time.perf_counter()
+        ctx.sketch_fn(fn)
+        torch.cuda.synchronize()
+        if it >= warmup:
+            t_sk += time.perf_counter() - a
         tt = ctx.recover()
         a = time.perf_counter()
-        err = tt.error_fn("hilbert")
+        err = tt.error_fn(fn)
         if it >= warmup:
             t_err += time.perf_counter() - a
         ranks = tt.ranks
@@ -227,13 +234,24 @@ def run_function(name, steps, warmup):
     ctx.close()
     kms /= max(launches, 1)
     flops = 4.0 * w.ell * w.numel
-    return {"workload": f"{name}: Hilbert tensor d={w.d} n={w.n[0]} ({w.numel} entries, "
-                        f"{8 * w.numel / 2**30:.2f} GiB in FP64, never stored), Table 1 ranks, sketch size {w.ell}",
-            "ranks": ranks, "tt_rel_error": err, "ms_per_step": round((t1 - t0) * 1e3 / steps, 4),
-            "sketch_kernel_ms": round(kms, 4), "error_pass_ms": round(t_err * 1e3 / steps, 4),
-            "sketch_entries_per_s": round(w.numel / (kms * 1e-3), 1),
-            "sketch_fp64_tflops": round(flops / (kms * 1e-3) / 1e12, 2),
-            "sketch_fp64_frac": round(flops / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+    size = f"{w.numel} entries, {8 * w.numel / 2**30:.2f} GiB in FP64, never stored"
+    if w.kind == "gauss":
+        desc = (f"{name}: Gaussian-bump tensor ({w.terms} bumps, width parameter {w.gamma:g}) d={w.d} n={w.n[0]} "
+                f"({size}), ranks {w.ranks()}, sketch size {w.ell}")
+    else:
+        desc = f"{name}: Hilbert tensor d={w.d} n={w.n[0]} ({size}), Table 1 ranks, sketch size {w.ell}"
+    out = {"workload": desc, "ranks": ranks, "tt_rel_error": err,
+           "ms_per_step": round((t1 - t0) * 1e3 / steps, 4), "sketch_fn_ms": round(t_sk * 1e3 / steps, 4),
+           "sketch_kernel_ms": round(kms, 4), "error_pass_ms": round(t_err * 1e3 / steps, 4)}
+    if w.kind == "gauss":
+        # evaluation at 2 x terms FP64 flops per entry, then the memory sketch of the chunks
+        ev = 2.0 * w.terms * w.numel
+        out["evaluation_fp64_tflops_in_sketch_fn"] = round(ev / (t_sk / steps) / 1e12, 2)
+    else:
+        out.update({"sketch_entries_per_s": round(w.numel / (kms * 1e-3), 1),
+                    "sketch_fp64_tflops": round(flops / (kms * 1e-3) / 1e12, 2),
+                    "sketch_fp64_frac": round(flops / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)})
+    return out
 
 
 def run_adjoint(steps, warmup):
@@ -375,6 +393,10 @@ def main():
             except Exception as e:
                 t1[wn] = {"error": str(e)}
         record["table1_hilbert"] = t1
+        try:
+            record["gauss_bumps"] = run_function("gb_d3", max(3, args.steps // 2), 1)
+        except Exception as e:
+            record["gauss_bumps"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         record["cpu_baseline"] = cpu_baseline(r["x"], w, r["psi"], r["omega"])
     print(json.dumps(record), flush=True)

@@ -160,25 +160,44 @@ pstt2_status pstt2_sketch_slabs(pstt2_ctx* ctx, int32_t nslabs, const void* cons
 
 /* Tensors given by a formula of their indices: the streaming setting of
  * Section 4.2, where each sub-tensor comes from a function of its indices and
- * the whole tensor is never stored.  The kernels evaluate the entries in place
- * of loading them.
+ * the whole tensor is never stored.
  *   HILBERT  X(i_1, ..., i_d) = 1 / (1 - d + i_1 + ... + i_d), 1 <= i_q <= n_q
  *            (the Hilbert tensor of Section 4.3 and Table 1), evaluated in
- *            FP64: the reciprocal of the integer index sum, correctly rounded. */
-typedef enum { PSTT2_FN_HILBERT = 0 } pstt2_fn_kind;
+ *            FP64 inside the sketch and error kernels: the reciprocal of the
+ *            integer index sum, correctly rounded.  Other fields unused.
+ *   GAUSS    X(i_1, ..., i_d) = sum_{j < n_terms} exp(-gamma sum_q (x_q - c_{j,q})^2),
+ *            x_q = 2 i_q / n_q - 1 with 1 <= i_q <= n_q (the Gaussian-bump
+ *            tensor of Section 4.4, for any d).  centers is host memory,
+ *            n_terms x d row-major (c_{j,q} at centers[j * d + q]), read during
+ *            the call only; 1 <= n_terms <= PSTT2_GAUSS_MAX_TERMS, gamma > 0.
+ *            Each bump is a product of one factor per mode, so the library
+ *            tabulates those factors (FP64 exp) and evaluates chunks of whole
+ *            columns of X_m into a workspace of at most PSTT2_GAUSS_CHUNK_BYTES
+ *            (one column if that is larger), which the memory kernels then
+ *            stream: the tensor is never stored whole.  The bumps are added in
+ *            increasing j. */
+typedef enum { PSTT2_FN_HILBERT = 0, PSTT2_FN_GAUSS = 1 } pstt2_fn_kind;
+#define PSTT2_GAUSS_MAX_TERMS 1024
+#define PSTT2_GAUSS_CHUNK_BYTES (1LL << 30)
 typedef struct {
   pstt2_fn_kind kind;
+  int32_t n_terms;         /* GAUSS: number of bumps */
+  double gamma;            /* GAUSS: width parameter */
+  const double* centers;   /* GAUSS: host, n_terms x d, row-major */
 } pstt2_fn;
 
 /* Stream the entries [first, first + count) of the tensor fn (flat
  * column-major, the context's mode sizes) into the sketches, as pstt2_sketch
- * does for a slab in memory.  Needs a context with dtype F64 and prec F64.
+ * does for a slab in memory.  HILBERT needs a context with dtype F64 and prec
+ * F64; GAUSS takes any context (its entries are evaluated in FP64 and rounded
+ * to the context's dtype, as a stored tensor of that dtype would be).
  * first and count must be multiples of R_m = n_1...n_m (whole columns of the
  * middle unfolding X_m); the same coverage rules as pstt2_sketch apply, and
- * slabs from memory and from fn may be mixed.  The library builds small index
+ * slabs from memory and from fn may be mixed.  HILBERT builds small index
  * tables (R_m + C_m int32 and sum_q n_q doubles) on first use and keeps them
- * with the context.  async.  Errors: EINVAL (kind, dtype / prec, alignment,
- * range), ESTATE (overlap, after recover), EDEVICE. */
+ * with the context; GAUSS builds its tables on every call.  async (GAUSS
+ * copies the centers before it returns).  Errors: EINVAL (kind, fields,
+ * dtype / prec, alignment, range), ESTATE (overlap, after recover), ENOMEM, EDEVICE. */
 pstt2_status pstt2_sketch_fn(pstt2_ctx* ctx, const pstt2_fn* fn, int64_t first, int64_t count);
 
 /* Recover the TT cores from the accumulated sketches: derive every split's
@@ -278,9 +297,9 @@ void pstt2_destroy(pstt2_ctx* ctx);
 pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* rel_err,
                       void* hip_stream);
 
-/* The same for the tensor fn (see pstt2_fn), evaluated in FP64 inside the
- * pass instead of read from memory; the mode sizes are the cores'.  sync.
- * Errors: EINVAL, ENUMERIC, EDEVICE. */
+/* The same for the tensor fn (see pstt2_fn), evaluated in FP64 instead of read
+ * from memory; the mode sizes are the cores'.  sync.
+ * Errors: EINVAL, ENUMERIC, ENOMEM, EDEVICE. */
 pstt2_status tt_error_fn(const tt_cores* cores, const pstt2_fn* fn, double* rel_err, void* hip_stream);
 
 /* Write entries [first, first + count) of X~ (flat column-major, entry formula

@@ -44,6 +44,8 @@ class Workload:
     rmax: int = 0              # rank cap in tolerance mode
     nslabs: int = 1            # number of contiguous slabs the tensor is delivered in
     rank_list: tuple = ()      # per-split target ranks r_1..r_{d-1} (overrides rank)
+    terms: int = 0             # number of Gaussian bumps (kind == "gauss")
+    gamma: float = 0.0         # their width parameter (kind == "gauss")
 
     @property
     def d(self) -> int:
@@ -109,6 +111,17 @@ WORKLOADS = {
     "t1_small3": Workload("t1_small3", 24, (61, 47, 53), "f64", "hilbert", ell=16, rank_list=(8, 8)),
     "t1_small5": Workload("t1_small5", 25, (13, 11, 12, 9, 10), "f64", "hilbert", ell=14,
                           rank_list=(6, 7, 7, 6)),
+    # Section 4.4: a sum of 100 Gaussian bumps (width parameter 10, centers uniform on
+    # [-1, 1]^d) on the order-3 shape of Table 1 (n = 960, 6.59 GB in FP64, never
+    # stored).  The paper prints no ranks for it; the unfoldings' singular values
+    # fall below 1e-10 of the norm past about 22, so ranks 24 and sketch size 32.
+    "gb_d3": Workload("gb_d3", 26, (960,) * 3, "f64", "gauss", ell=32, rank_list=(24, 24), terms=100,
+                      gamma=10.0),
+    # scaled-down twins (ragged modes) that the oracle finishes in seconds
+    "gb_small3": Workload("gb_small3", 27, (45, 38, 41), "f64", "gauss", ell=16, rank_list=(10, 10), terms=100,
+                          gamma=10.0),
+    "gb_small4": Workload("gb_small4", 28, (13, 11, 12, 9), "f64", "gauss", ell=14, rank_list=(7, 9, 7),
+                          terms=100, gamma=10.0),
 }
 
 
@@ -205,6 +218,47 @@ def hilbert_entries(n: Sequence[int], m: int, rows, cols) -> np.ndarray:
     return 1.0 / (sr[:, None] + sc[None, :] - d + 1).astype(np.float64)
 
 
+def gauss_centers(w: Workload) -> np.ndarray:
+    """Centers of the Gaussian-bump tensor (Section 4.4): terms x d, iid uniform on [-1, 1],
+    drawn from the workload's first stream."""
+    rc, _, _, _ = seed_streams(w.index)
+    return rc.uniform(-1.0, 1.0, size=(w.terms, w.d))
+
+
+def gauss_grid(nq: int) -> np.ndarray:
+    """Grid points x = 2 i / n - 1 of one mode, i = 1..n (Section 4.4; 1-based i)."""
+    return 2.0 * np.arange(1, nq + 1, dtype=np.float64) / nq - 1.0
+
+
+def gauss_tensor(n: Sequence[int], centers: np.ndarray, gamma: float) -> np.ndarray:
+    """X(i) = sum_j exp(-gamma * sum_q (x_q - c_{j,q})^2), flat column-major, FP64.
+    The bumps are added in increasing j; each exponent sums its modes in increasing q."""
+    d = len(n)
+    out = np.zeros(int(np.prod(n)), dtype=np.float64)
+    for c in centers:
+        e = np.zeros(1)
+        for q in range(d):
+            e = (e[:, None] + ((gauss_grid(n[q]) - c[q]) ** 2)[None, :]).reshape(-1, order="F")
+        out += np.exp(-gamma * e)
+    return out
+
+
+def gauss_entries(n: Sequence[int], m: int, rows, cols, centers: np.ndarray, gamma: float) -> np.ndarray:
+    """Entries X_m(rows[i], cols[j]) of the Gaussian-bump tensor's m-th unfolding, from the
+    formula, as an FP64 len(rows) x len(cols) array."""
+    def sq_dist(f, modes, cq):
+        f = np.asarray(f, dtype=np.int64).copy()
+        s = np.zeros(f.shape, dtype=np.float64)
+        for nq, c in zip(modes, cq):
+            s += (2.0 * (f % nq + 1) / nq - 1.0 - c) ** 2
+            f //= nq
+        return s
+    out = np.zeros((len(rows), len(cols)), dtype=np.float64)
+    for c in centers:
+        out += np.exp(-gamma * (sq_dist(rows, n[:m], c[:m])[:, None] + sq_dist(cols, n[m:], c[m:])[None, :]))
+    return out
+
+
 def add_noise(x: np.ndarray, rng: np.random.Generator, sigma: float, chunk: int = 1 << 24) -> None:
     """In place: x += sigma * N(0,1), drawn in fixed-size chunks (deterministic for a seed)."""
     if sigma == 0.0:
@@ -228,6 +282,8 @@ def make_tensor(w: Workload) -> np.ndarray:
         x = inverse_sum_tensor(w.n)
     elif w.kind == "hilbert":
         x = hilbert_tensor(w.n)
+    elif w.kind == "gauss":
+        x = gauss_tensor(w.n, gauss_centers(w), w.gamma)
     else:
         raise ValueError(f"unknown tensor kind {w.kind!r}")
     if w.dtype == "f32":

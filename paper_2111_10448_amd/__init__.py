@@ -21,7 +21,7 @@ import numpy as np
 from . import _lib as L
 from ._lib import PSTT2Error  # noqa: F401
 
-__all__ = ["PSTT2", "TT", "PSTT2Error", "decompose", "tt_error", "tt_error_fn", "tt_reconstruct", "version", "cores_struct",
+__all__ = ["PSTT2", "TT", "PSTT2Error", "GaussBumps", "decompose", "tt_error", "tt_error_fn", "tt_reconstruct", "version", "cores_struct",
            "PSTT2Reconstruct", "pstt2_reconstruct"]
 
 
@@ -106,7 +106,7 @@ class TT:
     def error(self, x) -> float:
         return tt_error(self, x, stream=self._stream)
 
-    def error_fn(self, fn: str = "hilbert") -> float:
+    def error_fn(self, fn="hilbert") -> float:
         """Relative error against a tensor given by a formula (see PSTT2.sketch_fn)."""
         return tt_error_fn(self, fn, stream=self._stream)
 
@@ -200,15 +200,14 @@ class PSTT2:
         L.check(L.lib().pstt2_sketch(self._c(), ctypes.c_void_p(x.data_ptr()), int(first), int(x.numel())),
                 self._ctx)
 
-    def sketch_fn(self, fn: str = "hilbert", first: int = 0, count: Optional[int] = None) -> None:
+    def sketch_fn(self, fn="hilbert", first: int = 0, count: Optional[int] = None) -> None:
         """Stream entries [first, first + count) of a tensor given by a formula of its
-        indices, evaluated inside the kernel ("hilbert": 1 / (1 - d + i_1 + ... + i_d)).
-        first and count are multiples of n_1...n_m; count defaults to the rest (async)."""
-        if fn not in L.FN:
-            raise ValueError(f"unknown tensor function {fn!r}")
+        indices: "hilbert" (1 / (1 - d + i_1 + ... + i_d), evaluated inside the kernel)
+        or a GaussBumps.  first and count are multiples of n_1...n_m; count defaults to
+        the rest (async)."""
+        f = _fn_struct(fn, len(self.n))
         if count is None:
             count = int(np.prod(self.n)) - int(first)
-        f = L.Fn(L.FN[fn])
         L.check(L.lib().pstt2_sketch_fn(self._c(), ctypes.byref(f), int(first), int(count)), self._ctx)
 
     def sketch_slabs(self, xs: Sequence, firsts: Sequence[int]) -> None:
@@ -241,9 +240,8 @@ class PSTT2:
             _check_dev(x)
         fp = None
         if fn is not None:
-            if fn not in L.FN:
-                raise ValueError(f"unknown tensor function {fn!r}")
-            fp = ctypes.byref(L.Fn(L.FN[fn]))
+            fs = _fn_struct(fn, len(self.n))
+            fp = ctypes.byref(fs)
         cs = L.TTCores()
         err = ctypes.c_double()
         L.check(L.lib().pstt2_recover_certified(self._c(), ctypes.c_void_p(x.data_ptr() if x is not None else 0), fp,
@@ -338,13 +336,34 @@ def tt_error(tt, x, stream=None) -> float:
     return out.value
 
 
-def tt_error_fn(tt, fn: str = "hilbert", stream=None) -> float:
-    """||X - X~||_F / ||X||_F for a tensor given by a formula, evaluated inside the pass."""
-    if fn not in L.FN:
+class GaussBumps:
+    """The Gaussian-bump tensor X(i) = sum_j exp(-gamma sum_q (x_q - c_{j,q})^2),
+    x_q = 2 i_q / n_q - 1 with 1-based i_q (Section 4.4).  centers: n_terms x d."""
+
+    def __init__(self, centers, gamma: float):
+        self.centers = np.ascontiguousarray(np.asarray(centers, dtype=np.float64))
+        if self.centers.ndim != 2 or not 1 <= self.centers.shape[0] <= L.GAUSS_MAX_TERMS:
+            raise ValueError("centers must be n_terms x d with 1 <= n_terms <= %d" % L.GAUSS_MAX_TERMS)
+        self.gamma = float(gamma)
+
+
+def _fn_struct(fn, d: int) -> "L.Fn":
+    """The C description of a tensor function of order d: "hilbert" or a GaussBumps
+    (whose centers array the struct points into; the library copies it during the call)."""
+    if isinstance(fn, GaussBumps):
+        if fn.centers.shape[1] != d:
+            raise ValueError(f"centers have {fn.centers.shape[1]} coordinates, the tensor has order {d}")
+        return L.Fn(L.FN["gauss"], fn.centers.shape[0], fn.gamma, fn.centers.ctypes.data)
+    if fn != "hilbert":
         raise ValueError(f"unknown tensor function {fn!r}")
+    return L.Fn(L.FN["hilbert"])
+
+
+def tt_error_fn(tt, fn="hilbert", stream=None) -> float:
+    """||X - X~||_F / ||X||_F for a tensor given by a formula ("hilbert" or a GaussBumps)."""
     cs = tt.struct() if isinstance(tt, TT) else tt
+    f = _fn_struct(fn, cs.d)
     out = ctypes.c_double()
-    f = L.Fn(L.FN[fn])
     L.check(L.lib().tt_error_fn(ctypes.byref(cs), ctypes.byref(f), ctypes.byref(out),
                                 ctypes.c_void_p(_stream_handle(stream))))
     return out.value

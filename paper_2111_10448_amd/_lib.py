@@ -21,7 +21,8 @@ F64, F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 MID = {"onepass": 0, "twopass": 1, "twosided": 2}
 DRM = {"nested": 0, "independent": 1}
-FN = {"hilbert": 0}
+FN = {"hilbert": 0, "gauss": 1}
+GAUSS_MAX_TERMS = 1024
 ALGO = {"pstt2": 0, "pstt": 1}
 
 
@@ -54,7 +55,8 @@ class TTCores(ctypes.Structure):
 
 
 class Fn(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int)]
+    _fields_ = [("kind", ctypes.c_int), ("n_terms", ctypes.c_int32), ("gamma", ctypes.c_double),
+                ("centers", ctypes.c_void_p)]
 
 
 class PSTT2Error(RuntimeError):

@@ -17,6 +17,8 @@ void pstt2_set_tls_error(const std::string& msg) { g_tls_err = msg; }
 
 namespace pstt2 {
 hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s, int fn);
+hipError_t tt_error_run_gauss(const tt_cores* c, const double* centers_host, int nterms, double gamma,
+                              double* e2x2, hipStream_t s);
 hipError_t tt_reconstruct_run(const tt_cores* c, void* out, int dtype, int64_t first, int64_t count, hipStream_t s);
 }
 
@@ -615,18 +617,59 @@ pstt2_status pstt2_sketch(pstt2_ctx* c, const void* x_dev, int64_t first, int64_
   return PSTT2_OK;
 }
 
+// fields of a tensor function (kind, and for GAUSS the bump parameters)
+static const char* fn_invalid(const pstt2_fn* fn) {
+  if (fn->kind == PSTT2_FN_HILBERT) return nullptr;
+  if (fn->kind != PSTT2_FN_GAUSS) return "unknown tensor function";
+  if (fn->n_terms < 1 || fn->n_terms > PSTT2_GAUSS_MAX_TERMS) return "n_terms must be in [1, PSTT2_GAUSS_MAX_TERMS]";
+  if (!(fn->gamma > 0.0) || !std::isfinite(fn->gamma)) return "gamma must be positive and finite";
+  if (!fn->centers) return "null centers";
+  return nullptr;
+}
+
+// Gaussian bumps: chunks of whole columns of X_m evaluated into a workspace in
+// the context's dtype, each streamed by the memory path like a slab.
+static pstt2_status sketch_gauss(pstt2_ctx* c, const pstt2_fn* fn, int64_t first, int64_t count) {
+  hipStream_t s = c->stream;
+  double* tabs = nullptr;
+  hipError_t e = ws_alloc((void**)&tabs, sizeof(double) * gauss_table_doubles(c->n, c->d, c->m, fn->n_terms), s);
+  if (e != hipSuccess) return hfail(c, e, "Gaussian-bump tables");
+  GaussTabs g;
+  e = gauss_tables(c->n, c->d, c->m, fn->centers, fn->n_terms, fn->gamma, tabs, &g, s);
+  const int esz = c->dtype == PSTT2_F64 ? 8 : 4;
+  const int64_t ncmax = gauss_chunk_cols(g, esz);
+  void* W = nullptr;
+  if (e == hipSuccess) e = ws_alloc(&W, (size_t)esz * c->R * std::min(ncmax, count / c->R), s);
+  pstt2_status st = PSTT2_OK;
+  if (e != hipSuccess) st = hfail(c, e, "Gaussian-bump workspace");
+  for (int64_t c0 = first / c->R; st == PSTT2_OK && c0 < (first + count) / c->R; c0 += ncmax) {
+    const int64_t nc = std::min(ncmax, (first + count) / c->R - c0);
+    e = gauss_columns(g, c0, nc, c->dtype, W, s);
+    if (e != hipSuccess) st = hfail(c, e, "Gaussian-bump columns");
+    else st = run_slabs(c, {Piece{W, c0 * c->R, nc * c->R}});
+  }
+  if (W) ws_free(W, s);
+  ws_free(tabs, s);
+  return st;
+}
+
 pstt2_status pstt2_sketch_fn(pstt2_ctx* c, const pstt2_fn* fn, int64_t first, int64_t count) {
   if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
   if (!fn) return fail(c, PSTT2_EINVAL, "null function");
-  if (fn->kind != PSTT2_FN_HILBERT) return fail(c, PSTT2_EINVAL, "unknown tensor function");
-  if (c->dtype != PSTT2_F64 || c->prec != PSTT2_P_F64)
-    return fail(c, PSTT2_EINVAL, "tensor functions need an FP64 context with FP64 sketches");
+  if (const char* why = fn_invalid(fn)) return fail(c, PSTT2_EINVAL, why);
+  if (fn->kind == PSTT2_FN_HILBERT && (c->dtype != PSTT2_F64 || c->prec != PSTT2_P_F64))
+    return fail(c, PSTT2_EINVAL, "the Hilbert function needs an FP64 context with FP64 sketches");
   if (c->recovered) return fail(c, PSTT2_ESTATE, "sketch after recover: call pstt2_reset first");
   if (first % c->R != 0 || count % c->R != 0)
     return fail(c, PSTT2_EINVAL, "first/count must be multiples of n_1...n_m (whole columns of X_m)");
   pstt2_status st = check_range(c, first, count);
   if (st != PSTT2_OK) return st;
   if (count == 0) return PSTT2_OK;
+  if (fn->kind == PSTT2_FN_GAUSS) {
+    st = sketch_gauss(c, fn, first, count);
+    if (st == PSTT2_OK) add_cover(c, first, count);
+    return st;
+  }
   hipError_t e = hipSuccess;
   if (!c->fn_rec) {
     double* rec = nullptr;
@@ -969,7 +1012,7 @@ pstt2_status pstt2_recover_certified(pstt2_ctx* c, const void* x_dev, const pstt
                                      tt_cores* out, double* rel_err) {
   if (!c || !out || !rel_err) return fail(c, PSTT2_EINVAL, "null argument");
   if ((x_dev == nullptr) == (fn == nullptr)) return fail(c, PSTT2_EINVAL, "give exactly one of x_dev and fn");
-  if (fn && fn->kind != PSTT2_FN_HILBERT) return fail(c, PSTT2_EINVAL, "unknown tensor function");
+  if (fn && fn_invalid(fn)) return fail(c, PSTT2_EINVAL, fn_invalid(fn));
   if (c->desc.ranks[0] > 0) return fail(c, PSTT2_ESTATE, "certified recovery needs a tolerance-mode context");
   if (c->desc.mid == PSTT2_MID_TWOPASS) return fail(c, PSTT2_ESTATE, "certified recovery covers the one-pass cores");
   if (max_tries < 1) return fail(c, PSTT2_EINVAL, "max_tries must be >= 1");
@@ -1371,7 +1414,7 @@ static pstt2_status check_cores(const tt_cores* t) {
   return PSTT2_OK;
 }
 
-static pstt2_status error_common(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, int fn,
+static pstt2_status error_common(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, const pstt2_fn* fn,
                                  double* rel_err, void* hip_stream) {
   double e2x2[2] = {0, 0};
   double* pin = pinned_scratch();
@@ -1381,7 +1424,9 @@ static pstt2_status error_common(const tt_cores* cores, const void* x_dev, pstt2
   hipError_t e = ar ? arena_begin(ar, (hipStream_t)hip_stream) : hipSuccess;
   if (e != hipSuccess) return hfail(nullptr, e, "tt_error");
   ArenaScope scope(ar);
-  e = tt_error_run(cores, x_dev, dtype, pin ? pin : e2x2, (hipStream_t)hip_stream, fn);
+  if (fn && fn->kind == PSTT2_FN_GAUSS)
+    e = tt_error_run_gauss(cores, fn->centers, fn->n_terms, fn->gamma, pin ? pin : e2x2, (hipStream_t)hip_stream);
+  else e = tt_error_run(cores, x_dev, dtype, pin ? pin : e2x2, (hipStream_t)hip_stream, fn ? 1 : 0);
   if (pin) {
     e2x2[0] = pin[0];
     e2x2[1] = pin[1];
@@ -1396,15 +1441,15 @@ pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtyp
   pstt2_status st = check_cores(cores);
   if (st != PSTT2_OK) return st;
   if (!x_dev || !rel_err) return fail(nullptr, PSTT2_EINVAL, "null argument");
-  return error_common(cores, x_dev, dtype, 0, rel_err, hip_stream);
+  return error_common(cores, x_dev, dtype, nullptr, rel_err, hip_stream);
 }
 
 pstt2_status tt_error_fn(const tt_cores* cores, const pstt2_fn* fn, double* rel_err, void* hip_stream) {
   pstt2_status st = check_cores(cores);
   if (st != PSTT2_OK) return st;
   if (!fn || !rel_err) return fail(nullptr, PSTT2_EINVAL, "null argument");
-  if (fn->kind != PSTT2_FN_HILBERT) return fail(nullptr, PSTT2_EINVAL, "unknown tensor function");
-  return error_common(cores, nullptr, PSTT2_F64, 1, rel_err, hip_stream);
+  if (const char* why = fn_invalid(fn)) return fail(nullptr, PSTT2_EINVAL, why);
+  return error_common(cores, nullptr, PSTT2_F64, fn, rel_err, hip_stream);
 }
 
 pstt2_status tt_reconstruct(const tt_cores* cores, void* x_out_dev, pstt2_dtype dtype, int64_t first, int64_t count,

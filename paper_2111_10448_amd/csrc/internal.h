@@ -82,6 +82,31 @@ inline int64_t hilbert_rec_len(const int64_t* n, int d) {
   return k;
 }
 
+// Gaussian-bump tensor X(i) = sum_j exp(-gamma sum_q (x_q - c_{j,q})^2) on the
+// split X_m: X(row, col) = sum_j e1(i_1, j) ahi(row / n_1, j) bc(col, j), the
+// per-mode factors multiplied out over modes 1, 2..m and m+1..d.  Tables are
+// j-major: e1[j * n1 + i_1], ahi[j * rhi + row / n_1], bc[j * bstride + col]
+// with bstride = C + kGaussCols and zero padding after column C - 1.
+constexpr int kGaussCols = 16;   // columns of X_m per thread in gauss_columns
+struct GaussTabs {
+  const double* e1;
+  const double* ahi;
+  const double* bc;
+  int32_t nterms;
+  int64_t n1, rhi, R, C, bstride;
+};
+// doubles of the buffer gauss_tables fills (centers, then the three tables)
+int64_t gauss_table_doubles(const int64_t* n, int d, int m, int nterms);
+// Copy the centers (host, nterms x d row-major) into buf and build the tables;
+// returns after stream s is idle.
+hipError_t gauss_tables(const int64_t* n, int d, int m, const double* centers_host, int nterms, double gamma,
+                        double* buf, GaussTabs* out, hipStream_t s);
+// Columns of X_m per workspace chunk: at most PSTT2_GAUSS_CHUNK_BYTES (one column
+// if larger), at most 65535 column blocks, at most C.
+int64_t gauss_chunk_cols(const GaussTabs& g, int elem_bytes);
+// Evaluate columns [c0, c0 + nc) of X_m into W (R x nc column-major, dtype F64 or F32).
+hipError_t gauss_columns(const GaussTabs& g, int64_t c0, int64_t nc, int dtype, void* W, hipStream_t s);
+
 // Launch the streaming dual-sketch kernel for the configured precision.
 hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s);
 // Entries after the T partials that the sketch kernels' idle lanes store to (never

@@ -320,6 +320,66 @@ hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x
   return e != hipSuccess ? e : e2;
 }
 
+// The Gaussian-bump tensor: chunks of whole columns of X_m are evaluated into a
+// workspace (gauss_columns) and run through the memory kernel against the
+// matching columns of Rt; every chunk's workgroup partials are kept and summed
+// in one fixed-order pass at the end.
+hipError_t tt_error_run_gauss(const tt_cores* c, const double* centers_host, int nterms, double gamma,
+                              double* e2x2, hipStream_t s) {
+  const int d = c->d;
+  const int split = (d + 1) / 2;
+  int64_t R = 1, C = 1;
+  for (int k = 0; k < split; ++k) R *= c->n[k];
+  for (int k = split; k < d; ++k) C *= c->n[k];
+  double* tabs = nullptr;
+  hipError_t e = ws_alloc((void**)&tabs, sizeof(double) * gauss_table_doubles(c->n, d, split, nterms), s);
+  if (e != hipSuccess) return e;
+  GaussTabs g;
+  e = gauss_tables(c->n, d, split, centers_host, nterms, gamma, tabs, &g, s);
+  double *L = nullptr, *Rt = nullptr, *ifb = nullptr;
+  if (e == hipSuccess) e = tt_interfaces(c, split, &L, &Rt, &ifb, s);
+  if (e != hipSuccess) {
+    ws_free(tabs, s);
+    return e;
+  }
+  const int r = c->r[split];
+  const int RK = rk_slot(r);
+  const int64_t ncmax = gauss_chunk_cols(g, sizeof(double));
+  const int64_t nchunk = (C + ncmax - 1) / ncmax;
+  const int gi = (int)((R + 511) / 512);
+  const int gjmax = (int)std::max<int64_t>(1, std::min<int64_t>(ncmax, (4096 + gi - 1) / gi));
+  double *part = nullptr, *Rp = nullptr, *W = nullptr;
+  e = ws_alloc((void**)&part, sizeof(double) * 2 * ((int64_t)gi * gjmax * nchunk + 1), s);
+  if (e == hipSuccess) e = ws_alloc((void**)&Rp, sizeof(double) * RK * C, s);
+  if (e == hipSuccess) e = ws_alloc((void**)&W, sizeof(double) * R * ncmax, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_pad_rt, dim3(grid_for(RK * C, 256)), dim3(256), 0, s, Rt, r, RK, C, Rp);
+    const bool pair = (R % 2) == 0;
+    const FnTabs none{nullptr, nullptr, nullptr};
+    int64_t np = 0;   // partial pairs written so far
+    for (int64_t c0 = 0; c0 < C && e == hipSuccess; c0 += ncmax) {
+      const int64_t nc = std::min(ncmax, C - c0);
+      const int gj = (int)std::max<int64_t>(1, std::min<int64_t>(nc, (4096 + gi - 1) / gi));
+      e = gauss_columns(g, c0, nc, PSTT2_F64, W, s);
+      if (e != hipSuccess) break;
+      e = pair ? launch_err_p<double, true, false>(W, R, nc, r, L, Rp + RK * c0, gi, gj, part + 2 * np, none, s)
+               : launch_err_p<double, false, false>(W, R, nc, r, L, Rp + RK * c0, gi, gj, part + 2 * np, none, s);
+      np += (int64_t)gi * gj;
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int)np, part + 2 * np);
+      e = hipMemcpyAsync(e2x2, part + 2 * np, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    }
+  }
+  if (part) ws_free(part, s);
+  if (Rp) ws_free(Rp, s);
+  if (W) ws_free(W, s);
+  ws_free(ifb, s);
+  ws_free(tabs, s);
+  hipError_t e2 = hipStreamSynchronize(s);
+  return e != hipSuccess ? e : e2;
+}
+
 template <typename T>
 __global__ void k_reconstruct(T* __restrict__ out, int64_t first, int64_t count, int64_t R, int r,
                               const double* __restrict__ L, const double* __restrict__ Rt) {

@@ -54,7 +54,26 @@ def test_struct_layouts_match_header():
     # d, pad, n[32], r[33], pad, core[32], owned, pad, stream
     assert ctypes.sizeof(L.TTCores) == 4 + 4 + 256 + 132 + 4 + 256 + 4 + 4 + 8
     assert L.TTCores.core.offset == 400 and L.TTCores.stream.offset == 664
-    assert ctypes.sizeof(L.Fn) == 4
+    assert ctypes.sizeof(L.Fn) == 24
+    assert L.Fn.n_terms.offset == 4 and L.Fn.gamma.offset == 8 and L.Fn.centers.offset == 16
+
+
+def test_fn_layout_matches_the_c_compiler(tmp_path):
+    """The same offsets as gcc lays out pstt2_fn from the header."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    from paper_2111_10448_amd import _lib as L
+    src = tmp_path / "fn.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pstt2.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu %d\\n", sizeof(pstt2_fn), offsetof(pstt2_fn, n_terms),'
+                   ' offsetof(pstt2_fn, gamma), offsetof(pstt2_fn, centers), PSTT2_GAUSS_MAX_TERMS); return 0; }\n')
+    exe = tmp_path / "fn"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [ctypes.sizeof(L.Fn), L.Fn.n_terms.offset, L.Fn.gamma.offset, L.Fn.centers.offset,
+                   L.GAUSS_MAX_TERMS]
 
 
 @pytest.mark.parametrize("field,value,msg", [
