@@ -178,7 +178,7 @@ pstt2_status pstt2_sketch_slabs(pstt2_ctx* ctx, int32_t nslabs, const void* cons
  *            increasing j. */
 typedef enum { PSTT2_FN_HILBERT = 0, PSTT2_FN_GAUSS = 1 } pstt2_fn_kind;
 #define PSTT2_GAUSS_MAX_TERMS 1024
-#define PSTT2_GAUSS_CHUNK_BYTES (1LL << 30)
+#define PSTT2_GAUSS_CHUNK_BYTES (1LL << 32)
 typedef struct {
   pstt2_fn_kind kind;
   int32_t n_terms;         /* GAUSS: number of bumps */

@@ -87,7 +87,7 @@ inline int64_t hilbert_rec_len(const int64_t* n, int d) {
 // per-mode factors multiplied out over modes 1, 2..m and m+1..d.  Tables are
 // j-major: e1[j * n1 + i_1], ahi[j * rhi + row / n_1], bc[j * bstride + col]
 // with bstride = C + kGaussCols and zero padding after column C - 1.
-constexpr int kGaussCols = 16;   // columns of X_m per thread in gauss_columns
+constexpr int kGaussCols = 64;   // columns of X_m per thread in gauss_columns
 struct GaussTabs {
   const double* e1;
   const double* ahi;
@@ -102,7 +102,7 @@ int64_t gauss_table_doubles(const int64_t* n, int d, int m, int nterms);
 hipError_t gauss_tables(const int64_t* n, int d, int m, const double* centers_host, int nterms, double gamma,
                         double* buf, GaussTabs* out, hipStream_t s);
 // Columns of X_m per workspace chunk: at most PSTT2_GAUSS_CHUNK_BYTES (one column
-// if larger), at most 65535 column blocks, at most C.
+// if larger; a multiple of kGaussCols when above it), at most 65535 column blocks, at most C.
 int64_t gauss_chunk_cols(const GaussTabs& g, int elem_bytes);
 // Evaluate columns [c0, c0 + nc) of X_m into W (R x nc column-major, dtype F64 or F32).
 hipError_t gauss_columns(const GaussTabs& g, int64_t c0, int64_t nc, int dtype, void* W, hipStream_t s);

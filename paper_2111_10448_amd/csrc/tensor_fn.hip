@@ -75,26 +75,41 @@ __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) p[t] = v;
 }
 
+constexpr int kGaussBlock = 256;   // threads per workgroup of k_gauss_cols
+
 // W(row, c) = sum_j a(row, j) b(c0 + c, j) for the columns [c0, c0 + nc) of X_m
 // (W is R_m x nc, column-major).  A thread owns one row and kGaussCols columns:
 // the row's a(row, j) is two lane-contiguous loads, the columns' b(col, j) are
-// the same for the whole wave (uniform loads), and each j costs kGaussCols FMAs.
-// The bumps are added in increasing j.
+// the same for the whole wave (uniform loads), and each j costs kGaussCols
+// FMAs.  The bumps are added in increasing j.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gauss_cols(const GaussTabs g, int64_t c0, int64_t nc, T* __restrict__ W) {
+__global__ __launch_bounds__(kGaussBlock) void k_gauss_cols(const GaussTabs g, int64_t c0, int64_t nc, T* __restrict__ W) {
   constexpr int CB = kGaussCols;
-  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t row = blockIdx.x * (int64_t)kGaussBlock + threadIdx.x;
   const int64_t cb = c0 + (int64_t)blockIdx.y * CB;
   const int ncb = (int)std::min<int64_t>(CB, c0 + nc - cb);
   if (row >= g.R) return;
-  const int64_t i1 = row % g.n1, hi = row / g.n1;
-  const double* __restrict__ e1 = g.e1 + i1;
-  const double* __restrict__ ah = g.ahi + hi;
+  const double* __restrict__ e1 = g.e1 + row % g.n1;
+  const double* __restrict__ ah = g.ahi + row / g.n1;
   const double* __restrict__ bc = g.bc + cb;   // columns past C read the table's zero padding
   double acc[CB];
 #pragma unroll
   for (int c = 0; c < CB; ++c) acc[c] = 0.0;
-  for (int j = 0; j < g.nterms; ++j) {
+  // two bumps per step: their four table loads are in flight together
+  constexpr int U = 2;
+  int j = 0;
+  for (; j + U <= g.nterms; j += U) {
+    double a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = e1[(int64_t)(j + u) * g.n1] * ah[(int64_t)(j + u) * g.rhi];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double* __restrict__ b = bc + (int64_t)(j + u) * g.bstride;
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[c] += a[u] * b[c];
+    }
+  }
+  for (; j < g.nterms; ++j) {
     const double a = e1[(int64_t)j * g.n1] * ah[(int64_t)j * g.rhi];
     const double* __restrict__ b = bc + (int64_t)j * g.bstride;
 #pragma unroll
@@ -158,18 +173,19 @@ hipError_t gauss_tables(const int64_t* n, int d, int m, const double* centers_ho
 }
 
 int64_t gauss_chunk_cols(const GaussTabs& g, int elem_bytes) {
-  const int64_t by_bytes = std::max<int64_t>(1, PSTT2_GAUSS_CHUNK_BYTES / (g.R * elem_bytes));
+  int64_t by_bytes = std::max<int64_t>(1, PSTT2_GAUSS_CHUNK_BYTES / (g.R * elem_bytes));
+  if (by_bytes > kGaussCols) by_bytes -= by_bytes % kGaussCols;   // whole column blocks
   const int64_t by_grid = (int64_t)65535 * kGaussCols;
   return std::min(std::min(by_bytes, by_grid), g.C);
 }
 
 hipError_t gauss_columns(const GaussTabs& g, int64_t c0, int64_t nc, int dtype, void* W, hipStream_t s) {
   if (nc <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((g.R + 255) / 256), (unsigned)((nc + kGaussCols - 1) / kGaussCols));
+  const dim3 grid((unsigned)((g.R + kGaussBlock - 1) / kGaussBlock), (unsigned)((nc + kGaussCols - 1) / kGaussCols));
   if (dtype == PSTT2_F64)
-    hipLaunchKernelGGL(k_gauss_cols<double>, grid, dim3(256), 0, s, g, c0, nc, (double*)W);
+    hipLaunchKernelGGL(k_gauss_cols<double>, grid, dim3(kGaussBlock), 0, s, g, c0, nc, (double*)W);
   else
-    hipLaunchKernelGGL(k_gauss_cols<float>, grid, dim3(256), 0, s, g, c0, nc, (float*)W);
+    hipLaunchKernelGGL(k_gauss_cols<float>, grid, dim3(kGaussBlock), 0, s, g, c0, nc, (float*)W);
   return hipGetLastError();
 }
 
