@@ -117,7 +117,7 @@ def test_gauss_error_paths():
 
 
 def test_gauss_table1_shape_full_size():
-    """n = 960, d = 3 (8.8e8 entries, never stored; seven workspace chunks of columns):
+    """n = 960, d = 3 (8.8e8 entries, never stored; two workspace chunks of columns):
     sampled sketch entries match their definition and the relative error at ranks 24
     is below 1e-10."""
     import paper_2111_10448_amd as P
