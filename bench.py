@@ -192,11 +192,13 @@ def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass", drm=
     return res
 
 
-def run_function(name, steps, warmup):
+def run_function(name, steps, warmup, prec="f64"):
     """Tensors given by a formula, never stored: Table 1's Hilbert tensors (evaluated
     inside the sketch and error kernels) or the Gaussian bumps of Section 4.4
     (evaluated into workspace chunks of columns that the memory kernels stream).
-    Reset, sketch, recover and the error pass against the same formula."""
+    Reset, sketch, recover and the error pass against the same formula.  prec other
+    than f64 (Gaussian bumps only): an FP32 context, the evaluated chunks rounded to
+    FP32 and sketched in that precision."""
     import torch
     import inputs
     import paper_2111_10448_amd as P
@@ -205,8 +207,9 @@ def run_function(name, steps, warmup):
     psi, omega = inputs.drm_factors(w)
     fac = inputs.pack_factors(psi, omega, w.d)
     fn = P.GaussBumps(inputs.gauss_centers(w), w.gamma) if w.kind == "gauss" else "hilbert"
-    ctx = P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", ranks=w.ranks())
-    log(f"[bench] {name}: {w.kind} tensor n={w.n[0]}^{w.d}, timing {steps} steps")
+    dtype = "f64" if prec == "f64" else "f32"
+    ctx = P.PSTT2(w.n, w.ell, fac, dtype=dtype, prec=prec, ranks=w.ranks())
+    log(f"[bench] {name}: {w.kind} tensor n={w.n[0]}^{w.d}, {prec} sketches, timing {steps} steps")
     t_err = t_sk = 0.0
     for it in range(warmup + steps):
         if it == warmup:
@@ -237,7 +240,7 @@ def run_function(name, steps, warmup):
     size = f"{w.numel} entries, {8 * w.numel / 2**30:.2f} GiB in FP64, never stored"
     if w.kind == "gauss":
         desc = (f"{name}: Gaussian-bump tensor ({w.terms} bumps, width parameter {w.gamma:g}) d={w.d} n={w.n[0]} "
-                f"({size}), ranks {w.ranks()}, sketch size {w.ell}")
+                f"({size}), ranks {w.ranks()}, sketch size {w.ell}, {prec} sketches")
     else:
         desc = f"{name}: Hilbert tensor d={w.d} n={w.n[0]} ({size}), Table 1 ranks, sketch size {w.ell}"
     out = {"workload": desc, "ranks": ranks, "tt_rel_error": err,
@@ -397,6 +400,11 @@ def main():
             record["gauss_bumps"] = run_function("gb_d3", max(3, args.steps // 2), 1)
         except Exception as e:
             record["gauss_bumps"] = {"error": str(e)}
+        for pr in ("f32", "bf16x3"):
+            try:
+                record[f"gauss_bumps_{pr}"] = run_function("gb_d3", max(3, args.steps // 2), 1, prec=pr)
+            except Exception as e:
+                record[f"gauss_bumps_{pr}"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         record["cpu_baseline"] = cpu_baseline(r["x"], w, r["psi"], r["omega"])
     print(json.dumps(record), flush=True)
