@@ -53,6 +53,7 @@ def _oracle_policy(x, w, drm, eps, max_tries):
     ("c5_fd", 0.1, "memory", True),         # first try: ranks (5, 6, 5), error 0.25
     ("t1_small5", 1e-4, "hilbert", True),   # first try: error 4.5e-4
     ("t1_small3", 3e-6, "hilbert", True),
+    ("gb_small3", 1e-3, "gauss", True),      # 4 recoveries on the oracle
     ("c5_fd", 1e-4, "memory", False),       # below the noise floor: stops with every rank at its cap
 ])
 def test_certified_tolerance_mode_matches_oracle_policy(name, eps, source, certified):
@@ -72,8 +73,9 @@ def test_certified_tolerance_mode_matches_oracle_policy(name, eps, source, certi
         ctx.sketch(xg)
         tt, err = ctx.recover_certified(x=xg, max_tries=8)
     else:
-        ctx.sketch_fn(source)
-        tt, err = ctx.recover_certified(fn=source, max_tries=8)
+        fn = P.GaussBumps(inputs.gauss_centers(w), w.gamma) if source == "gauss" else source
+        ctx.sketch_fn(fn)
+        tt, err = ctx.recover_certified(fn=fn, max_tries=8)
     say(f"    oracle: {tries} recoveries, ranks {r_ref}, error {e_ref:.3e}; GPU ranks {tt.ranks[1:-1]}, "
         f"error {err:.3e}")
     assert tries >= 2
