@@ -87,7 +87,7 @@ inline int64_t hilbert_rec_len(const int64_t* n, int d) {
 // per-mode factors multiplied out over modes 1, 2..m and m+1..d.  Tables are
 // j-major: e1[j * n1 + i_1], ahi[j * rhi + row / n_1], bc[j * bstride + col]
 // with bstride = C + kGaussCols and zero padding after column C - 1.
-constexpr int kGaussCols = 64;   // columns of X_m per thread in gauss_columns
+constexpr int kGaussCols = 32;   // columns of X_m per thread in gauss_columns
 struct GaussTabs {
   const double* e1;
   const double* ahi;

@@ -78,47 +78,47 @@ __global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
 constexpr int kGaussBlock = 256;   // threads per workgroup of k_gauss_cols
 
 // W(row, c) = sum_j a(row, j) b(c0 + c, j) for the columns [c0, c0 + nc) of X_m
-// (W is R_m x nc, column-major).  A thread owns one row and kGaussCols columns:
-// the row's a(row, j) is two lane-contiguous loads, the columns' b(col, j) are
-// the same for the whole wave (uniform loads), and each j costs kGaussCols
-// FMAs.  The bumps are added in increasing j.
+// (W is R_m x nc, column-major).  A thread owns two rows (kGaussBlock apart)
+// and kGaussCols columns: a row's a(row, j) is two lane-contiguous loads, the
+// columns' b(col, j) are the same for the whole wave (uniform loads, each
+// feeding both rows), and each j costs 2 kGaussCols FMAs.  The bumps are added
+// in increasing j.
 template <typename T>
 __global__ __launch_bounds__(kGaussBlock) void k_gauss_cols(const GaussTabs g, int64_t c0, int64_t nc, T* __restrict__ W) {
   constexpr int CB = kGaussCols;
-  const int64_t row = blockIdx.x * (int64_t)kGaussBlock + threadIdx.x;
+  const int64_t r0 = blockIdx.x * (int64_t)(2 * kGaussBlock) + threadIdx.x;
   const int64_t cb = c0 + (int64_t)blockIdx.y * CB;
   const int ncb = (int)std::min<int64_t>(CB, c0 + nc - cb);
-  if (row >= g.R) return;
-  const double* __restrict__ e1 = g.e1 + row % g.n1;
-  const double* __restrict__ ah = g.ahi + row / g.n1;
+  if (r0 >= g.R) return;
+  // the second row is clamped into the matrix and dropped at the store
+  const bool two = r0 + kGaussBlock < g.R;
+  const int64_t r1 = two ? r0 + kGaussBlock : r0;
+  const double* __restrict__ e1a = g.e1 + r0 % g.n1;
+  const double* __restrict__ aha = g.ahi + r0 / g.n1;
+  const double* __restrict__ e1b = g.e1 + r1 % g.n1;
+  const double* __restrict__ ahb = g.ahi + r1 / g.n1;
   const double* __restrict__ bc = g.bc + cb;   // columns past C read the table's zero padding
-  double acc[CB];
+  double acc0[CB], acc1[CB];
 #pragma unroll
-  for (int c = 0; c < CB; ++c) acc[c] = 0.0;
-  // two bumps per step: their four table loads are in flight together
-  constexpr int U = 2;
-  int j = 0;
-  for (; j + U <= g.nterms; j += U) {
-    double a[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) a[u] = e1[(int64_t)(j + u) * g.n1] * ah[(int64_t)(j + u) * g.rhi];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const double* __restrict__ b = bc + (int64_t)(j + u) * g.bstride;
-#pragma unroll
-      for (int c = 0; c < CB; ++c) acc[c] += a[u] * b[c];
-    }
-  }
-  for (; j < g.nterms; ++j) {
-    const double a = e1[(int64_t)j * g.n1] * ah[(int64_t)j * g.rhi];
+  for (int c = 0; c < CB; ++c) acc0[c] = acc1[c] = 0.0;
+  for (int j = 0; j < g.nterms; ++j) {
+    const double a0 = e1a[(int64_t)j * g.n1] * aha[(int64_t)j * g.rhi];
+    const double a1 = e1b[(int64_t)j * g.n1] * ahb[(int64_t)j * g.rhi];
     const double* __restrict__ b = bc + (int64_t)j * g.bstride;
 #pragma unroll
-    for (int c = 0; c < CB; ++c) acc[c] += a * b[c];
+    for (int c = 0; c < CB; ++c) {
+      acc0[c] += a0 * b[c];
+      acc1[c] += a1 * b[c];
+    }
   }
-  T* w = W + (cb - c0) * g.R + row;
+  T* w0 = W + (cb - c0) * g.R + r0;
+  T* w1 = W + (cb - c0) * g.R + r1;
 #pragma unroll
   for (int c = 0; c < CB; ++c)
-    if (c < ncb) w[(int64_t)c * g.R] = (T)acc[c];
+    if (c < ncb) {
+      w0[(int64_t)c * g.R] = (T)acc0[c];
+      if (two) w1[(int64_t)c * g.R] = (T)acc1[c];
+    }
 }
 
 unsigned grid1(int64_t work) {
@@ -181,7 +181,8 @@ int64_t gauss_chunk_cols(const GaussTabs& g, int elem_bytes) {
 
 hipError_t gauss_columns(const GaussTabs& g, int64_t c0, int64_t nc, int dtype, void* W, hipStream_t s) {
   if (nc <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((g.R + kGaussBlock - 1) / kGaussBlock), (unsigned)((nc + kGaussCols - 1) / kGaussCols));
+  const dim3 grid((unsigned)((g.R + 2 * kGaussBlock - 1) / (2 * kGaussBlock)),
+                  (unsigned)((nc + kGaussCols - 1) / kGaussCols));
   if (dtype == PSTT2_F64)
     hipLaunchKernelGGL(k_gauss_cols<double>, grid, dim3(kGaussBlock), 0, s, g, c0, nc, (double*)W);
   else
