@@ -192,13 +192,14 @@ def run_workload(name, prec, steps, warmup, ranks_from=None, mid="onepass", drm=
     return res
 
 
-def run_function(name, steps, warmup, prec="f64"):
+def run_function(name, steps, warmup, prec="f64", mid="onepass"):
     """Tensors given by a formula, never stored: Table 1's Hilbert tensors (evaluated
     inside the sketch and error kernels) or the Gaussian bumps of Section 4.4
     (evaluated into workspace chunks of columns that the memory kernels stream).
     Reset, sketch, recover and the error pass against the same formula.  prec other
     than f64 (Gaussian bumps only): an FP32 context, the evaluated chunks rounded to
-    FP32 and sketched in that precision."""
+    FP32 and sketched in that precision.  mid="twopass": the paper's PSTT2, whose
+    middle core evaluates the function a second time (pstt2_middle_pass_fn)."""
     import torch
     import inputs
     import paper_2111_10448_amd as P
@@ -208,8 +209,8 @@ def run_function(name, steps, warmup, prec="f64"):
     fac = inputs.pack_factors(psi, omega, w.d)
     fn = P.GaussBumps(inputs.gauss_centers(w), w.gamma) if w.kind == "gauss" else "hilbert"
     dtype = "f64" if prec == "f64" else "f32"
-    ctx = P.PSTT2(w.n, w.ell, fac, dtype=dtype, prec=prec, ranks=w.ranks())
-    log(f"[bench] {name}: {w.kind} tensor n={w.n[0]}^{w.d}, {prec} sketches, timing {steps} steps")
+    ctx = P.PSTT2(w.n, w.ell, fac, dtype=dtype, prec=prec, ranks=w.ranks(), mid=mid)
+    log(f"[bench] {name}: {w.kind} tensor n={w.n[0]}^{w.d}, {prec} sketches, {mid} middle core, timing {steps} steps")
     t_err = t_sk = 0.0
     for it in range(warmup + steps):
         if it == warmup:
@@ -224,6 +225,8 @@ def run_function(name, steps, warmup, prec="f64"):
         if it >= warmup:
             t_sk += time.perf_counter() - a
         tt = ctx.recover()
+        if mid == "twopass":
+            ctx.middle_pass_fn(tt, fn)
         a = time.perf_counter()
         err = tt.error_fn(fn)
         if it >= warmup:
@@ -240,7 +243,7 @@ def run_function(name, steps, warmup, prec="f64"):
     size = f"{w.numel} entries, {8 * w.numel / 2**30:.2f} GiB in FP64, never stored"
     if w.kind == "gauss":
         desc = (f"{name}: Gaussian-bump tensor ({w.terms} bumps, width parameter {w.gamma:g}) d={w.d} n={w.n[0]} "
-                f"({size}), ranks {w.ranks()}, sketch size {w.ell}, {prec} sketches")
+                f"({size}), ranks {w.ranks()}, sketch size {w.ell}, {prec} sketches, {mid} middle core")
     else:
         desc = f"{name}: Hilbert tensor d={w.d} n={w.n[0]} ({size}), Table 1 ranks, sketch size {w.ell}"
     out = {"workload": desc, "ranks": ranks, "tt_rel_error": err,
@@ -400,6 +403,10 @@ def main():
             record["gauss_bumps"] = run_function("gb_d3", max(3, args.steps // 2), 1)
         except Exception as e:
             record["gauss_bumps"] = {"error": str(e)}
+        try:
+            record["gauss_bumps_twopass"] = run_function("gb_d3", max(3, args.steps // 2), 1, mid="twopass")
+        except Exception as e:
+            record["gauss_bumps_twopass"] = {"error": str(e)}
         for pr in ("f32", "bf16x3"):
             try:
                 record[f"gauss_bumps_{pr}"] = run_function("gb_d3", max(3, args.steps // 2), 1, prec=pr)

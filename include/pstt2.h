@@ -237,6 +237,18 @@ pstt2_status pstt2_recover_certified(pstt2_ctx* ctx, const void* x_dev, const ps
 pstt2_status pstt2_middle_pass(pstt2_ctx* ctx, tt_cores* cores, const void* x_dev, int64_t first,
                                int64_t count);
 
+/* The same second pass over the tensor function fn (see pstt2_fn): Section 4.4's
+ * PSTT2 evaluates the function a second time for its last core, which the one-pass
+ * cores avoid.  The entries [first, first + count) are evaluated in FP64 into
+ * workspace chunks of whole columns of the pass's unfolding (at most
+ * PSTT2_GAUSS_CHUNK_BYTES each, in the context's dtype) that pstt2_middle_pass
+ * then reads; first and count must be multiples of that unfolding's row count
+ * (n_1...n_m, or n_1...n_{d-1} for PSTT2_ALGO_PSTT).  Returns once the last
+ * chunk's work is queued.  Errors: those of pstt2_middle_pass, EINVAL (fn
+ * fields, alignment), ENOMEM, EDEVICE. */
+pstt2_status pstt2_middle_pass_fn(pstt2_ctx* ctx, tt_cores* cores, const pstt2_fn* fn, int64_t first,
+                                  int64_t count);
+
 /* Vector-Jacobian product of the one-pass map X -> X~ (the cores returned by
  * the last pstt2_recover of this context, reconstructed by the entry formula
  * of Section 2.2), with the pivots and ranks of that recovery held fixed.

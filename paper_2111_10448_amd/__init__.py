@@ -255,6 +255,15 @@ class PSTT2:
                                           int(first), int(x.numel())), self._ctx)
         self._keep.append(x)
 
+    def middle_pass_fn(self, tt: TT, fn="hilbert", first: int = 0, count: Optional[int] = None) -> None:
+        """The two-pass middle core's second pass over a tensor function ("hilbert" or a
+        GaussBumps), evaluated in workspace chunks; count defaults to the rest."""
+        f = _fn_struct(fn, len(self.n))
+        if count is None:
+            count = int(np.prod(self.n)) - int(first)
+        L.check(L.lib().pstt2_middle_pass_fn(self._c(), ctypes.byref(tt.struct()), ctypes.byref(f), int(first),
+                                             int(count)), self._ctx)
+
     def vjp(self, tt: "TT", x=None, gbar=None):
         """J^T gbar for X~ = the one-pass approximation (either one-pass middle-core
         rule, either DRM scheme; pivots and ranks of the last recover held fixed);

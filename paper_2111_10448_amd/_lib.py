@@ -82,6 +82,7 @@ def lib():
     L.pstt2_sketch_slabs.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.pstt2_recover.argtypes = [vp, ctypes.POINTER(TTCores)]
     L.pstt2_middle_pass.argtypes = [vp, ctypes.POINTER(TTCores), vp, i64, i64]
+    L.pstt2_middle_pass_fn.argtypes = [vp, ctypes.POINTER(TTCores), ctypes.POINTER(Fn), i64, i64]
     L.pstt2_vjp.argtypes = [vp, ctypes.POINTER(TTCores), vp, vp, vp]
     L.pstt2_get_sketch.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                    ctypes.POINTER(i64)]
@@ -106,7 +107,8 @@ def lib():
     L.pstt2_version.restype = ctypes.c_char_p
     for f in ("pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
               "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_reset", "tt_error", "tt_reconstruct", "tt_cores_copy",
-              "pstt2_profile", "pstt2_profile_read", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified"):
+              "pstt2_profile", "pstt2_profile_read", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified",
+              "pstt2_middle_pass_fn"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -119,7 +121,8 @@ def check(status: int, ctx=None) -> None:
 
 
 # Every symbol include/pstt2.h declares.
-EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
+EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass",
+           "pstt2_middle_pass_fn", "pstt2_vjp",
            "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_profile", "pstt2_profile_read", "pstt2_reset",
            "pstt2_destroy", "tt_error", "tt_reconstruct", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified",
            "tt_cores_copy", "tt_cores_free", "pstt2_last_error", "pstt2_version"]

@@ -1081,6 +1081,51 @@ pstt2_status pstt2_middle_pass(pstt2_ctx* c, tt_cores* cores, const void* x_dev,
   return PSTT2_OK;
 }
 
+pstt2_status pstt2_middle_pass_fn(pstt2_ctx* c, tt_cores* cores, const pstt2_fn* fn, int64_t first,
+                                  int64_t count) {
+  if (!c || !cores || !fn) return fail(c, PSTT2_EINVAL, "null argument");
+  if (const char* why = fn_invalid(fn)) return fail(c, PSTT2_EINVAL, why);
+  if (c->desc.mid != PSTT2_MID_TWOPASS || !c->recovered)
+    return fail(c, PSTT2_ESTATE, "middle pass needs a two-pass context after pstt2_recover");
+  if (first < 0 || count < 0 || first + count > c->N) return fail(c, PSTT2_EINVAL, "slab range outside the tensor");
+  if (first % c->R != 0 || count % c->R != 0)
+    return fail(c, PSTT2_EINVAL, "first/count must be whole columns of the pass's unfolding");
+  if (count == 0) return PSTT2_OK;
+  hipStream_t s = c->stream;
+  const int esz = c->dtype == PSTT2_F64 ? 8 : 4;
+  // tables of the split the pass runs at (m, or d - 1 for the one-sided algorithm)
+  GaussTabs g;
+  double* tabs = nullptr;
+  int32_t *row_t = nullptr, *col_t = nullptr;
+  hipError_t e = hipSuccess;
+  int64_t ncmax = 0;
+  if (fn->kind == PSTT2_FN_GAUSS) {
+    e = ws_alloc((void**)&tabs, sizeof(double) * gauss_table_doubles(c->n, c->d, c->m, fn->n_terms), s);
+    if (e == hipSuccess) e = gauss_tables(c->n, c->d, c->m, fn->centers, fn->n_terms, fn->gamma, tabs, &g, s);
+    if (e == hipSuccess) ncmax = gauss_chunk_cols(g, esz);
+  } else {
+    e = ws_alloc((void**)&tabs, sizeof(double) * hilbert_rec_len(c->n, c->d), s);
+    if (e == hipSuccess) e = ws_alloc((void**)&row_t, sizeof(int32_t) * c->R, s);
+    if (e == hipSuccess) e = ws_alloc((void**)&col_t, sizeof(int32_t) * c->C, s);
+    if (e == hipSuccess) e = hilbert_tables(c->n, c->d, c->m, c->R, c->C, tabs, row_t, col_t, s);
+    ncmax = std::min(c->C, std::max<int64_t>(1, PSTT2_GAUSS_CHUNK_BYTES / (c->R * esz)));
+  }
+  void* W = nullptr;
+  if (e == hipSuccess) e = ws_alloc(&W, (size_t)esz * c->R * std::min(ncmax, count / c->R), s);
+  pstt2_status st = e == hipSuccess ? PSTT2_OK : hfail(c, e, "tensor-function workspace");
+  for (int64_t c0 = first / c->R; st == PSTT2_OK && c0 < (first + count) / c->R; c0 += ncmax) {
+    const int64_t nc = std::min(ncmax, (first + count) / c->R - c0);
+    e = fn->kind == PSTT2_FN_GAUSS ? gauss_columns(g, c0, nc, c->dtype, W, s)
+                                   : hilbert_columns(tabs, row_t, col_t, c->R, c0, nc, c->dtype, W, s);
+    st = e == hipSuccess ? pstt2_middle_pass(c, cores, W, c0 * c->R, nc * c->R) : hfail(c, e, "tensor-function columns");
+  }
+  if (W) ws_free(W, s);
+  if (col_t) ws_free(col_t, s);
+  if (row_t) ws_free(row_t, s);
+  if (tabs) ws_free(tabs, s);
+  return st;
+}
+
 pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, const void* gbar_dev,
                        void* gx_dev) {
   if (!c || !cores || !gx_dev) return fail(c, PSTT2_EINVAL, "null argument");

@@ -76,6 +76,10 @@ struct SketchArgs {
 // entries, row_t R and col_t C.
 hipError_t hilbert_tables(const int64_t* n, int d, int m, int64_t R, int64_t C, double* rec, int32_t* row_t,
                           int32_t* col_t, hipStream_t s);
+// Columns [c0, c0 + nc) of X_m of the Hilbert tensor from its tables into W
+// (R x nc column-major, dtype F64 or F32).
+hipError_t hilbert_columns(const double* rec, const int32_t* row_t, const int32_t* col_t, int64_t R, int64_t c0,
+                           int64_t nc, int dtype, void* W, hipStream_t s);
 inline int64_t hilbert_rec_len(const int64_t* n, int d) {
   int64_t k = 2;
   for (int q = 0; q < d; ++q) k += n[q] - 1;

@@ -121,6 +121,16 @@ __global__ __launch_bounds__(kGaussBlock) void k_gauss_cols(const GaussTabs g, i
     }
 }
 
+// W(row, c) = rec[row_t[row] + col_t[c0 + c]] for the columns [c0, c0 + nc) of X_m
+template <typename T>
+__global__ void k_hilbert_cols(const double* __restrict__ rec, const int32_t* __restrict__ row_t,
+                               const int32_t* __restrict__ col_t, int64_t R, int64_t c0, int64_t nc,
+                               T* __restrict__ W) {
+  const int64_t tot = R * nc;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x)
+    W[t] = (T)rec[row_t[t % R] + col_t[c0 + t / R]];
+}
+
 unsigned grid1(int64_t work) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 4096));
 }
@@ -187,6 +197,17 @@ hipError_t gauss_columns(const GaussTabs& g, int64_t c0, int64_t nc, int dtype, 
     hipLaunchKernelGGL(k_gauss_cols<double>, grid, dim3(kGaussBlock), 0, s, g, c0, nc, (double*)W);
   else
     hipLaunchKernelGGL(k_gauss_cols<float>, grid, dim3(kGaussBlock), 0, s, g, c0, nc, (float*)W);
+  return hipGetLastError();
+}
+
+hipError_t hilbert_columns(const double* rec, const int32_t* row_t, const int32_t* col_t, int64_t R, int64_t c0,
+                           int64_t nc, int dtype, void* W, hipStream_t s) {
+  if (nc <= 0) return hipSuccess;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((R * nc + 255) / 256, 65536));
+  if (dtype == PSTT2_F64)
+    hipLaunchKernelGGL(k_hilbert_cols<double>, dim3(g), dim3(256), 0, s, rec, row_t, col_t, R, c0, nc, (double*)W);
+  else
+    hipLaunchKernelGGL(k_hilbert_cols<float>, dim3(g), dim3(256), 0, s, rec, row_t, col_t, R, c0, nc, (float*)W);
   return hipGetLastError();
 }
 
