@@ -195,8 +195,9 @@ typedef struct {
  * middle unfolding X_m); the same coverage rules as pstt2_sketch apply, and
  * slabs from memory and from fn may be mixed.  HILBERT builds small index
  * tables (R_m + C_m int32 and sum_q n_q doubles) on first use and keeps them
- * with the context; GAUSS builds its tables on every call.  async (GAUSS
- * copies the centers before it returns).  Errors: EINVAL (kind, fields,
+ * with the context; GAUSS builds its tables on every call.  async (GAUSS first
+ * waits for the stream's earlier work and its own table set-up, so the centers
+ * may be freed on return, then queues the chunks).  Errors: EINVAL (kind, fields,
  * dtype / prec, alignment, range), ESTATE (overlap, after recover), ENOMEM, EDEVICE. */
 pstt2_status pstt2_sketch_fn(pstt2_ctx* ctx, const pstt2_fn* fn, int64_t first, int64_t count);
 
@@ -237,15 +238,16 @@ pstt2_status pstt2_recover_certified(pstt2_ctx* ctx, const void* x_dev, const ps
 pstt2_status pstt2_middle_pass(pstt2_ctx* ctx, tt_cores* cores, const void* x_dev, int64_t first,
                                int64_t count);
 
-/* The same second pass over the tensor function fn (see pstt2_fn): Section 4.4's
- * PSTT2 evaluates the function a second time for its last core, which the one-pass
- * cores avoid.  The entries [first, first + count) are evaluated in FP64 into
- * workspace chunks of whole columns of the pass's unfolding (at most
- * PSTT2_GAUSS_CHUNK_BYTES each, in the context's dtype) that pstt2_middle_pass
- * then reads; first and count must be multiples of that unfolding's row count
- * (n_1...n_m, or n_1...n_{d-1} for PSTT2_ALGO_PSTT).  Returns once the last
- * chunk's work is queued.  Errors: those of pstt2_middle_pass, EINVAL (fn
- * fields, alignment), ENOMEM, EDEVICE. */
+/* The same second pass over the tensor function fn (see pstt2_fn): Section
+ * 4.4's PSTT2 evaluates the function a second time for its middle core (the
+ * one-sided algorithm: its last core), which the one-pass cores avoid.  The
+ * entries [first, first + count) are evaluated in FP64 into workspace chunks of
+ * whole columns of the pass's unfolding (at most PSTT2_GAUSS_CHUNK_BYTES each,
+ * in the context's dtype) that pstt2_middle_pass then reads; first and count
+ * must be multiples of that unfolding's row count (n_1...n_m, or
+ * n_1...n_{d-1} for PSTT2_ALGO_PSTT).  Like pstt2_sketch_fn it waits for the
+ * table set-up and returns once the last chunk's work is queued.  Errors:
+ * those of pstt2_middle_pass, EINVAL (fn fields, alignment), ENOMEM, EDEVICE. */
 pstt2_status pstt2_middle_pass_fn(pstt2_ctx* ctx, tt_cores* cores, const pstt2_fn* fn, int64_t first,
                                   int64_t count);
 
