@@ -1172,7 +1172,9 @@ hipError_t middle_ls(const double* Z, int64_t nz, const double* A, int rm, int e
 
 // Two-pass middle core over a slab of X (flat entries [first, first+count)):
 // G(a, i, b) += sum Qprev(row', a) X(row' + Rp i, col') Pm(col', b).
-// One block per (i, col') fibre present in the slab; FP64.
+// One block per (i, col') fibre present in the slab; FP64.  Used when X_m has a
+// single column (the one-sided algorithm's last core, Pm = 1); otherwise the
+// two fixed-order kernels below.
 template <typename T>
 __global__ __launch_bounds__(256) void k_middle_twopass(const T* __restrict__ x, int64_t first, int64_t count,
                                                         int64_t Rp, int nm, int64_t Cm, const double* __restrict__ Qp,
@@ -1208,12 +1210,101 @@ __global__ __launch_bounds__(256) void k_middle_twopass(const T* __restrict__ x,
   }
 }
 
+// Two steps in a fixed order (no atomics) when X_m has more than one column:
+// (1) Z = X_m(:, slab) P_m(slab, :), R_m x r_m: a thread owns one row of X_m
+//     and walks its share of the slab's columns (P_m's row is wave-uniform);
+//     column shares go to gj partials.
+// (2) G(a, i, b) += sum_{row'} Qprev(row', a) Z(row' + R_{m-1} i, b): one block
+//     per (i, b), the partials added in increasing share order.
+template <typename T, int RK>
+__global__ __launch_bounds__(256) void k_twopass_z(const T* __restrict__ x, int64_t first, int64_t count, int64_t R,
+                                                   int64_t Cm, const double* __restrict__ Pm, int rm, int gi_count,
+                                                   int gj_count, double* __restrict__ Zp) {
+  const int gi = blockIdx.x % gi_count, g = blockIdx.x / gi_count;
+  const int64_t row = (int64_t)gi * 256 + threadIdx.x;
+  if (row >= R) return;
+  const int64_t c0 = first / R, c1 = (first + count + R - 1) / R;
+  const int64_t cb = c0 + g * (c1 - c0) / gj_count, ce = c0 + (g + 1) * (c1 - c0) / gj_count;
+  double acc[RK];
+#pragma unroll
+  for (int b = 0; b < RK; ++b) acc[b] = 0.0;
+  for (int64_t col = cb; col < ce; ++col) {
+    const int64_t e = col * R + row;
+    if (e < first || e >= first + count) continue;   // rows outside a partial first / last column
+    const double xv = (double)x[e - first];
+#pragma unroll
+    for (int b = 0; b < RK; ++b)
+      if (b < rm) acc[b] += xv * Pm[(int64_t)b * Cm + col];
+  }
+#pragma unroll
+  for (int b = 0; b < RK; ++b)
+    if (b < rm) Zp[((int64_t)g * rm + b) * R + row] = acc[b];
+}
+
+__global__ __launch_bounds__(256) void k_twopass_g(const double* __restrict__ Zp, int gj_count, int64_t Rp, int nm,
+                                                   const double* __restrict__ Qp, int rp, int rm,
+                                                   double* __restrict__ G) {
+  constexpr int MX = PSTT2_MAX_ELL;
+  __shared__ double red[MX][4];
+  const int i = (int)(blockIdx.x % nm), b = (int)(blockIdx.x / nm);
+  const int64_t R = Rp * nm;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double part[MX];
+#pragma unroll
+  for (int a = 0; a < MX; ++a) part[a] = 0.0;
+  for (int64_t rr = threadIdx.x; rr < Rp; rr += blockDim.x) {
+    const int64_t row = rr + Rp * i;
+    double z = 0.0;
+    for (int g = 0; g < gj_count; ++g) z += Zp[((int64_t)g * rm + b) * R + row];
+#pragma unroll
+    for (int a = 0; a < MX; ++a)
+      if (a < rp) part[a] += Qp[(int64_t)a * Rp + rr] * z;
+  }
+#pragma unroll
+  for (int a = 0; a < MX; ++a) {
+    if (a < rp) {
+      const double v = wave_sum(part[a]);
+      if (lane == 0) red[a][w] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < rp) {
+    const int a = threadIdx.x;
+    G[a + (int64_t)rp * (i + (int64_t)nm * b)] += red[a][0] + red[a][1] + red[a][2] + red[a][3];
+  }
+}
+
+template <typename T>
+static void launch_twopass_z(const T* x, int64_t first, int64_t count, int64_t R, int64_t Cm, const double* Pm,
+                             int rm, int gi, int gj, double* Zp, hipStream_t s) {
+  const dim3 g((unsigned)(gi * gj)), bl(256);
+  if (rm <= 8) hipLaunchKernelGGL((k_twopass_z<T, 8>), g, bl, 0, s, x, first, count, R, Cm, Pm, rm, gi, gj, Zp);
+  else if (rm <= 16) hipLaunchKernelGGL((k_twopass_z<T, 16>), g, bl, 0, s, x, first, count, R, Cm, Pm, rm, gi, gj, Zp);
+  else if (rm <= 24) hipLaunchKernelGGL((k_twopass_z<T, 24>), g, bl, 0, s, x, first, count, R, Cm, Pm, rm, gi, gj, Zp);
+  else hipLaunchKernelGGL((k_twopass_z<T, 32>), g, bl, 0, s, x, first, count, R, Cm, Pm, rm, gi, gj, Zp);
+}
+
 hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count, int64_t Rprev, int nm, int64_t Cm,
                           const double* Qprev, int rprev, const double* Pm, int rm, double* G, hipStream_t s) {
   const int64_t f0 = first / Rprev;
   const int64_t f1 = (first + count + Rprev - 1) / Rprev;
   const unsigned nb = (unsigned)(f1 - f0);
   if (nb == 0) return hipSuccess;
+  if (Cm > 1) {
+    const int64_t R = Rprev * nm;
+    const int64_t ncol = (first + count + R - 1) / R - first / R;
+    const int gi = (int)((R + 255) / 256);
+    const int gj = (int)std::max<int64_t>(1, std::min<int64_t>(ncol, 2048 / gi));
+    double* Zp = nullptr;
+    hipError_t e = ws_alloc((void**)&Zp, sizeof(double) * gj * rm * R, s);
+    if (e != hipSuccess) return e;
+    if (dtype == PSTT2_F64) launch_twopass_z((const double*)x, first, count, R, Cm, Pm, rm, gi, gj, Zp, s);
+    else launch_twopass_z((const float*)x, first, count, R, Cm, Pm, rm, gi, gj, Zp, s);
+    hipLaunchKernelGGL(k_twopass_g, dim3((unsigned)(nm * rm)), dim3(256), 0, s, Zp, gj, Rprev, nm, Qprev, rprev, rm, G);
+    e = hipGetLastError();
+    ws_free(Zp, s);
+    return e;
+  }
   if (dtype == PSTT2_F64)
     hipLaunchKernelGGL(k_middle_twopass<double>, dim3(nb), dim3(256), 0, s, (const double*)x, first, count, Rprev, nm,
                        Cm, Qprev, rprev, Pm, rm, G);
