@@ -1212,14 +1212,15 @@ __global__ __launch_bounds__(256) void k_middle_twopass(const T* __restrict__ x,
 
 // Two steps in a fixed order (no atomics) when X_m has more than one column:
 // (1) Z = X_m(:, slab) P_m(slab, :), R_m x r_m: a thread owns one row of X_m
-//     and walks its share of the slab's columns (P_m's row is wave-uniform);
-//     column shares go to gj partials.
+//     and walks its share of the slab's columns; P_m is staged row-major with
+//     its rows padded to RK (Pt, zero past r_m), so a column's weights are one
+//     contiguous wave-uniform read; column shares go to gj partials.
 // (2) G(a, i, b) += sum_{row'} Qprev(row', a) Z(row' + R_{m-1} i, b): one block
 //     per (i, b), the partials added in increasing share order.
 template <typename T, int RK>
 __global__ __launch_bounds__(256) void k_twopass_z(const T* __restrict__ x, int64_t first, int64_t count, int64_t R,
-                                                   int64_t Cm, const double* __restrict__ Pm, int rm, int gi_count,
-                                                   int gj_count, double* __restrict__ Zp) {
+                                                   const double* __restrict__ Pt, int rm, int gi_count, int gj_count,
+                                                   double* __restrict__ Zp) {
   const int gi = blockIdx.x % gi_count, g = blockIdx.x / gi_count;
   const int64_t row = (int64_t)gi * 256 + threadIdx.x;
   if (row >= R) return;
@@ -1228,13 +1229,32 @@ __global__ __launch_bounds__(256) void k_twopass_z(const T* __restrict__ x, int6
   double acc[RK];
 #pragma unroll
   for (int b = 0; b < RK; ++b) acc[b] = 0.0;
-  for (int64_t col = cb; col < ce; ++col) {
+  // eight columns' loads in flight; an entry outside the slab (rows of a partial
+  // first or last column) reads the slab's first entry and is given weight 0
+  constexpr int U = 8;
+  auto load = [&](int64_t col) -> double {
     const int64_t e = col * R + row;
-    if (e < first || e >= first + count) continue;   // rows outside a partial first / last column
-    const double xv = (double)x[e - first];
+    const bool ok = e >= first && e < first + count;
+    const double v = (double)x[ok ? e - first : 0];
+    return ok ? v : 0.0;
+  };
+  int64_t col = cb;
+  for (; col + U <= ce; col += U) {
+    double xv[U];
 #pragma unroll
-    for (int b = 0; b < RK; ++b)
-      if (b < rm) acc[b] += xv * Pm[(int64_t)b * Cm + col];
+    for (int u = 0; u < U; ++u) xv[u] = load(col + u);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double* p = Pt + (col + u) * RK;
+#pragma unroll
+      for (int b = 0; b < RK; ++b) acc[b] += xv[u] * p[b];
+    }
+  }
+  for (; col < ce; ++col) {
+    const double xv = load(col);
+    const double* p = Pt + col * RK;
+#pragma unroll
+    for (int b = 0; b < RK; ++b) acc[b] += xv * p[b];
   }
 #pragma unroll
   for (int b = 0; b < RK; ++b)
@@ -1274,14 +1294,27 @@ __global__ __launch_bounds__(256) void k_twopass_g(const double* __restrict__ Zp
   }
 }
 
+// Pt(col, b) = Pm(col, b) for b < rm, 0 for rm <= b < RK (Pt row-major, RK per row)
+__global__ void k_twopass_pt(const double* __restrict__ Pm, int64_t Cm, int rm, int RK, double* __restrict__ Pt) {
+  const int64_t tot = Cm * RK;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(t % RK);
+    Pt[t] = b < rm ? Pm[(int64_t)b * Cm + t / RK] : 0.0;
+  }
+}
+
+static int twopass_rk(int rm) { return rm <= 8 ? 8 : rm <= 16 ? 16 : rm <= 24 ? 24 : 32; }
+
 template <typename T>
-static void launch_twopass_z(const T* x, int64_t first, int64_t count, int64_t R, int64_t Cm, const double* Pm,
-                             int rm, int gi, int gj, double* Zp, hipStream_t s) {
+static void launch_twopass_z(const T* x, int64_t first, int64_t count, int64_t R, const double* Pt, int rm, int gi,
+                             int gj, double* Zp, hipStream_t s) {
   const dim3 g((unsigned)(gi * gj)), bl(256);
-  if (rm <= 8) hipLaunchKernelGGL((k_twopass_z<T, 8>), g, bl, 0, s, x, first, count, R, Cm, Pm, rm, gi, gj, Zp);
-  else if (rm <= 16) hipLaunchKernelGGL((k_twopass_z<T, 16>), g, bl, 0, s, x, first, count, R, Cm, Pm, rm, gi, gj, Zp);
-  else if (rm <= 24) hipLaunchKernelGGL((k_twopass_z<T, 24>), g, bl, 0, s, x, first, count, R, Cm, Pm, rm, gi, gj, Zp);
-  else hipLaunchKernelGGL((k_twopass_z<T, 32>), g, bl, 0, s, x, first, count, R, Cm, Pm, rm, gi, gj, Zp);
+  switch (twopass_rk(rm)) {
+    case 8: hipLaunchKernelGGL((k_twopass_z<T, 8>), g, bl, 0, s, x, first, count, R, Pt, rm, gi, gj, Zp); break;
+    case 16: hipLaunchKernelGGL((k_twopass_z<T, 16>), g, bl, 0, s, x, first, count, R, Pt, rm, gi, gj, Zp); break;
+    case 24: hipLaunchKernelGGL((k_twopass_z<T, 24>), g, bl, 0, s, x, first, count, R, Pt, rm, gi, gj, Zp); break;
+    default: hipLaunchKernelGGL((k_twopass_z<T, 32>), g, bl, 0, s, x, first, count, R, Pt, rm, gi, gj, Zp); break;
+  }
 }
 
 hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count, int64_t Rprev, int nm, int64_t Cm,
@@ -1295,13 +1328,21 @@ hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count
     const int64_t ncol = (first + count + R - 1) / R - first / R;
     const int gi = (int)((R + 255) / 256);
     const int gj = (int)std::max<int64_t>(1, std::min<int64_t>(ncol, 2048 / gi));
-    double* Zp = nullptr;
+    const int RK = twopass_rk(rm);
+    double *Zp = nullptr, *Pt = nullptr;
     hipError_t e = ws_alloc((void**)&Zp, sizeof(double) * gj * rm * R, s);
-    if (e != hipSuccess) return e;
-    if (dtype == PSTT2_F64) launch_twopass_z((const double*)x, first, count, R, Cm, Pm, rm, gi, gj, Zp, s);
-    else launch_twopass_z((const float*)x, first, count, R, Cm, Pm, rm, gi, gj, Zp, s);
+    if (e == hipSuccess) e = ws_alloc((void**)&Pt, sizeof(double) * Cm * RK, s);
+    if (e != hipSuccess) {
+      if (Zp) ws_free(Zp, s);
+      return e;
+    }
+    hipLaunchKernelGGL(k_twopass_pt, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((Cm * RK + 255) / 256, 4096))),
+                       dim3(256), 0, s, Pm, Cm, rm, RK, Pt);
+    if (dtype == PSTT2_F64) launch_twopass_z((const double*)x, first, count, R, Pt, rm, gi, gj, Zp, s);
+    else launch_twopass_z((const float*)x, first, count, R, Pt, rm, gi, gj, Zp, s);
     hipLaunchKernelGGL(k_twopass_g, dim3((unsigned)(nm * rm)), dim3(256), 0, s, Zp, gj, Rprev, nm, Qprev, rprev, rm, G);
     e = hipGetLastError();
+    ws_free(Pt, s);
     ws_free(Zp, s);
     return e;
   }
