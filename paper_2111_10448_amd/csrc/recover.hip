@@ -1261,6 +1261,53 @@ __global__ __launch_bounds__(256) void k_twopass_z(const T* __restrict__ x, int6
     if (b < rm) Zp[((int64_t)g * rm + b) * R + row] = acc[b];
 }
 
+// The same for FP64 slabs of whole columns with R even: a lane owns rows
+// (2t, 2t + 1) and reads both with one 16-byte load per column.  cols are
+// local to the slab (column c0 + col of X_m is x + col R).
+template <int RK>
+__global__ __launch_bounds__(256) void k_twopass_z2(const double* __restrict__ x, int64_t R, int64_t c0, int64_t ncol,
+                                                    const double* __restrict__ Pt, int rm, int gi_count, int gj_count,
+                                                    double* __restrict__ Zp) {
+  const int gi = blockIdx.x % gi_count, g = blockIdx.x / gi_count;
+  const int64_t row = ((int64_t)gi * 256 + threadIdx.x) * 2;
+  if (row >= R) return;
+  const int64_t cb = g * ncol / gj_count, ce = (g + 1) * ncol / gj_count;
+  double acc0[RK], acc1[RK];
+#pragma unroll
+  for (int b = 0; b < RK; ++b) acc0[b] = acc1[b] = 0.0;
+  constexpr int U = 8;
+  int64_t col = cb;
+  for (; col + U <= ce; col += U) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = *(const double2*)(x + (col + u) * R + row);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double* p = Pt + (c0 + col + u) * RK;
+#pragma unroll
+      for (int b = 0; b < RK; ++b) {
+        acc0[b] += v[u].x * p[b];
+        acc1[b] += v[u].y * p[b];
+      }
+    }
+  }
+  for (; col < ce; ++col) {
+    const double2 v = *(const double2*)(x + col * R + row);
+    const double* p = Pt + (c0 + col) * RK;
+#pragma unroll
+    for (int b = 0; b < RK; ++b) {
+      acc0[b] += v.x * p[b];
+      acc1[b] += v.y * p[b];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < RK; ++b)
+    if (b < rm) {
+      Zp[((int64_t)g * rm + b) * R + row] = acc0[b];
+      Zp[((int64_t)g * rm + b) * R + row + 1] = acc1[b];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_twopass_g(const double* __restrict__ Zp, int gj_count, int64_t Rp, int nm,
                                                    const double* __restrict__ Qp, int rp, int rm,
                                                    double* __restrict__ G) {
@@ -1326,7 +1373,10 @@ hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count
   if (Cm > 1) {
     const int64_t R = Rprev * nm;
     const int64_t ncol = (first + count + R - 1) / R - first / R;
-    const int gi = (int)((R + 255) / 256);
+    // pair loads: FP64 slab of whole columns, R even, 16-byte aligned base
+    const bool pair = dtype == PSTT2_F64 && R % 2 == 0 && first % R == 0 && count % R == 0 &&
+                      ((uintptr_t)x % 16) == 0;
+    const int gi = (int)(pair ? (R + 511) / 512 : (R + 255) / 256);
     const int gj = (int)std::max<int64_t>(1, std::min<int64_t>(ncol, 2048 / gi));
     const int RK = twopass_rk(rm);
     double *Zp = nullptr, *Pt = nullptr;
@@ -1338,8 +1388,21 @@ hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count
     }
     hipLaunchKernelGGL(k_twopass_pt, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((Cm * RK + 255) / 256, 4096))),
                        dim3(256), 0, s, Pm, Cm, rm, RK, Pt);
-    if (dtype == PSTT2_F64) launch_twopass_z((const double*)x, first, count, R, Pt, rm, gi, gj, Zp, s);
-    else launch_twopass_z((const float*)x, first, count, R, Pt, rm, gi, gj, Zp, s);
+    if (pair) {
+      const dim3 g((unsigned)(gi * gj)), bl(256);
+      const double* xd = (const double*)x;
+      const int64_t c0 = first / R;
+      switch (RK) {
+        case 8: hipLaunchKernelGGL((k_twopass_z2<8>), g, bl, 0, s, xd, R, c0, ncol, Pt, rm, gi, gj, Zp); break;
+        case 16: hipLaunchKernelGGL((k_twopass_z2<16>), g, bl, 0, s, xd, R, c0, ncol, Pt, rm, gi, gj, Zp); break;
+        case 24: hipLaunchKernelGGL((k_twopass_z2<24>), g, bl, 0, s, xd, R, c0, ncol, Pt, rm, gi, gj, Zp); break;
+        default: hipLaunchKernelGGL((k_twopass_z2<32>), g, bl, 0, s, xd, R, c0, ncol, Pt, rm, gi, gj, Zp); break;
+      }
+    } else if (dtype == PSTT2_F64) {
+      launch_twopass_z((const double*)x, first, count, R, Pt, rm, gi, gj, Zp, s);
+    } else {
+      launch_twopass_z((const float*)x, first, count, R, Pt, rm, gi, gj, Zp, s);
+    }
     hipLaunchKernelGGL(k_twopass_g, dim3((unsigned)(nm * rm)), dim3(256), 0, s, Zp, gj, Rprev, nm, Qprev, rprev, rm, G);
     e = hipGetLastError();
     ws_free(Pt, s);
