@@ -637,7 +637,7 @@ static pstt2_status sketch_gauss(pstt2_ctx* c, const pstt2_fn* fn, int64_t first
   GaussTabs g;
   e = gauss_tables(c->n, c->d, c->m, fn->centers, fn->n_terms, fn->gamma, tabs, &g, s);
   const int esz = c->dtype == PSTT2_F64 ? 8 : 4;
-  const int64_t ncmax = gauss_chunk_cols(g, esz);
+  const int64_t ncmax = e == hipSuccess ? gauss_chunk_cols(g, esz) : 1;   // g is set only on success
   void* W = nullptr;
   if (e == hipSuccess) e = ws_alloc(&W, (size_t)esz * c->R * std::min(ncmax, count / c->R), s);
   pstt2_status st = PSTT2_OK;
@@ -1098,7 +1098,7 @@ pstt2_status pstt2_middle_pass_fn(pstt2_ctx* c, tt_cores* cores, const pstt2_fn*
   double* tabs = nullptr;
   int32_t *row_t = nullptr, *col_t = nullptr;
   hipError_t e = hipSuccess;
-  int64_t ncmax = 0;
+  int64_t ncmax = 1;   // set from the tables once they exist
   if (fn->kind == PSTT2_FN_GAUSS) {
     e = ws_alloc((void**)&tabs, sizeof(double) * gauss_table_doubles(c->n, c->d, c->m, fn->n_terms), s);
     if (e == hipSuccess) e = gauss_tables(c->n, c->d, c->m, fn->centers, fn->n_terms, fn->gamma, tabs, &g, s);
