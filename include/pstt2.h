@@ -26,6 +26,17 @@
  *     every other pointer is host memory.
  *   - Every call returns a pstt2_status; nothing throws across the ABI.  On an
  *     error the outputs are left untouched and pstt2_last_error() describes it.
+ *     The exception: a call that adds data into a context's sketches (or into
+ *     a two-pass middle core) in several launches and fails after the first of
+ *     them has run leaves those sums partial.  The context is then poisoned:
+ *     every later sketch, recover, middle-pass and vjp call on it returns
+ *     PSTT2_ESTATE until pstt2_reset (and a middle core being accumulated by
+ *     pstt2_middle_pass_fn must be recomputed).  Nothing is double-counted by
+ *     retrying after the reset.
+ *   - Every device allocation of the library counts against an optional
+ *     memory budget (pstt2_set_memory_limit; initial value from the
+ *     environment variable PSTT2_MAX_BYTES, in bytes).  A request past it
+ *     fails with PSTT2_ENOMEM, like a failed hipMalloc.
  *   - Calls marked "async" enqueue work on the context's (or the given) HIP
  *     stream and return before it runs; device-side failures of async work are
  *     reported by the next synchronising call.  Calls marked "sync" block the
@@ -307,7 +318,9 @@ void pstt2_destroy(pstt2_ctx* ctx);
 
 /* Relative error ||X - X~||_F / ||X||_F by entrywise differences over one
  * streaming pass, sums in FP64 (Section 4.1: the error measured for every
- * trial).  cores may point at caller memory.  sync.  Errors: EINVAL, EDEVICE. */
+ * trial).  For X = 0 the result is 0 when X~ = 0 too, and ENUMERIC otherwise.
+ * cores may point at caller memory.  sync.  Errors: EINVAL, ENUMERIC, ENOMEM,
+ * EDEVICE. */
 pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* rel_err,
                       void* hip_stream);
 
@@ -329,6 +342,24 @@ pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream)
  * already enqueued on the stream that produced them, and clear the struct.
  * NULL is ignored. */
 void tt_cores_free(tt_cores* cores);
+
+/* Device-memory budget of the library in bytes (<= 0: none).  Buffers already
+ * allocated are kept; a later request that would take the live total past the
+ * budget fails with PSTT2_ENOMEM.  Process-wide, all devices.  Never fails. */
+pstt2_status pstt2_set_memory_limit(int64_t bytes);
+
+/* Live and peak bytes of device memory held by the library (contexts,
+ * workspaces, cores not yet released) and the budget (-1: none).  Any pointer
+ * may be NULL.  Never fails. */
+pstt2_status pstt2_memory_stats(int64_t* live_bytes, int64_t* peak_bytes, int64_t* limit_bytes);
+
+/* Testing hook for the failure paths: after this call the next `count` kernel
+ * launches of the library's streaming stages (sketch, partial reduction,
+ * partial column, tensor-function columns, two-pass middle core) go ahead and
+ * the one after them is reported as a failed launch (PSTT2_EDEVICE) without
+ * running; then the hook disarms.  count < 0 disarms it.  Host-side only: no
+ * kernel is altered.  Process-wide.  Never fails. */
+pstt2_status pstt2_inject_launch_failure(int64_t count);
 
 /* Message for the last failing call on ctx, or (ctx == NULL) on this thread. */
 const char* pstt2_last_error(const pstt2_ctx* ctx);

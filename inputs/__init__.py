@@ -100,6 +100,18 @@ WORKLOADS = {
     "c4_small": Workload("c4_small", 13, (6, 5, 7, 6, 5, 6, 4, 5), "f32", "tt", tt_rank=4, noise=1e-4,
                          ell=8, rank=4, nslabs=7),
     "c5_small": Workload("c5_small", 14, (20, 17, 19, 21), "f32", "tt", tt_rank=6, noise=1e-3, ell=12, rank=6),
+    # twins of the d=6 FP64 recipe at the benchmark's own sketch parameters (rank 10,
+    # sketch size 20; the tests also set 24, 28, 32): 1716 x 990 middle unfolding,
+    # so 7 (or 4) row blocks with a ragged last one and 62 column chunks, the last
+    # with 14 columns.  The _odd twin has an odd row count (1287 x 770): its columns
+    # are not 16-byte aligned, which selects the kernel's unaligned loads.
+    "c2_twin": Workload("c2_twin", 15, (12, 11, 13, 10, 9, 11), "f64", "tt", tt_rank=10, noise=1e-8,
+                        unit_norm=True, ell=20, rank=10),
+    "c2_twin_odd": Workload("c2_twin_odd", 16, (13, 11, 9, 10, 7, 11), "f64", "tt", tt_rank=10, noise=1e-8,
+                            unit_norm=True, ell=20, rank=10, nslabs=9),
+    # the d=8 FP32 slab recipe at sketch size 24: a 32-wide sketch tile with 8 padding columns
+    "c4_twin24": Workload("c4_twin24", 17, (6, 5, 7, 6, 5, 6, 4, 5), "f32", "tt", tt_rank=8, noise=1e-4,
+                          ell=24, rank=8, nslabs=7),
     # Table 1 (Section 4.3): Hilbert tensors of order 3, 5 and 9 with the printed TT
     # ranks (6.59 GB, 60.8 GB and 38.4 GB in FP64).  Sketch size 32 (the library's
     # largest): oversampling 7 to 20.  The GPU evaluates them inside its kernels.

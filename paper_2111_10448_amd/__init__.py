@@ -22,7 +22,7 @@ from . import _lib as L
 from ._lib import PSTT2Error  # noqa: F401
 
 __all__ = ["PSTT2", "TT", "PSTT2Error", "GaussBumps", "decompose", "tt_error", "tt_error_fn", "tt_reconstruct", "version", "cores_struct",
-           "PSTT2Reconstruct", "pstt2_reconstruct"]
+           "PSTT2Reconstruct", "pstt2_reconstruct", "set_memory_limit", "memory_stats", "inject_launch_failure"]
 
 
 def _torch():
@@ -55,6 +55,23 @@ def _check_dev(t):
 
 def version() -> str:
     return L.lib().pstt2_version().decode()
+
+
+def set_memory_limit(nbytes: int) -> None:
+    """Device-memory budget of the library in bytes (<= 0: none)."""
+    L.check(L.lib().pstt2_set_memory_limit(int(nbytes)))
+
+
+def memory_stats() -> dict:
+    """Live and peak device bytes held by the library, and the budget (-1: none)."""
+    live, peak, lim = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    L.check(L.lib().pstt2_memory_stats(ctypes.byref(live), ctypes.byref(peak), ctypes.byref(lim)))
+    return {"live": live.value, "peak": peak.value, "limit": lim.value}
+
+
+def inject_launch_failure(count: int) -> None:
+    """Testing hook: the launch after the next `count` streaming launches is reported as failed."""
+    L.check(L.lib().pstt2_inject_launch_failure(int(count)))
 
 
 class TT:

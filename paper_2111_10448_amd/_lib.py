@@ -105,10 +105,14 @@ def lib():
     L.pstt2_last_error.restype = ctypes.c_char_p
     L.pstt2_version.argtypes = []
     L.pstt2_version.restype = ctypes.c_char_p
+    L.pstt2_set_memory_limit.argtypes = [i64]
+    L.pstt2_memory_stats.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.pstt2_inject_launch_failure.argtypes = [i64]
     for f in ("pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
               "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_reset", "tt_error", "tt_reconstruct", "tt_cores_copy",
               "pstt2_profile", "pstt2_profile_read", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified",
-              "pstt2_middle_pass_fn"):
+              "pstt2_middle_pass_fn", "pstt2_set_memory_limit", "pstt2_memory_stats",
+              "pstt2_inject_launch_failure"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -125,4 +129,5 @@ EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover"
            "pstt2_middle_pass_fn", "pstt2_vjp",
            "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_profile", "pstt2_profile_read", "pstt2_reset",
            "pstt2_destroy", "tt_error", "tt_reconstruct", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified",
-           "tt_cores_copy", "tt_cores_free", "pstt2_last_error", "pstt2_version"]
+           "tt_cores_copy", "tt_cores_free", "pstt2_last_error", "pstt2_version", "pstt2_set_memory_limit",
+           "pstt2_memory_stats", "pstt2_inject_launch_failure"]

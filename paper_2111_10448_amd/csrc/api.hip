@@ -76,6 +76,11 @@ struct pstt2_ctx {
   double* fn_rec = nullptr;
   int32_t* fn_row = nullptr;
   int32_t* fn_col = nullptr;
+  // launches that added into the sketches; a call that fails after one of them
+  // leaves the sketches partly accumulated, which poisons the context until
+  // pstt2_reset
+  int64_t accum = 0;
+  bool poisoned = false;
   std::string err;
 };
 
@@ -189,6 +194,16 @@ pstt2_status check_range(pstt2_ctx* c, int64_t first, int64_t count) {
   return PSTT2_OK;
 }
 
+constexpr const char* kPoisoned =
+    "an earlier call failed after adding part of its data to the sketches: call pstt2_reset";
+
+// A failed accumulating call that had already added into the sketches
+// (c->accum moved since `before`) poisons the context.
+pstt2_status settle(pstt2_ctx* c, pstt2_status st, int64_t before) {
+  if (st != PSTT2_OK && c->accum != before) c->poisoned = true;
+  return st;
+}
+
 void add_cover(pstt2_ctx* c, int64_t first, int64_t count) {
   if (count == 0) return;
   c->cover[first] = first + count;
@@ -263,8 +278,10 @@ pstt2_status run_slabs(pstt2_ctx* c, const std::vector<Piece>& ps) {
   for (int g = 0; g < pass_groups(c); ++g) {
     double *Yd = nullptr, *Td = nullptr;
     const SketchArgs ga = group_args(c, g, &Yd, &Td);
-    for (const Edge& ed : edges)
+    for (const Edge& ed : edges) {
       HIPCK(c, launch_partial_col(c->dtype, ed.x, ed.r0, ed.r1, ed.col, ga, Yd, Td, c->stream));
+      ++c->accum;
+    }
     const pstt2_status st = launch_segs(c, ga, segs, Yd, Td);
     if (st != PSTT2_OK) return st;
   }
@@ -305,6 +322,7 @@ pstt2_status launch_segs(pstt2_ctx* c, const SketchArgs& ga, const std::vector<S
         c->ev_used.push_back(ev);
       }
       HIPCK(c, launch_reduce(c->prec, a, Yd, Td, c->flag, c->stream));
+      ++c->accum;
     }
   }
   return PSTT2_OK;
@@ -454,13 +472,13 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
     return st;
   };
   hipError_t e;
-  if ((e = hipMalloc(&c->fac, sizeof(double) * off)) != hipSuccess) return bail(e, "hipMalloc(factors)");
+  if ((e = dev_malloc(&c->fac, sizeof(double) * off)) != hipSuccess) return bail(e, "hipMalloc(factors)");
   if ((e = hipMemcpy(c->fac, desc->drm_factors, sizeof(double) * off, hipMemcpyHostToDevice)) != hipSuccess)
     return bail(e, "hipMemcpy(factors)");
-  if ((e = hipMalloc(&c->Y, sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Y)");
-  if ((e = hipMalloc(&c->Tt, sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(T)");
-  if ((e = hipMalloc(&c->flag, sizeof(int))) != hipSuccess) return bail(e, "hipMalloc(flag)");
-  if ((e = hipMalloc(&c->piv_dev, sizeof(int) * (d + 1) * c->ell)) != hipSuccess) return bail(e, "hipMalloc(piv)");
+  if ((e = dev_malloc(&c->Y, sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Y)");
+  if ((e = dev_malloc(&c->Tt, sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(T)");
+  if ((e = dev_malloc(&c->flag, sizeof(int))) != hipSuccess) return bail(e, "hipMalloc(flag)");
+  if ((e = dev_malloc(&c->piv_dev, sizeof(int) * (d + 1) * c->ell)) != hipSuccess) return bail(e, "hipMalloc(piv)");
   {
     // keep stream-ordered workspace in the device's default pool between
     // synchronisations (the recovery and the error pass allocate and free
@@ -472,8 +490,8 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
       (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
   }
-  if ((e = hipMalloc(&c->one, sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(one)");
-  if ((e = hipMalloc(&c->Bk, sizeof(double) * (d + 1) * c->ell * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Bk)");
+  if ((e = dev_malloc(&c->one, sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(one)");
+  if ((e = dev_malloc(&c->Bk, sizeof(double) * (d + 1) * c->ell * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Bk)");
   {
     std::vector<int64_t> ch((size_t)(d + 1) * 2 * d + d, 0);
     for (int k = 1; k <= d - 1; ++k) {
@@ -482,7 +500,7 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
       for (int j = 0; j < r.cnt; ++j) ch[((size_t)k * 2 + 1) * d + j] = r.off[j];
     }
     for (int q = 0; q < d; ++q) ch[(size_t)(d + 1) * 2 * d + q] = c->n[q];
-    if ((e = hipMalloc(&c->chain_dev, sizeof(int64_t) * ch.size())) != hipSuccess) return bail(e, "hipMalloc(chain)");
+    if ((e = dev_malloc(&c->chain_dev, sizeof(int64_t) * ch.size())) != hipSuccess) return bail(e, "hipMalloc(chain)");
     if ((e = hipMemcpy(c->chain_dev, ch.data(), sizeof(int64_t) * ch.size(), hipMemcpyHostToDevice)) != hipSuccess)
       return bail(e, "hipMemcpy(chain)");
   }
@@ -493,11 +511,11 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   c->gi = (int)((c->R + rows_per_block - 1) / rows_per_block);
   c->gj_max = std::max(1, c->ncu * wg_per_cu / c->gi);
   const size_t psz = c->prec == PSTT2_P_F64 ? 8 : 4;
-  if ((e = hipMalloc(&c->ypart, psz * c->gj_max * c->ell * c->R)) != hipSuccess) return bail(e, "hipMalloc(ypart)");
-  if ((e = hipMalloc(&c->tpart, psz * (c->gi * c->ell * c->C + kTPartPad))) != hipSuccess)
+  if ((e = dev_malloc(&c->ypart, psz * c->gj_max * c->ell * c->R)) != hipSuccess) return bail(e, "hipMalloc(ypart)");
+  if ((e = dev_malloc(&c->tpart, psz * (c->gi * c->ell * c->C + kTPartPad))) != hipSuccess)
     return bail(e, "hipMalloc(tpart)");
   c->L4 = (c->ell + 3) / 4 * 4;
-  if ((e = hipMalloc(&c->om_tab, sizeof(double) * c->C * c->L4)) != hipSuccess) return bail(e, "hipMalloc(omega)");
+  if ((e = dev_malloc(&c->om_tab, sizeof(double) * c->C * c->L4)) != hipSuccess) return bail(e, "hipMalloc(omega)");
   if ((e = build_omega_table(base_args(c), c->L4, c->om_tab, c->stream)) != hipSuccess)
     return bail(e, "omega table");
   if (c->indep) {
@@ -505,16 +523,16 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
     c->iY.assign(d + 1, nullptr);
     c->iT.assign(d + 1, nullptr);
     for (int k = 1; k < c->m; ++k) {
-      if ((e = hipMalloc(&c->iom_tab[k], sizeof(double) * c->C * c->L4)) != hipSuccess) return bail(e, "hipMalloc(omega)");
-      if ((e = hipMalloc(&c->iY[k], sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Y)");
+      if ((e = dev_malloc(&c->iom_tab[k], sizeof(double) * c->C * c->L4)) != hipSuccess) return bail(e, "hipMalloc(omega)");
+      if ((e = dev_malloc(&c->iY[k], sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Y)");
       SketchArgs a = base_args(c);
       for (int q = 0; q < PSTT2_MAX_D; ++q) a.omega_off[q] = c->iom_off[k][q];
       if ((e = build_omega_table(a, c->L4, c->iom_tab[k], c->stream)) != hipSuccess) return bail(e, "omega table");
     }
     for (int k = c->m + 1; k <= d - 1; ++k)
-      if ((e = hipMalloc(&c->iT[k], sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(T)");
-    if ((e = hipMalloc(&c->sinkY, sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(sink)");
-    if ((e = hipMalloc(&c->sinkT, sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(sink)");
+      if ((e = dev_malloc(&c->iT[k], sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(T)");
+    if ((e = dev_malloc(&c->sinkY, sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(sink)");
+    if ((e = dev_malloc(&c->sinkT, sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(sink)");
   }
   c->S.assign(d + 1, nullptr);
   c->Tk.assign(d + 1, nullptr);
@@ -542,6 +560,7 @@ pstt2_status pstt2_reset(pstt2_ctx* c) {
     if (t) HIPCK(c, hipMemsetAsync(t, 0, sizeof(double) * c->C * c->ell, c->stream));
   c->cover.clear();
   c->covered = 0;
+  c->poisoned = false;
   return PSTT2_OK;
 }
 
@@ -583,35 +602,37 @@ void pstt2_destroy(pstt2_ctx* c) {
   arena_release(&c->arena, c->stream);
   arena_release(&c->varena, c->stream);
   (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(c->fac);
-  (void)hipFree(c->Y);
-  (void)hipFree(c->Tt);
-  (void)hipFree(c->ypart);
-  (void)hipFree(c->tpart);
-  (void)hipFree(c->flag);
-  (void)hipFree(c->piv_dev);
-  (void)hipFree(c->one);
-  (void)hipFree(c->Bk);
-  (void)hipFree(c->chain_dev);
-  (void)hipFree(c->om_tab);
-  for (double* p : c->iom_tab) (void)hipFree(p);
-  for (double* p : c->iY) (void)hipFree(p);
-  for (double* p : c->iT) (void)hipFree(p);
-  (void)hipFree(c->sinkY);
-  (void)hipFree(c->sinkT);
-  (void)hipFree(c->fn_rec);
-  (void)hipFree(c->fn_row);
-  (void)hipFree(c->fn_col);
+  dev_free(c->fac);
+  dev_free(c->Y);
+  dev_free(c->Tt);
+  dev_free(c->ypart);
+  dev_free(c->tpart);
+  dev_free(c->flag);
+  dev_free(c->piv_dev);
+  dev_free(c->one);
+  dev_free(c->Bk);
+  dev_free(c->chain_dev);
+  dev_free(c->om_tab);
+  for (double* p : c->iom_tab) dev_free(p);
+  for (double* p : c->iY) dev_free(p);
+  for (double* p : c->iT) dev_free(p);
+  dev_free(c->sinkY);
+  dev_free(c->sinkT);
+  dev_free(c->fn_rec);
+  dev_free(c->fn_row);
+  dev_free(c->fn_col);
   delete c;
 }
 
 pstt2_status pstt2_sketch(pstt2_ctx* c, const void* x_dev, int64_t first, int64_t count) {
   if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
   if (!x_dev && count > 0) return fail(c, PSTT2_EINVAL, "null slab pointer");
+  if (c->poisoned) return fail(c, PSTT2_ESTATE, kPoisoned);
   if (c->recovered) return fail(c, PSTT2_ESTATE, "sketch after recover: call pstt2_reset first");
   pstt2_status st = check_range(c, first, count);
   if (st != PSTT2_OK) return st;
-  st = run_slabs(c, {Piece{x_dev, first, count}});
+  const int64_t before = c->accum;
+  st = settle(c, run_slabs(c, {Piece{x_dev, first, count}}), before);
   if (st != PSTT2_OK) return st;
   add_cover(c, first, count);
   return PSTT2_OK;
@@ -659,14 +680,16 @@ pstt2_status pstt2_sketch_fn(pstt2_ctx* c, const pstt2_fn* fn, int64_t first, in
   if (const char* why = fn_invalid(fn)) return fail(c, PSTT2_EINVAL, why);
   if (fn->kind == PSTT2_FN_HILBERT && (c->dtype != PSTT2_F64 || c->prec != PSTT2_P_F64))
     return fail(c, PSTT2_EINVAL, "the Hilbert function needs an FP64 context with FP64 sketches");
+  if (c->poisoned) return fail(c, PSTT2_ESTATE, kPoisoned);
   if (c->recovered) return fail(c, PSTT2_ESTATE, "sketch after recover: call pstt2_reset first");
   if (first % c->R != 0 || count % c->R != 0)
     return fail(c, PSTT2_EINVAL, "first/count must be multiples of n_1...n_m (whole columns of X_m)");
   pstt2_status st = check_range(c, first, count);
   if (st != PSTT2_OK) return st;
   if (count == 0) return PSTT2_OK;
+  const int64_t before = c->accum;
   if (fn->kind == PSTT2_FN_GAUSS) {
-    st = sketch_gauss(c, fn, first, count);
+    st = settle(c, sketch_gauss(c, fn, first, count), before);
     if (st == PSTT2_OK) add_cover(c, first, count);
     return st;
   }
@@ -674,14 +697,14 @@ pstt2_status pstt2_sketch_fn(pstt2_ctx* c, const pstt2_fn* fn, int64_t first, in
   if (!c->fn_rec) {
     double* rec = nullptr;
     int32_t *row_t = nullptr, *col_t = nullptr;
-    e = hipMalloc(&rec, sizeof(double) * hilbert_rec_len(c->n, c->d));
-    if (e == hipSuccess) e = hipMalloc(&row_t, sizeof(int32_t) * c->R);
-    if (e == hipSuccess) e = hipMalloc(&col_t, sizeof(int32_t) * c->C);
+    e = dev_malloc(&rec, sizeof(double) * hilbert_rec_len(c->n, c->d));
+    if (e == hipSuccess) e = dev_malloc(&row_t, sizeof(int32_t) * c->R);
+    if (e == hipSuccess) e = dev_malloc(&col_t, sizeof(int32_t) * c->C);
     if (e == hipSuccess) e = hilbert_tables(c->n, c->d, c->m, c->R, c->C, rec, row_t, col_t, c->stream);
     if (e != hipSuccess) {
-      (void)hipFree(rec);
-      (void)hipFree(row_t);
-      (void)hipFree(col_t);
+      dev_free(rec);
+      dev_free(row_t);
+      dev_free(col_t);
       return hfail(c, e, "Hilbert tables");
     }
     c->fn_rec = rec;
@@ -696,7 +719,7 @@ pstt2_status pstt2_sketch_fn(pstt2_ctx* c, const pstt2_fn* fn, int64_t first, in
     ga.fn_rec = c->fn_rec;
     ga.fn_row = c->fn_row;
     ga.fn_col = c->fn_col;
-    st = launch_segs(c, ga, segs, Yd, Td);
+    st = settle(c, launch_segs(c, ga, segs, Yd, Td), before);
     if (st != PSTT2_OK) return st;
   }
   add_cover(c, first, count);
@@ -707,6 +730,7 @@ pstt2_status pstt2_sketch_slabs(pstt2_ctx* c, int32_t nslabs, const void* const*
                                 const int64_t* counts) {
   if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
   if (nslabs < 0 || (nslabs > 0 && (!xs || !firsts || !counts))) return fail(c, PSTT2_EINVAL, "bad slab arrays");
+  if (c->poisoned) return fail(c, PSTT2_ESTATE, kPoisoned);
   if (c->recovered) return fail(c, PSTT2_ESTATE, "sketch after recover: call pstt2_reset first");
   // validate every slab (including overlaps among themselves) before launching
   std::map<int64_t, int64_t> saved = c->cover;
@@ -723,7 +747,8 @@ pstt2_status pstt2_sketch_slabs(pstt2_ctx* c, int32_t nslabs, const void* const*
     add_cover(c, firsts[s], counts[s]);
     ps.push_back(Piece{xs[s], firsts[s], counts[s]});
   }
-  pstt2_status st = run_slabs(c, ps);
+  const int64_t before = c->accum;
+  pstt2_status st = settle(c, run_slabs(c, ps), before);
   if (st != PSTT2_OK) {
     c->cover = saved;
     c->covered = saved_cov;
@@ -733,6 +758,7 @@ pstt2_status pstt2_sketch_slabs(pstt2_ctx* c, int32_t nslabs, const void* const*
 
 pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   if (!c || !out) return fail(c, PSTT2_EINVAL, "null argument");
+  if (c->poisoned) return fail(c, PSTT2_ESTATE, kPoisoned);
   if (c->covered != c->N) return fail(c, PSTT2_ESTATE, "not every entry of X was streamed exactly once");
   free_recovery(c);
   const int d = c->d, m = c->m, ell = c->ell;
@@ -871,7 +897,7 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   }
   for (int k = 0; k <= d; ++k) tc.r[k] = r[k];
   double* base = nullptr;
-  HIPCK(c, hipMallocAsync((void**)&base, sizeof(double) * tot, s));
+  HIPCK(c, dev_malloc_async((void**)&base, sizeof(double) * tot, s));
   tc.stream = (void*)s;
   int64_t o = 0;
   for (int k = 0; k < d; ++k) {
@@ -1063,6 +1089,7 @@ pstt2_status pstt2_recover_certified(pstt2_ctx* c, const void* x_dev, const pstt
 
 pstt2_status pstt2_middle_pass(pstt2_ctx* c, tt_cores* cores, const void* x_dev, int64_t first, int64_t count) {
   if (!c || !cores) return fail(c, PSTT2_EINVAL, "null argument");
+  if (c->poisoned) return fail(c, PSTT2_ESTATE, kPoisoned);
   if (c->desc.mid != PSTT2_MID_TWOPASS || !c->recovered)
     return fail(c, PSTT2_ESTATE, "middle pass needs a two-pass context after pstt2_recover");
   if (first < 0 || count < 0 || first + count > c->N) return fail(c, PSTT2_EINVAL, "slab range outside the tensor");
@@ -1085,6 +1112,7 @@ pstt2_status pstt2_middle_pass_fn(pstt2_ctx* c, tt_cores* cores, const pstt2_fn*
                                   int64_t count) {
   if (!c || !cores || !fn) return fail(c, PSTT2_EINVAL, "null argument");
   if (const char* why = fn_invalid(fn)) return fail(c, PSTT2_EINVAL, why);
+  if (c->poisoned) return fail(c, PSTT2_ESTATE, kPoisoned);
   if (c->desc.mid != PSTT2_MID_TWOPASS || !c->recovered)
     return fail(c, PSTT2_ESTATE, "middle pass needs a two-pass context after pstt2_recover");
   if (first < 0 || count < 0 || first + count > c->N) return fail(c, PSTT2_EINVAL, "slab range outside the tensor");
@@ -1113,12 +1141,15 @@ pstt2_status pstt2_middle_pass_fn(pstt2_ctx* c, tt_cores* cores, const pstt2_fn*
   void* W = nullptr;
   if (e == hipSuccess) e = ws_alloc(&W, (size_t)esz * c->R * std::min(ncmax, count / c->R), s);
   pstt2_status st = e == hipSuccess ? PSTT2_OK : hfail(c, e, "tensor-function workspace");
+  bool added = false;   // a chunk already added into the middle core
   for (int64_t c0 = first / c->R; st == PSTT2_OK && c0 < (first + count) / c->R; c0 += ncmax) {
     const int64_t nc = std::min(ncmax, (first + count) / c->R - c0);
     e = fn->kind == PSTT2_FN_GAUSS ? gauss_columns(g, c0, nc, c->dtype, W, s)
                                    : hilbert_columns(tabs, row_t, col_t, c->R, c0, nc, c->dtype, W, s);
     st = e == hipSuccess ? pstt2_middle_pass(c, cores, W, c0 * c->R, nc * c->R) : hfail(c, e, "tensor-function columns");
+    if (st == PSTT2_OK) added = true;
   }
+  if (st != PSTT2_OK && added) c->poisoned = true;
   if (W) ws_free(W, s);
   if (col_t) ws_free(col_t, s);
   if (row_t) ws_free(row_t, s);
@@ -1130,6 +1161,7 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
                        void* gx_dev) {
   if (!c || !cores || !gx_dev) return fail(c, PSTT2_EINVAL, "null argument");
   if (!gbar_dev && !x_dev) return fail(c, PSTT2_EINVAL, "x_dev is needed for the fused loss (gbar_dev == NULL)");
+  if (c->poisoned) return fail(c, PSTT2_ESTATE, kPoisoned);
   if (!c->recovered) return fail(c, PSTT2_ESTATE, "pstt2_vjp needs a successful pstt2_recover first");
   if (c->desc.mid == PSTT2_MID_TWOPASS) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the one-pass middle cores only");
   if (c->pstt) return fail(c, PSTT2_ESTATE, "pstt2_vjp covers the two-sided algorithm only");
@@ -1442,10 +1474,25 @@ pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream)
   return PSTT2_OK;
 }
 
+pstt2_status pstt2_set_memory_limit(int64_t bytes) {
+  mem_limit_set(bytes);
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_memory_stats(int64_t* live_bytes, int64_t* peak_bytes, int64_t* limit_bytes) {
+  mem_stats(live_bytes, peak_bytes, limit_bytes);
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_inject_launch_failure(int64_t count) {
+  fault_arm(count);
+  return PSTT2_OK;
+}
+
 void tt_cores_free(tt_cores* t) {
   if (!t) return;
   // one stream-ordered allocation, based at core[0]
-  if (t->owned && t->d >= 1) (void)hipFreeAsync(t->core[0], (hipStream_t)t->stream);
+  if (t->owned && t->d >= 1) dev_free_async(t->core[0], (hipStream_t)t->stream);
   std::memset(t, 0, sizeof(*t));
 }
 

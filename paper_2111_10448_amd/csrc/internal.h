@@ -13,6 +13,25 @@
 
 namespace pstt2 {
 
+// ---- device memory (workspace.hip) ----
+// Every device allocation of the library: counted against the memory budget
+// (pstt2_set_memory_limit / PSTT2_MAX_BYTES) and in the live / peak totals.
+hipError_t dev_malloc_raw(void** p, size_t bytes);
+template <typename T>
+inline hipError_t dev_malloc(T** p, size_t bytes) {
+  return dev_malloc_raw((void**)p, bytes);
+}
+hipError_t dev_malloc_async(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p);
+void dev_free_async(void* p, hipStream_t s);
+void mem_limit_set(int64_t bytes);
+void mem_stats(int64_t* live, int64_t* peak, int64_t* limit);
+// Launch-failure injection (pstt2_inject_launch_failure): after fault_arm(k)
+// the next k launch sites proceed and the one after reports a failure without
+// launching; fault_take() is called at each such site.
+void fault_arm(int64_t count);
+bool fault_take();
+
 // ---- device workspace (workspace.hip) ----
 struct Arena {
   char* base = nullptr;

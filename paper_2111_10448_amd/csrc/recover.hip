@@ -1370,6 +1370,7 @@ hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count
   const int64_t f1 = (first + count + Rprev - 1) / Rprev;
   const unsigned nb = (unsigned)(f1 - f0);
   if (nb == 0) return hipSuccess;
+  if (fault_take()) return hipErrorLaunchFailure;
   if (Cm > 1) {
     const int64_t R = Rprev * nm;
     const int64_t ncol = (first + count + R - 1) / R - first / R;

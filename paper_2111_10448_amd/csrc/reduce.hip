@@ -89,6 +89,7 @@ __global__ void k_reduce_t_join(const double* __restrict__ part, const SketchArg
 }
 
 hipError_t launch_reduce(int prec, const SketchArgs& a, double* Y, double* Tt, int* flag, hipStream_t s) {
+  if (fault_take()) return hipErrorLaunchFailure;
   const int bs = 256;
   const int64_t ny = a.R * a.ell;
   const unsigned gy = (unsigned)std::min<int64_t>((ny + bs - 1) / bs, 4096);

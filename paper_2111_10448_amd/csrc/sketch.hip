@@ -1022,6 +1022,7 @@ static hipError_t launch_t(const SketchArgs& a, bool aligned, hipStream_t s) {
 }
 
 hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s) {
+  if (fault_take()) return hipErrorLaunchFailure;
   if (a.fn && prec != P_F64) return hipErrorInvalidValue;
   // 16-byte loads need every column (and segment start) 16-byte aligned.
   const int esz = prec == P_F64 ? 8 : 4;
@@ -1081,6 +1082,7 @@ __global__ void k_partial_col(const T* __restrict__ x, int64_t r0, int64_t r1, i
 
 hipError_t launch_partial_col(int dtype, const void* x, int64_t r0, int64_t r1, int64_t gcol, const SketchArgs& a,
                               double* Y, double* Tt, hipStream_t s) {
+  if (fault_take()) return hipErrorLaunchFailure;
   if (dtype == PSTT2_F64)
     hipLaunchKernelGGL(k_partial_col<double>, dim3(1), dim3(512), 0, s, (const double*)x, r0, r1, gcol, a, Y, Tt);
   else

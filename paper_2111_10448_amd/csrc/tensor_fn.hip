@@ -146,6 +146,7 @@ int64_t gauss_table_doubles(const int64_t* n, int d, int m, int nterms) {
 
 hipError_t gauss_tables(const int64_t* n, int d, int m, const double* centers_host, int nterms, double gamma,
                         double* buf, GaussTabs* out, hipStream_t s) {
+  if (fault_take()) return hipErrorLaunchFailure;
   Modes M;
   for (int q = 0; q < PSTT2_MAX_D; ++q) M.n[q] = q < d ? n[q] : 1;
   int64_t R = 1, C = 1;
@@ -191,6 +192,7 @@ int64_t gauss_chunk_cols(const GaussTabs& g, int elem_bytes) {
 
 hipError_t gauss_columns(const GaussTabs& g, int64_t c0, int64_t nc, int dtype, void* W, hipStream_t s) {
   if (nc <= 0) return hipSuccess;
+  if (fault_take()) return hipErrorLaunchFailure;
   const dim3 grid((unsigned)((g.R + 2 * kGaussBlock - 1) / (2 * kGaussBlock)),
                   (unsigned)((nc + kGaussCols - 1) / kGaussCols));
   if (dtype == PSTT2_F64)
@@ -203,6 +205,7 @@ hipError_t gauss_columns(const GaussTabs& g, int64_t c0, int64_t nc, int dtype, 
 hipError_t hilbert_columns(const double* rec, const int32_t* row_t, const int32_t* col_t, int64_t R, int64_t c0,
                            int64_t nc, int dtype, void* W, hipStream_t s) {
   if (nc <= 0) return hipSuccess;
+  if (fault_take()) return hipErrorLaunchFailure;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((R * nc + 255) / 256, 65536));
   if (dtype == PSTT2_F64)
     hipLaunchKernelGGL(k_hilbert_cols<double>, dim3(g), dim3(256), 0, s, rec, row_t, col_t, R, c0, nc, (double*)W);

@@ -1,0 +1,222 @@
+"""Failure paths through the C ABI, forced from the host so every kernel that
+runs still runs normally: the device-memory budget (ENOMEM from every
+allocating stage, nothing leaked, outputs untouched), launch failures injected
+between the launches of one call (the context is poisoned only if part of the
+data had already been added, and a retry after pstt2_reset is not
+double-counted), and the defined result for X = 0."""
+import numpy as np
+import pytest
+
+import inputs
+from oracle import tt_sketch as O
+
+from gpu_common import compare, gpu_run, oracle_run, say, setup
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _clean_limits():
+    import paper_2111_10448_amd as P
+    P.set_memory_limit(0)
+    P.inject_launch_failure(-1)
+    yield
+    P.set_memory_limit(0)
+    P.inject_launch_failure(-1)
+
+
+def _status(exc_info):
+    return exc_info.value.status
+
+
+def test_memory_budget_create_and_recover():
+    import torch
+    import paper_2111_10448_amd as P
+    from paper_2111_10448_amd import _lib as L
+    w = inputs.WORKLOADS["c2_small"]
+    say("[gpu] memory budget: create, recover")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    xg = torch.from_numpy(x).cuda()
+    torch.cuda.synchronize()
+    live0 = P.memory_stats()["live"]
+    # create needs the sketches and partials: refused, nothing kept
+    P.set_memory_limit(live0 + 4096)
+    with pytest.raises(P.PSTT2Error) as e:
+        P.PSTT2(w.n, w.ell, fac, ranks=w.ranks())
+    assert _status(e) == L.ENOMEM
+    assert P.memory_stats()["live"] == live0
+    P.set_memory_limit(0)
+    ctx = P.PSTT2(w.n, w.ell, fac, ranks=w.ranks())
+    ctx.sketch(xg)        # the pass allocates nothing
+    # the recovery's workspace does not fit: ENOMEM, the sketches are kept
+    P.set_memory_limit(P.memory_stats()["live"])
+    with pytest.raises(P.PSTT2Error) as e:
+        ctx.recover()
+    assert _status(e) == L.ENOMEM
+    P.set_memory_limit(0)
+    tt = ctx.recover()
+    out = compare(ctx, tt, xg, x, w, ref, "f64", check_cores=True)
+    say(f"    after the refused recovery {out}")
+    tt.free()
+    ctx.close()
+    torch.cuda.synchronize()
+    assert P.memory_stats()["live"] <= live0 + (1 << 20)   # at most the error pass's kept arena
+
+
+def test_memory_budget_gauss_sketch():
+    """The Gaussian-bump path refused at its table and at its column workspace, then retried."""
+    import torch
+    import paper_2111_10448_amd as P
+    from paper_2111_10448_amd import _lib as L
+    w = inputs.WORKLOADS["gb_small3"]
+    say("[gpu] memory budget: Gaussian-bump sketch")
+    x = inputs.make_tensor(w)
+    psi, om = inputs.drm_factors(w)
+    fac = inputs.pack_factors(psi, om, w.d)
+    ref = oracle_run(x, w, psi, om)
+    fn = P.GaussBumps(inputs.gauss_centers(w), w.gamma)
+    ctx = P.PSTT2(w.n, w.ell, fac, ranks=w.ranks())
+    torch.cuda.synchronize()
+    live = P.memory_stats()["live"]
+    m = O.middle_index(w.d)
+    R = int(np.prod(w.n[:m]))
+    tab_bytes = 8 * (w.terms * (w.d + w.n[0] + R // w.n[0] + x.size // R + 32) + 4096)
+    for limit in (live + 1024, live + tab_bytes):   # tables refused; then the column workspace
+        P.set_memory_limit(limit)
+        with pytest.raises(P.PSTT2Error) as e:
+            ctx.sketch_fn(fn)
+        assert _status(e) == L.ENOMEM
+    P.set_memory_limit(0)
+    ctx.sketch_fn(fn)     # nothing was added by the refused calls
+    tt = ctx.recover()
+    xg = torch.from_numpy(x).cuda()
+    out = compare(ctx, tt, xg, x, w, ref, "f64")
+    say(f"    {out}")
+    tt.free()
+    ctx.close()
+
+
+def test_injected_failure_before_any_addition_is_retryable():
+    import torch
+    import paper_2111_10448_amd as P
+    from paper_2111_10448_amd import _lib as L
+    w = inputs.WORKLOADS["c4_small"]
+    say("[gpu] injected launch failure at the first launch")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    xg = torch.from_numpy(x).cuda()
+    bounds = inputs.slab_bounds(x.size, w.n[0], w.nslabs)
+    ctx = P.PSTT2(w.n, w.ell, fac, dtype="f32", prec="f32", ranks=w.ranks())
+    P.inject_launch_failure(0)
+    with pytest.raises(P.PSTT2Error) as e:
+        ctx.sketch_slabs([xg[f:f + c] for f, c in bounds], [f for f, _ in bounds])
+    assert _status(e) == L.EDEVICE
+    # nothing was added and the coverage was rolled back: the same call again
+    ctx.sketch_slabs([xg[f:f + c] for f, c in bounds], [f for f, _ in bounds])
+    tt = ctx.recover()
+    out = compare(ctx, tt, xg, x, w, ref, "f32")
+    say(f"    {out}")
+    tt.free()
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", ["slabs", "hilbert_groups", "gauss_tables"])
+def test_injected_failure_after_an_addition_poisons(case):
+    """A call that fails after part of its data was added leaves the context
+    poisoned (ESTATE) until pstt2_reset; the retry after the reset matches the oracle."""
+    import dataclasses
+    import torch
+    import paper_2111_10448_amd as P
+    from paper_2111_10448_amd import _lib as L
+    say(f"[gpu] injected launch failure mid-call: {case}")
+    if case == "slabs":
+        # slab edges cut columns: the partial-column launch adds first, the next launch fails
+        w = inputs.WORKLOADS["c4_small"]
+        x, psi, omega, fac = setup(w)
+        ref = oracle_run(x, w, psi, omega)
+        xg = torch.from_numpy(x).cuda()
+        bounds = inputs.slab_bounds(x.size, w.n[0], w.nslabs)
+        ctx = P.PSTT2(w.n, w.ell, fac, dtype="f32", prec="f32", ranks=w.ranks())
+
+        def run():
+            ctx.sketch_slabs([xg[f:f + c] for f, c in bounds], [f for f, _ in bounds])
+        prec, fail_after = "f32", 1
+    elif case == "hilbert_groups":
+        # independent factors: one sketch + reduction per pass group; the second group's sketch fails
+        w = inputs.WORKLOADS["t1_small5"]
+        x = inputs.make_tensor(w)
+        psi, omega = inputs.drm_factors_independent(w)
+        fac = inputs.pack_factors_independent(psi, omega, w.d)
+        ref = oracle_run(x, w, psi, omega, drm="independent")
+        xg = torch.from_numpy(x).cuda()
+        ctx = P.PSTT2(w.n, w.ell, fac, ranks=w.ranks(), drm="independent")
+
+        def run():
+            ctx.sketch_fn("hilbert")
+        prec, fail_after = "f64", 2
+    else:
+        # Gaussian bumps over two calls: the second call's table set-up fails
+        # (nothing of it was added: not poisoned), then the retry completes
+        w = inputs.WORKLOADS["gb_small3"]
+        x = inputs.make_tensor(w)
+        psi, omega = inputs.drm_factors(w)
+        fac = inputs.pack_factors(psi, omega, w.d)
+        ref = oracle_run(x, w, psi, omega)
+        xg = torch.from_numpy(x).cuda()
+        fn = P.GaussBumps(inputs.gauss_centers(w), w.gamma)
+        ctx = P.PSTT2(w.n, w.ell, fac, ranks=w.ranks())
+        m = O.middle_index(w.d)
+        R = int(np.prod(w.n[:m]))
+        half = (x.size // R // 2) * R
+        ctx.sketch_fn(fn, 0, half)
+        P.inject_launch_failure(0)
+        with pytest.raises(P.PSTT2Error) as e:
+            ctx.sketch_fn(fn, half)
+        assert _status(e) == L.EDEVICE
+        ctx.sketch_fn(fn, half)
+        tt = ctx.recover()
+        out = compare(ctx, tt, xg, x, w, ref, "f64")
+        say(f"    {out}")
+        tt.free()
+        ctx.close()
+        return
+    P.inject_launch_failure(fail_after)
+    with pytest.raises(P.PSTT2Error) as e:
+        run()
+    assert _status(e) == L.EDEVICE
+    for call in (run, ctx.recover):
+        with pytest.raises(P.PSTT2Error) as e:
+            call()
+        assert _status(e) == L.ESTATE
+    ctx.reset()
+    run()
+    tt = ctx.recover()
+    out = compare(ctx, tt, xg, x, w, ref, prec)
+    say(f"    after reset {out}")
+    tt.free()
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", ["ranks", "eps"])
+def test_zero_tensor(mode):
+    """X = 0: recovery succeeds (the sketches are zero, the bases are unit vectors),
+    X~ is exactly zero like the oracle's, and the relative error is defined as 0."""
+    import torch
+    import paper_2111_10448_amd as P
+    w = inputs.WORKLOADS["c1"]
+    say(f"[gpu] zero tensor ({mode})")
+    x = np.zeros(w.numel)
+    psi, omega = inputs.drm_factors(w)
+    fac = inputs.pack_factors(psi, omega, w.d)
+    kw = {"ranks": w.ranks()} if mode == "ranks" else {"eps": 1e-3, "rmax": 4}
+    ref = O.pstt2(x, w.n, O.NestedKR(psi, omega), **kw)
+    xg = torch.from_numpy(x).cuda()
+    with P.PSTT2(w.n, w.ell, fac, **kw) as ctx:
+        ctx.sketch(xg)
+        tt = ctx.recover()
+        assert tt.ranks == [1] + list(ref["ranks"]) + [1]
+        xt = tt.reconstruct().cpu().numpy()
+        assert not np.any(xt) and not np.any(O.tt_full(ref["cores"]))
+        assert tt.error(xg) == 0.0
+        tt.free()

@@ -1,8 +1,8 @@
 """Full-size GPU checks in the launch configuration the benchmark times.
 
-The oracle cannot run the whole decomposition of a 1e9-entry tensor in a test,
-so these compare sampled sketch entries computed one by one from their
-definition (Y_R(i, c) = sum_j X_m(i, j) Omega_m(j, c), T_m(a, j) =
+The noisy d=6 tensor runs through the oracle on the host and is compared with
+it split by split.  The others compare sampled sketch entries computed one by one
+from their definition (Y_R(i, c) = sum_j X_m(i, j) Omega_m(j, c), T_m(a, j) =
 sum_i Psi_m(i, a) X_m(i, j), Khatri-Rao DRM columns built with np.kron), and
 properties that hold at any size: exact recovery of the noiseless exact-rank
 tensor, the error level of the noisy one, and ranks.
@@ -119,14 +119,62 @@ def test_c2_exact_rank_full_size():
     assert err < 1e-11
 
 
-def test_c2_noisy_full_size():
-    """d=6, n=32 with N(0, 1e-8) noise: sketches entrywise, error at the noise level."""
+def test_c2_noisy_full_size_against_oracle():
+    """d=6, n=32 with N(0, 1e-8) noise (8.6 GB FP64), the benchmark's launch: the oracle's
+    PSTT2-onepass runs on the same tensor on the host, and every sketch of every split,
+    B_k, pivots, ranks, the gauge-fixed FP64 cores and the error are compared with it."""
+    import time
+    import torch
+    import paper_2111_10448_amd as P
     w = inputs.WORKLOADS["c2"]
-    say("[gpu] full size c2")
-    x, psi, omega, y, t, err, ranks = _run(w, "f64")
-    worst = _check_sampled(x, w, psi, omega, y, t, 16, 1e-13, 2)
+    say("[gpu] full size c2 against the oracle")
+    x = _tensor(w)
+    psi, omega = inputs.drm_factors(w)
+    fac = inputs.pack_factors(psi, omega, w.d)
+    d, m = w.d, O.middle_index(w.d)
+    xg = torch.from_numpy(x).cuda()
+    ctx = P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", ranks=w.ranks())
+    ctx.sketch(xg)
+    tt = ctx.recover()
+    got = {"S": {k: ctx.get_sketch(0, k) for k in range(1, m + 1)},
+           "T": {k: ctx.get_sketch(1, k) for k in range(m, d)},
+           "B": {k: ctx.get_sketch(2, k) for k in range(1, d)},
+           "piv": {k: ctx.pivots(k) for k in range(1, d)}}
+    cores = tt.cores_numpy()
+    err = tt.error(xg)
+    ranks = tt.ranks
+    tt.free()
+    ctx.close()
+    del xg
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    drm = O.NestedKR(psi, omega)
+    ref = O.pstt2(x, w.n, drm, ranks=w.ranks())
+    e_ref = O.tt_error(x, ref["cores"])
+    say(f"    oracle on the host: {time.perf_counter() - t0:.1f} s")
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    worst = {"Y": rel(got["S"][m], ref["Y"])}
+    for k in range(1, m):
+        worst[f"S{k}"] = rel(got["S"][k], ref["S"][k])
+    for k in range(m, d):
+        worst[f"T{k}"] = rel(got["T"][k], ref["T"][k].T)
+    # B_k from the oracle's own one-sided sketches and the dense Khatri-Rao DRMs
+    for k in range(1, d):
+        b = drm.psi_dense(k).T @ ref["S"][k] if k < m else ref["T"][k] @ drm.omega_dense(k, d)
+        worst[f"B{k}"] = rel(got["B"][k], b)
+    assert max(worst.values()) < 1e-12, worst
+    assert ranks == [1] + list(ref["ranks"]) + [1]
+    for k in range(1, d):
+        rk = ref["ranks"][k - 1]
+        assert list(got["piv"][k][:rk]) == list(ref["piv"][k][:rk]), k
+    dg = [rel(a, b) for a, b in zip(cores, ref["cores"])]
     noise_rel = w.noise * np.sqrt(x.size) / np.linalg.norm(x)
-    say(f"    sampled sketch max rel {worst:.2e}, tt_error {err:.3e} (noise level {noise_rel:.3e})")
+    say(f"    sketches {max(worst.values()):.2e}, cores {max(dg):.2e}, tt_error {err:.6e} "
+        f"(oracle {e_ref:.6e}, noise level {noise_rel:.3e})")
+    assert max(dg) < 1e-8, dg
+    assert abs(err - e_ref) <= 1e-10 * 1.01 + 1e-6 * e_ref, (err, e_ref)
     # the projection of the noise is the floor; the one-pass sketch stays within
     # a small factor of it (Theorem 4 with p = r)
     assert noise_rel * 0.5 < err < 10 * noise_rel

@@ -246,3 +246,79 @@ def test_tt_error_and_reconstruct_on_given_cores():
     ref32 = np.linalg.norm((xt + noise).astype(np.float32).astype(np.float64) - xt) / \
         np.linalg.norm((xt + noise).astype(np.float32).astype(np.float64))
     assert abs(e32 - ref32) < 1e-6 * ref32
+
+
+@pytest.mark.parametrize("ell", [20, 24, 28, 32])
+@pytest.mark.parametrize("name", ["c2_twin", "c2_twin_odd"])
+def test_fp64_benchmark_sketch_sizes(name, ell):
+    """The FP64 kernel at every sketch size the FP64 workloads use (20 = the d=6 benchmark,
+    its 16-wide plus 4-wide tile mix; 24 and 28 mix 16 + 8 and 16 + 12; 32 = the 8-wave
+    workgroup of the memory path), element by element against the oracle: every sketch,
+    B_k, pivots, ranks, gauge-fixed FP64 cores, X~ and the error.  c2_twin streams the
+    whole tensor (one segment, 16-byte loads); c2_twin_odd has an odd row count (scalar
+    loads) and arrives in 9 scrambled slabs in one launch (multi-segment launch, slab
+    edges through the partial-column kernel)."""
+    import dataclasses
+    w = dataclasses.replace(inputs.WORKLOADS[name], ell=ell)
+    say(f"[gpu] FP64 parity {w.name} n={w.n} ell={ell} slabs={w.nslabs}")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    slabs = None
+    if w.nslabs > 1:
+        slabs = inputs.slab_bounds(x.size, w.n[0], w.nslabs)
+        order = np.random.default_rng(ell).permutation(len(slabs))
+        slabs = [slabs[i] for i in order]
+    ctx, tt, xg = gpu_run(x, w, fac, "f64", slabs=slabs, batched=slabs is not None)
+    out = compare(ctx, tt, xg, x, w, ref, "f64", check_cores=True)
+    say(f"    {out}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,prec", [("c4_twin24", "f32"), ("c4_twin24", "bf16x3"), ("c3_small", "bf16")])
+def test_fp32_family_padded_sketch_size(name, prec):
+    """Sketch size 24 in the FP32-family kernels: a 32-wide sketch tile whose last 8
+    columns are padding; 7 slabs in scrambled order, one launch.  Plain BF16 runs on
+    the smooth 1/sum twin (the workload it is benchmarked on) with the oracle's
+    ranks: on the random-TT twin its rounding (2^-9 per operand) is amplified past
+    the 5e-3 X~ tolerance by the spread of the sketch's singular values."""
+    import dataclasses
+    w = dataclasses.replace(inputs.WORKLOADS[name], ell=24, nslabs=7)
+    say(f"[gpu] padded sketch size {w.name} ell={w.ell} prec={prec}")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    slabs = inputs.slab_bounds(x.size, w.n[0], w.nslabs)
+    order = np.random.default_rng(24).permutation(len(slabs))
+    slabs = [slabs[i] for i in order]
+    ranks = ref["ranks"] if prec == "bf16" else None
+    ctx, tt, xg = gpu_run(x, w, fac, prec, slabs=slabs, batched=True, ranks=ranks)
+    out = compare(ctx, tt, xg, x, w, ref, prec, check_pivots=(prec != "bf16"))
+    say(f"    {out}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("rank,ell", [(20, 24), (28, 32)])
+def test_twopass_wide_ranks_split_pass(rank, ell):
+    """Two-pass middle core with middle ranks 20 and 28 (the 24- and 32-wide register
+    tiles of the pair-load Z pass: FP64, even row count, whole columns), the second pass
+    given as two whole-column halves, the second half first, so the later launch starts
+    at a column offset."""
+    import dataclasses
+    import torch
+    w = dataclasses.replace(inputs.WORKLOADS["c2_twin"], tt_rank=rank, rank=rank, ell=ell)
+    say(f"[gpu] two-pass ranks {rank} ell {ell} {w.n}")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega, middle="twopass")
+    import paper_2111_10448_amd as P
+    xg = torch.from_numpy(x).cuda()
+    ctx = P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", ranks=w.ranks(), mid="twopass")
+    ctx.sketch(xg)
+    tt = ctx.recover()
+    m = O.middle_index(w.d)
+    R = int(np.prod(w.n[:m]))
+    half = (x.size // R // 2) * R
+    ctx.middle_pass(tt, xg[half:], half)
+    ctx.middle_pass(tt, xg[:half], 0)
+    torch.cuda.synchronize()
+    out = compare(ctx, tt, xg, x, w, ref, "f64", check_cores=True)
+    say(f"    {out}")
+    ctx.close()
