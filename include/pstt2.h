@@ -324,6 +324,26 @@ void pstt2_destroy(pstt2_ctx* ctx);
 pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* rel_err,
                       void* hip_stream);
 
+/* tt_error without allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same pass and the same sums in the same order as tt_error,
+ * but every temporary (interface tables, padded right interface, workgroup
+ * partials) lives in one static device buffer of PSTT2_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device it runs on until the process ends; no
+ * allocation of any kind is made.  err_dev is caller-owned device memory of
+ * three doubles: err_dev[0] = ||X - X~||_F / ||X||_F (0 for X = 0 = X~, +inf
+ * for X = 0 != X~), err_dev[1] = sum (x - x~)^2, err_dev[2] = sum x^2.  async:
+ * the result is in err_dev once the stream passes the work; nothing is
+ * synchronised.  Every call on a device shares that device's buffer (nothing
+ * in it needs clearing, each call writes what it reads), so calls that overlap
+ * on one device, on any streams, race: serialise them.  Errors: EINVAL
+ * (cores, null pointers, dtype), ENOMEM (the pass would need more than
+ * PSTT2_NOALLOC_SCRATCH_BYTES: about 8 (R_m r_m + 16 C_m) bytes at the
+ * middle split, e.g. 10 MB for d = 6, n = 32, rank 10), EDEVICE. */
+#define PSTT2_NOALLOC_SCRATCH_BYTES (64LL << 20)
+pstt2_status tt_error_noalloc(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* err_dev,
+                              void* hip_stream);
+
 /* The same for the tensor fn (see pstt2_fn), evaluated in FP64 instead of read
  * from memory; the mode sizes are the cores'.  sync.
  * Errors: EINVAL, ENUMERIC, ENOMEM, EDEVICE. */

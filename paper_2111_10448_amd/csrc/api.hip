@@ -1536,6 +1536,24 @@ pstt2_status tt_error(const tt_cores* cores, const void* x_dev, pstt2_dtype dtyp
   return error_common(cores, x_dev, dtype, nullptr, rel_err, hip_stream);
 }
 
+pstt2_status tt_error_noalloc(const tt_cores* cores, const void* x_dev, pstt2_dtype dtype, double* err_dev,
+                              void* hip_stream) {
+  pstt2_status st = check_cores(cores);
+  if (st != PSTT2_OK) return st;
+  if (!x_dev || !err_dev) return fail(nullptr, PSTT2_EINVAL, "null argument");
+  if (dtype != PSTT2_F64 && dtype != PSTT2_F32) return fail(nullptr, PSTT2_EINVAL, "bad dtype");
+  const int64_t need = tt_error_scratch_bytes(cores);
+  if (need > PSTT2_NOALLOC_SCRATCH_BYTES) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "tt_error_noalloc needs %lld bytes of scratch; the static buffer holds %lld",
+                  (long long)need, (long long)PSTT2_NOALLOC_SCRATCH_BYTES);
+    return fail(nullptr, PSTT2_ENOMEM, msg);
+  }
+  const hipError_t e = tt_error_noalloc_run(cores, x_dev, dtype, err_dev, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hfail(nullptr, e, "tt_error_noalloc");
+  return PSTT2_OK;
+}
+
 pstt2_status tt_error_fn(const tt_cores* cores, const pstt2_fn* fn, double* rel_err, void* hip_stream) {
   pstt2_status st = check_cores(cores);
   if (st != PSTT2_OK) return st;

@@ -239,6 +239,11 @@ hipError_t adj_out(int dtype, const SketchArgs& g, int prec, const double* Yb, c
 
 // TT evaluation (tt_eval.hip).
 hipError_t tt_interfaces(const tt_cores* c, int split, double** L, double** Rt, double** base, hipStream_t s);
+// Bytes of the static scratch the allocation-free error pass of these cores needs.
+int64_t tt_error_scratch_bytes(const tt_cores* c);
+// The error pass in the static scratch; err_dev receives (relative error,
+// sum (x - x~)^2, sum x^2).  async.
+hipError_t tt_error_noalloc_run(const tt_cores* c, const void* x, int dtype, double* err_dev, hipStream_t s);
 }  // namespace pstt2
 
 // Thread-local error text for calls without a context.

@@ -10,6 +10,7 @@
 // loads).  Squared differences are summed in FP64, never through
 // ||X||^2 - 2<X, X~> + ||X~||^2, which cancels.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 
@@ -59,12 +60,9 @@ __global__ void k_right_iface(const double* __restrict__ G, int rp, int nk, int 
   }
 }
 
-// Interfaces in one stream-ordered allocation: *base is returned for a single
-// hipFreeAsync on the same stream; *Lout (R_split x r_split) and *Rout
-// (r_split x C_split) point into it.
-hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** Rout, double** base, hipStream_t s) {
+// Doubles of every intermediate interface level at this split.
+static int64_t tt_interfaces_doubles(const tt_cores* c, int split) {
   const int d = c->d;
-  // sizes of every intermediate level
   int64_t tot = 0, Rp = c->n[0];
   tot += Rp * c->r[1];
   for (int k = 1; k < split; ++k) {
@@ -77,12 +75,16 @@ hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** R
     Ck *= c->n[k];
     tot += Ck * c->r[k];
   }
-  double* ws = nullptr;
-  hipError_t e = ws_alloc((void**)&ws, sizeof(double) * tot, s);
-  if (e != hipSuccess) return e;
-  *base = ws;
+  return tot;
+}
+
+// The interface levels built into ws (tt_interfaces_doubles of them); *Lout
+// (R_split x r_split) and *Rout (r_split x C_split) point into ws or at a core.
+static hipError_t tt_interfaces_in(const tt_cores* c, int split, double* ws, double** Lout, double** Rout,
+                                   hipStream_t s) {
+  const int d = c->d;
   double* cur = ws;
-  Rp = c->n[0];
+  int64_t Rp = c->n[0];
   double* L = c->core[0];   // L_1 = G_1 (read only)
   for (int k = 1; k < split; ++k) {
     const int nk = (int)c->n[k];
@@ -93,7 +95,7 @@ hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** R
     L = Ln;
     Rp *= nk;
   }
-  Ck = c->n[d - 1];
+  int64_t Ck = c->n[d - 1];
   double* R = c->core[d - 1];   // Rt_d = G_d (read only)
   for (int k = d - 2; k >= split; --k) {
     const int nk = (int)c->n[k];
@@ -107,6 +109,16 @@ hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** R
   *Lout = L;
   *Rout = R;
   return hipGetLastError();
+}
+
+// Interfaces in one stream-ordered workspace allocation: *base is returned for
+// a single ws_free on the same stream.
+hipError_t tt_interfaces(const tt_cores* c, int split, double** Lout, double** Rout, double** base, hipStream_t s) {
+  double* ws = nullptr;
+  hipError_t e = ws_alloc((void**)&ws, sizeof(double) * tt_interfaces_doubles(c, split), s);
+  if (e != hipSuccess) return e;
+  *base = ws;
+  return tt_interfaces_in(c, split, ws, Lout, Rout, s);
 }
 
 // ---- tt_error: one streaming pass over X ----
@@ -217,7 +229,11 @@ __global__ __launch_bounds__(256) void k_tt_error(const T* __restrict__ x, int64
 }
 
 // Fixed-order sum of nb (e2, x2) pairs: strided per thread, then a tree.
-__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int nb, double* __restrict__ out) {
+// out[0..1] = (e2, x2); with rel, out[0..2] = (relative error, e2, x2), the
+// relative error by the host rule (sqrt(e2 / x2); for x2 = 0: 0 if e2 = 0,
+// else +inf).
+__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int nb, double* __restrict__ out,
+                                                   bool rel) {
   __shared__ double sa[256], sb[256];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nb; i += 256) {
@@ -235,8 +251,10 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ pa
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = sa[0];
-    out[1] = sb[0];
+    const int o = rel ? 1 : 0;
+    out[o] = sa[0];
+    out[o + 1] = sb[0];
+    if (rel) out[0] = sb[0] > 0.0 ? sqrt(sa[0] / sb[0]) : (sa[0] > 0.0 ? INFINITY : 0.0);
   }
 }
 
@@ -277,47 +295,122 @@ static hipError_t launch_err(const T* x, int64_t R, int64_t C, int r, const doub
               : launch_err_p<T, false, false>(x, R, C, r, L, Rt, gi, gj, part, none, s);
 }
 
+// Geometry and scratch of one error pass over X_m at the middle split.
+struct ErrPlan {
+  int split, r, RK, gi, gj;
+  int64_t R, C;
+  int64_t n_iface, n_part, n_rp;   // doubles of the interfaces, the partials (+ the 3 results), padded Rt
+};
+
+static ErrPlan err_plan(const tt_cores* c) {
+  ErrPlan p;
+  const int d = c->d;
+  p.split = (d + 1) / 2;
+  p.R = p.C = 1;
+  for (int k = 0; k < p.split; ++k) p.R *= c->n[k];
+  for (int k = p.split; k < d; ++k) p.C *= c->n[k];
+  p.r = c->r[p.split];
+  p.RK = rk_slot(p.r);
+  p.gi = (int)((p.R + 511) / 512);
+  p.gj = (int)std::max<int64_t>(1, std::min<int64_t>(p.C, (4096 + p.gi - 1) / p.gi));
+  p.n_iface = tt_interfaces_doubles(c, p.split);
+  p.n_part = 2 * (int64_t)p.gi * p.gj + 3;
+  p.n_rp = (int64_t)p.RK * p.C;
+  return p;
+}
+
+// The pass itself into caller-provided scratch: interfaces, padded Rt, the
+// workgroup partials and their fixed-order sum at out: (e2, x2), or with rel
+// (relative error, e2, x2).
+// Every scratch entry is written before it is read: nothing needs clearing.
+static hipError_t err_launch(const tt_cores* c, const ErrPlan& p, const void* x, int dtype, const FnTabs& fn,
+                             double* iface, double* part, double* Rp, double* out, bool rel, hipStream_t s) {
+  double *L = nullptr, *Rt = nullptr;
+  hipError_t e = tt_interfaces_in(c, p.split, iface, &L, &Rt, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pad_rt, dim3(grid_for(p.n_rp, 256)), dim3(256), 0, s, Rt, p.r, p.RK, p.C, Rp);
+  if (fn.rec) e = launch_err_p<double, false, true>(nullptr, p.R, p.C, p.r, L, Rp, p.gi, p.gj, part, fn, s);
+  else if (dtype == PSTT2_F64) e = launch_err((const double*)x, p.R, p.C, p.r, L, Rp, p.gi, p.gj, part, s);
+  else e = launch_err((const float*)x, p.R, p.C, p.r, L, Rp, p.gi, p.gj, part, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, p.gi * p.gj, out, rel);
+  return hipGetLastError();
+}
+
 // x == nullptr: the Hilbert tensor (fn != 0), evaluated from its index tables
 hipError_t tt_error_run(const tt_cores* c, const void* x, int dtype, double* e2x2, hipStream_t s, int fn) {
-  const int d = c->d;
-  const int split = (d + 1) / 2;
-  double *L = nullptr, *Rt = nullptr, *ifb = nullptr;
-  hipError_t e = tt_interfaces(c, split, &L, &Rt, &ifb, s);
-  if (e != hipSuccess) return e;
-  int64_t R = 1, C = 1;
-  for (int k = 0; k < split; ++k) R *= c->n[k];
-  for (int k = split; k < d; ++k) C *= c->n[k];
-  const int r = c->r[split];
-  const int gi = (int)((R + 511) / 512);
-  const int gj = (int)std::max<int64_t>(1, std::min<int64_t>(C, (4096 + gi - 1) / gi));
-  double *part = nullptr, *Rp = nullptr, *rec = nullptr;
+  const ErrPlan p = err_plan(c);
+  double *iface = nullptr, *part = nullptr, *Rp = nullptr, *rec = nullptr;
   int32_t *row_t = nullptr, *col_t = nullptr;
-  const int RK = rk_slot(r);
-  e = ws_alloc((void**)&part, sizeof(double) * 2 * ((int64_t)gi * gj + 1), s);
-  if (e == hipSuccess) e = ws_alloc((void**)&Rp, sizeof(double) * RK * C, s);
+  hipError_t e = ws_alloc((void**)&iface, sizeof(double) * std::max<int64_t>(p.n_iface, 1), s);
+  if (e == hipSuccess) e = ws_alloc((void**)&part, sizeof(double) * p.n_part, s);
+  if (e == hipSuccess) e = ws_alloc((void**)&Rp, sizeof(double) * p.n_rp, s);
   if (fn) {
-    if (e == hipSuccess) e = ws_alloc((void**)&rec, sizeof(double) * hilbert_rec_len(c->n, d), s);
-    if (e == hipSuccess) e = ws_alloc((void**)&row_t, sizeof(int32_t) * R, s);
-    if (e == hipSuccess) e = ws_alloc((void**)&col_t, sizeof(int32_t) * C, s);
-    if (e == hipSuccess) e = hilbert_tables(c->n, d, split, R, C, rec, row_t, col_t, s);
+    if (e == hipSuccess) e = ws_alloc((void**)&rec, sizeof(double) * hilbert_rec_len(c->n, c->d), s);
+    if (e == hipSuccess) e = ws_alloc((void**)&row_t, sizeof(int32_t) * p.R, s);
+    if (e == hipSuccess) e = ws_alloc((void**)&col_t, sizeof(int32_t) * p.C, s);
+    if (e == hipSuccess) e = hilbert_tables(c->n, c->d, p.split, p.R, p.C, rec, row_t, col_t, s);
   }
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pad_rt, dim3(grid_for(RK * C, 256)), dim3(256), 0, s, Rt, r, RK, C, Rp);
-  if (fn) e = launch_err_p<double, false, true>(nullptr, R, C, r, L, Rp, gi, gj, part, FnTabs{rec, row_t, col_t}, s);
-  else if (dtype == PSTT2_F64) e = launch_err((const double*)x, R, C, r, L, Rp, gi, gj, part, s);
-  else e = launch_err((const float*)x, R, C, r, L, Rp, gi, gj, part, s);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, gi * gj, part + 2 * (int64_t)gi * gj);
-    e = hipMemcpyAsync(e2x2, part + 2 * (int64_t)gi * gj, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-  }
-  ws_free(part, s);
-  ws_free(Rp, s);
+  double* out = part ? part + 2 * (int64_t)p.gi * p.gj : nullptr;
+  if (e == hipSuccess) e = err_launch(c, p, x, dtype, FnTabs{rec, row_t, col_t}, iface, part, Rp, out, false, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(e2x2, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (part) ws_free(part, s);
+  if (Rp) ws_free(Rp, s);
   if (rec) ws_free(rec, s);
   if (row_t) ws_free(row_t, s);
   if (col_t) ws_free(col_t, s);
-  ws_free(ifb, s);
+  if (iface) ws_free(iface, s);
   hipError_t e2 = hipStreamSynchronize(s);
   return e != hipSuccess ? e : e2;
+}
+
+// ---- the same pass with no allocation (tt_error_noalloc) ----
+// The scratch is one file-scope device array.  Host code never uses its name as
+// an address: the device address comes from hipGetSymbolAddress, once per
+// device (each device holds its own copy), and only that pointer reaches the
+// kernels.  Calls that overlap on one device share the array and race.
+static __device__ __align__(256) unsigned char scratch[PSTT2_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+hipError_t scratch_base(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+int64_t align_doubles(int64_t n) { return (n + 31) / 32 * 32; }   // 256-byte steps
+}  // namespace
+
+// Bytes of static scratch an error pass of these cores needs.
+int64_t tt_error_scratch_bytes(const tt_cores* c) {
+  const ErrPlan p = err_plan(c);
+  return 8 * (align_doubles(std::max<int64_t>(p.n_iface, 1)) + align_doubles(p.n_part) + align_doubles(p.n_rp));
+}
+
+hipError_t tt_error_noalloc_run(const tt_cores* c, const void* x, int dtype, double* err_dev, hipStream_t s) {
+  const ErrPlan p = err_plan(c);
+  void* base = nullptr;
+  hipError_t e = scratch_base(&base);
+  if (e != hipSuccess) return e;
+  double* iface = (double*)base;
+  double* part = iface + align_doubles(std::max<int64_t>(p.n_iface, 1));
+  double* Rp = part + align_doubles(p.n_part);
+  // the three results go straight to the caller's buffer
+  return err_launch(c, p, x, dtype, FnTabs{nullptr, nullptr, nullptr}, iface, part, Rp, err_dev, true, s);
 }
 
 // The Gaussian-bump tensor: chunks of whole columns of X_m are evaluated into a
@@ -367,7 +460,7 @@ hipError_t tt_error_run_gauss(const tt_cores* c, const double* centers_host, int
       np += (int64_t)gi * gj;
     }
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int)np, part + 2 * np);
+      hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int)np, part + 2 * np, false);
       e = hipMemcpyAsync(e2x2, part + 2 * np, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     }
   }
