@@ -77,8 +77,21 @@ typedef enum { PSTT2_F64 = 0, PSTT2_F32 = 1 } pstt2_dtype;
  *           terms t0 + t1 + t2 (exact for FP32 values), the six products
  *           t_i * t_j with i + j <= 2 on bfloat16 matrix cores, FP32
  *           accumulation; about FP32 accuracy
- * F32 / BF16 / BF16X3 need dtype F32. */
-typedef enum { PSTT2_P_F64 = 0, PSTT2_P_F32 = 1, PSTT2_P_BF16 = 2, PSTT2_P_BF16X3 = 3 } pstt2_prec;
+ *   F16     X and the DRM rounded to IEEE half precision (round to nearest
+ *           even), FP32 accumulation on the f16 matrix cores: eight times
+ *           finer rounding than BF16 at the same rate.  Half precision spans
+ *           6.1e-5 .. 65504 (with gradual underflow below): entries of X or of
+ *           the DRM past 65504 in magnitude become infinite and recover
+ *           reports ENUMERIC; tensors whose entries sit far below 6e-5 lose
+ *           relative precision and should be scaled by the caller.
+ * F32 / BF16 / BF16X3 / F16 need dtype F32. */
+typedef enum {
+  PSTT2_P_F64 = 0,
+  PSTT2_P_F32 = 1,
+  PSTT2_P_BF16 = 2,
+  PSTT2_P_BF16X3 = 3,
+  PSTT2_P_F16 = 4
+} pstt2_prec;
 
 /* Middle-core rule.  ONEPASS: least squares from the extra right sketch of the
  * middle unfolding (PSTT2-onepass).  TWOPASS: second stream over X,
@@ -127,13 +140,15 @@ typedef struct {
   double eps;                 /* tolerance mode: target relative Frobenius error, 0 < eps < 1 */
   int32_t rmax;               /* tolerance mode: rank cap (<= 0: ell - 2) */
   int32_t ell;                /* sketch size r + p, 1 <= ell <= PSTT2_MAX_ELL */
-  const double* drm_factors;  /* host, copied at create; factor q is n_q x ell with ell fastest
+  const double* drm_factors;  /* host, copied at create, or NULL (drawn from seed); factor q is n_q x ell with ell fastest
                                  (element (i, c) at i*ell + c), iid standard Gaussian in the
                                  paper's DRMs (Section 3.2).  NESTED: psi_1..psi_{d-1} then
                                  omega_2..omega_d.  INDEPENDENT: for split k = 1..d-1 in turn,
                                  psi^(k)_1..psi^(k)_k then omega^(k)_{k+1}..omega^(k)_d */
   pstt2_drm drm;              /* factor scheme */
   pstt2_algo algo;            /* two-sided PSTT2 (0) or one-sided PSTT */
+  uint64_t seed;              /* drm_factors == NULL: the library draws the factors from this
+                                 seed (see pstt2_drm_factors) */
 } pstt2_desc;
 
 /* A tensor train.  Core k (0-based) is r[k] x n[k] x r[k+1], column-major
@@ -362,6 +377,20 @@ pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream)
  * already enqueued on the stream that produced them, and clear the struct.
  * NULL is ignored. */
 void tt_cores_free(tt_cores* cores);
+
+/* The DRM factors a context draws when desc->drm_factors is NULL (Algorithm
+ * PSTT: i.i.d. standard Gaussian entries, Section 3.2), in the packed layout of
+ * pstt2_desc.drm_factors for desc's d, n, ell and drm (other fields unused).
+ * Entry j of the buffer is the standard normal
+ *   p = j / 2, (x0..x3) = Philox4x32-10(counter (p mod 2^32, p div 2^32, 0, 0),
+ *                                       key (seed mod 2^32, seed div 2^32))
+ *   u1 = 1 - ((x0 >> 5) 2^26 + (x1 >> 6)) / 2^53,  u2 = ((x2 >> 5) 2^26 + (x3 >> 6)) / 2^53
+ *   entry 2p = sqrt(-2 ln u1) cos(2 pi u2),   entry 2p + 1 = sqrt(-2 ln u1) sin(2 pi u2)
+ * (Philox4x32-10: Salmon, Moraes, Dror, Shaw, SC 2011; Box-Muller transform).
+ * host_out == NULL: *count receives the number of doubles.  Otherwise *count
+ * must hold the capacity of host_out and receives the number written.  Host
+ * only, needs no GPU.  Errors: EINVAL. */
+pstt2_status pstt2_drm_factors(const pstt2_desc* desc, double* host_out, int64_t* count);
 
 /* Device-memory budget of the library in bytes (<= 0: none).  Buffers already
  * allocated are kept; a later request that would take the live total past the

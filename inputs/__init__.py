@@ -351,6 +351,85 @@ def pack_factors_independent(psi: dict, omega: dict, d: int) -> np.ndarray:
     return np.concatenate(parts)
 
 
+# ---- counter-based Gaussian stream (the library's seeded factors) ----
+# Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+# as 1, 2, 3", SC 2011) and the Box-Muller transform, written from their
+# published definitions.  Entry j of the stream: p = j // 2, four 32-bit words
+# x = Philox4x32-10(counter (p mod 2^32, p div 2^32, 0, 0), key (seed mod 2^32,
+# seed div 2^32)); u1 = 1 - ((x0 >> 5) 2^26 + (x1 >> 6)) / 2^53,
+# u2 = ((x2 >> 5) 2^26 + (x3 >> 6)) / 2^53; entry 2p = sqrt(-2 ln u1) cos(2 pi u2)
+# and entry 2p + 1 = sqrt(-2 ln u1) sin(2 pi u2).
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)     # round multipliers
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)     # Weyl key increments
+_U32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(counters: np.ndarray, seed: int) -> np.ndarray:
+    """Philox4x32-10 of 64-bit block counters (words (c mod 2^32, c div 2^32, 0, 0)) under a 64-bit key.
+
+    Returns an (len(counters), 4) uint64 array of the four 32-bit output words.
+    """
+    c = np.asarray(counters, dtype=np.uint64)
+    w0, w1 = c & _U32, c >> np.uint64(32)
+    w2 = np.zeros_like(c)
+    w3 = np.zeros_like(c)
+    k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
+    for rnd in range(10):
+        if rnd:
+            k0 = (k0 + _PHILOX_W[0]) & 0xFFFFFFFF
+            k1 = (k1 + _PHILOX_W[1]) & 0xFFFFFFFF
+        p0 = np.uint64(_PHILOX_M[0]) * w0          # < 2^64: exact in uint64
+        p1 = np.uint64(_PHILOX_M[1]) * w2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _U32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _U32
+        w0, w1, w2, w3 = hi1 ^ w1 ^ np.uint64(k0), lo1, hi0 ^ w3 ^ np.uint64(k1), lo0
+    return np.stack([w0, w1, w2, w3], axis=1)
+
+
+def philox_normals(seed: int, count: int, first: int = 0) -> np.ndarray:
+    """Entries first .. first + count - 1 of the seeded standard-normal stream above."""
+    j = np.arange(first, first + count, dtype=np.uint64)
+    x = philox4x32_10(j >> np.uint64(1), seed)
+    def unit53(a, b):
+        return ((a >> np.uint64(5)).astype(np.float64) * 67108864.0 + (b >> np.uint64(6)).astype(np.float64)) \
+            / 9007199254740992.0
+    u1 = 1.0 - unit53(x[:, 0], x[:, 1])
+    u2 = unit53(x[:, 2], x[:, 3])
+    two_pi = 2.0 * math.pi
+    out = np.empty(count)
+    # the C library's log / sqrt / cos / sin, one value at a time (as the host code does)
+    for t in range(count):
+        rad = math.sqrt(-2.0 * math.log(float(u1[t])))
+        ang = two_pi * float(u2[t])
+        out[t] = rad * (math.sin(ang) if (first + t) & 1 else math.cos(ang))
+    return out
+
+
+def seeded_factors(n: Sequence[int], ell: int, seed: int, drm: str = "nested"):
+    """The factors a context draws from `seed` (no caller factors): the stream cut into
+    the packed layout.  Returns (psi, omega) like drm_factors / drm_factors_independent."""
+    d = len(n)
+    if drm == "nested":
+        sizes = [("psi", q) for q in range(1, d)] + [("omega", q) for q in range(2, d + 1)]
+    else:
+        sizes = []
+        for k in range(1, d):
+            sizes += [("psi", k, q) for q in range(1, k + 1)] + [("omega", k, q) for q in range(k + 1, d + 1)]
+    total = sum(n[key[-1] - 1] * ell for key in sizes)
+    z = philox_normals(seed, total)
+    psi, omega, o = {}, {}, 0
+    for key in sizes:
+        nq = n[key[-1] - 1]
+        blk = z[o:o + nq * ell].reshape(nq, ell)
+        o += nq * ell
+        tgt = psi if key[0] == "psi" else omega
+        if drm == "nested":
+            tgt[key[1]] = blk
+        else:
+            tgt.setdefault(key[1], {})[key[2]] = blk
+    return psi, omega
+
+
 def slab_bounds(numel: int, fiber: int, nslabs: int):
     """Split [0, numel) into nslabs contiguous runs of whole fibers of length `fiber`.
 

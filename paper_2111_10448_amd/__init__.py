@@ -22,7 +22,8 @@ from . import _lib as L
 from ._lib import PSTT2Error  # noqa: F401
 
 __all__ = ["PSTT2", "TT", "PSTT2Error", "GaussBumps", "decompose", "tt_error", "tt_error_fn", "tt_reconstruct", "version", "cores_struct",
-           "PSTT2Reconstruct", "pstt2_reconstruct", "set_memory_limit", "memory_stats", "inject_launch_failure"]
+           "PSTT2Reconstruct", "pstt2_reconstruct", "set_memory_limit", "memory_stats", "inject_launch_failure",
+           "drm_factors_from_seed"]
 
 
 def _torch():
@@ -55,6 +56,23 @@ def _check_dev(t):
 
 def version() -> str:
     return L.lib().pstt2_version().decode()
+
+
+def drm_factors_from_seed(n: Sequence[int], ell: int, seed: int, drm: str = "nested") -> np.ndarray:
+    """The packed factors a context with no caller factors draws from `seed` (host only)."""
+    desc = L.Desc()
+    desc.d = len(n)
+    for k, v in enumerate(n):
+        desc.n[k] = int(v)
+    desc.ell = int(ell)
+    desc.drm = L.DRM[drm]
+    desc.seed = int(seed)
+    cnt = ctypes.c_int64(0)
+    L.check(L.lib().pstt2_drm_factors(ctypes.byref(desc), None, ctypes.byref(cnt)))
+    out = np.empty(cnt.value)
+    L.check(L.lib().pstt2_drm_factors(ctypes.byref(desc), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      ctypes.byref(cnt)))
+    return out
 
 
 def set_memory_limit(nbytes: int) -> None:
@@ -172,9 +190,12 @@ def cores_struct(cores: Sequence, n: Sequence[int], ranks: Sequence[int]) -> L.T
 class PSTT2:
     """A PSTT2-onepass (or two-pass) context: DRM factors, sketches, slab coverage."""
 
-    def __init__(self, n: Sequence[int], ell: int, factors: np.ndarray, *, dtype: str = "f64",
+    def __init__(self, n: Sequence[int], ell: int, factors: Optional[np.ndarray] = None, *, dtype: str = "f64",
                  prec: Optional[str] = None, ranks: Optional[Sequence[int]] = None, eps: Optional[float] = None,
-                 rmax: int = 0, mid: str = "onepass", drm: str = "nested", algo: str = "pstt2", stream=None):
+                 rmax: int = 0, mid: str = "onepass", drm: str = "nested", algo: str = "pstt2", stream=None,
+                 seed: int = 0):
+        """factors: the packed DRM factors (host), or None to have the library draw
+        them from `seed` (see drm_factors_from_seed)."""
         self.n = [int(v) for v in n]
         self.d = len(self.n)
         self.ell = int(ell)
@@ -198,8 +219,13 @@ class PSTT2:
             desc.eps = float(eps if eps is not None else 0.0)
             desc.rmax = int(rmax)
         desc.ell = self.ell
-        self._fac = np.ascontiguousarray(factors, dtype=np.float64)
-        desc.drm_factors = self._fac.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        desc.seed = int(seed)
+        if factors is None:
+            self._fac = None
+            desc.drm_factors = None
+        else:
+            self._fac = np.ascontiguousarray(factors, dtype=np.float64)
+            desc.drm_factors = self._fac.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self._ctx = ctypes.c_void_p()
         L.check(L.lib().pstt2_create(ctypes.byref(desc), ctypes.c_void_p(_stream_handle(stream)),
                                      ctypes.byref(self._ctx)))

@@ -18,7 +18,7 @@ MAX_ELL = 32
 OK, EINVAL, ESHAPE, ENOMEM, EDEVICE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENUMERIC", -6: "ESTATE"}
 F64, F32 = 0, 1
-PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3, "f16": 4}
 MID = {"onepass": 0, "twopass": 1, "twosided": 2}
 DRM = {"nested": 0, "independent": 1}
 FN = {"hilbert": 0, "gauss": 1}
@@ -41,6 +41,7 @@ class Desc(ctypes.Structure):
         ("drm_factors", ctypes.POINTER(ctypes.c_double)),
         ("drm", ctypes.c_int),
         ("algo", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -110,11 +111,12 @@ def lib():
     L.pstt2_memory_stats.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.pstt2_inject_launch_failure.argtypes = [i64]
     L.tt_error_noalloc.argtypes = [ctypes.POINTER(TTCores), vp, st, vp, vp]
+    L.pstt2_drm_factors.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     for f in ("pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
               "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_reset", "tt_error", "tt_reconstruct", "tt_cores_copy",
               "pstt2_profile", "pstt2_profile_read", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified",
               "pstt2_middle_pass_fn", "pstt2_set_memory_limit", "pstt2_memory_stats",
-              "pstt2_inject_launch_failure", "tt_error_noalloc"):
+              "pstt2_inject_launch_failure", "tt_error_noalloc", "pstt2_drm_factors"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -132,4 +134,4 @@ EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover"
            "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_profile", "pstt2_profile_read", "pstt2_reset",
            "pstt2_destroy", "tt_error", "tt_reconstruct", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified",
            "tt_cores_copy", "tt_cores_free", "pstt2_last_error", "pstt2_version", "pstt2_set_memory_limit",
-           "pstt2_memory_stats", "pstt2_inject_launch_failure", "tt_error_noalloc"]
+           "pstt2_memory_stats", "pstt2_inject_launch_failure", "tt_error_noalloc", "pstt2_drm_factors"]

@@ -329,6 +329,7 @@ __global__ void k_core_right_adj_next(const double* __restrict__ Gb, const doubl
 __device__ __forceinline__ double drm_eff(double v, int prec) {
   if (prec == PSTT2_P_F64) return v;
   const float f = (float)v;
+  if (prec == PSTT2_P_F16) return (double)(float)(_Float16)f;
   if (prec != PSTT2_P_BF16) return (double)f;
   uint32_t u = __float_as_uint(f);
   const uint32_t h = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;

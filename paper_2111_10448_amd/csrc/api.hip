@@ -377,6 +377,37 @@ int tolerance_rank(const double* s, int ell, double eps, int d) {
   return std::max(rr, 1);
 }
 
+// Doubles of the packed factor buffer and, when c is given, every factor's
+// offset: nested psi_1..psi_{d-1}, omega_2..omega_d; independent: per split
+// k, psi^(k)_1..psi^(k)_k then omega^(k)_{k+1}..omega^(k)_d.
+int64_t factor_layout(const pstt2_desc* desc, pstt2_ctx* c) {
+  const int d = desc->d;
+  const int64_t ell = desc->ell;
+  int64_t off = 0;
+  if (desc->drm != PSTT2_DRM_INDEPENDENT) {
+    for (int q = 1; q <= d - 1; ++q) {
+      if (c) c->psi_off[q - 1] = off;
+      off += desc->n[q - 1] * ell;
+    }
+    for (int q = 2; q <= d; ++q) {
+      if (c) c->omega_off[q - 1] = off;
+      off += desc->n[q - 1] * ell;
+    }
+  } else {
+    for (int k = 1; k <= d - 1; ++k) {
+      for (int q = 1; q <= k; ++q) {
+        if (c) c->ipsi_off[k][q - 1] = off;
+        off += desc->n[q - 1] * ell;
+      }
+      for (int q = k + 1; q <= d; ++q) {
+        if (c) c->iom_off[k][q - 1] = off;
+        off += desc->n[q - 1] * ell;
+      }
+    }
+  }
+  return off;
+}
+
 }  // namespace
 
 extern "C" {
@@ -392,14 +423,13 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   if (d < 2 || d > PSTT2_MAX_D) return fail(nullptr, PSTT2_EINVAL, "d must be in [2, 32]");
   if (desc->ell < 1 || desc->ell > PSTT2_MAX_ELL) return fail(nullptr, PSTT2_EINVAL, "ell must be in [1, 32]");
   if (desc->dtype != PSTT2_F64 && desc->dtype != PSTT2_F32) return fail(nullptr, PSTT2_EINVAL, "bad dtype");
-  if (desc->prec < PSTT2_P_F64 || desc->prec > PSTT2_P_BF16X3) return fail(nullptr, PSTT2_EINVAL, "bad prec");
+  if (desc->prec < PSTT2_P_F64 || desc->prec > PSTT2_P_F16) return fail(nullptr, PSTT2_EINVAL, "bad prec");
   if (desc->dtype == PSTT2_F64 && desc->prec != PSTT2_P_F64)
     return fail(nullptr, PSTT2_EINVAL, "FP64 tensors use PSTT2_P_F64 arithmetic");
   if (desc->dtype == PSTT2_F32 && desc->prec == PSTT2_P_F64)
-    return fail(nullptr, PSTT2_EINVAL, "FP32 tensors use PSTT2_P_F32, PSTT2_P_BF16 or PSTT2_P_BF16X3");
+    return fail(nullptr, PSTT2_EINVAL, "FP32 tensors use PSTT2_P_F32, PSTT2_P_BF16, PSTT2_P_BF16X3 or PSTT2_P_F16");
   if (desc->mid != PSTT2_MID_ONEPASS && desc->mid != PSTT2_MID_TWOPASS && desc->mid != PSTT2_MID_TWOSIDED)
     return fail(nullptr, PSTT2_EINVAL, "bad mid");
-  if (!desc->drm_factors) return fail(nullptr, PSTT2_EINVAL, "drm_factors is required");
   if (desc->drm != PSTT2_DRM_NESTED && desc->drm != PSTT2_DRM_INDEPENDENT) return fail(nullptr, PSTT2_EINVAL, "bad drm");
   if (desc->algo != PSTT2_ALGO_PSTT2 && desc->algo != PSTT2_ALGO_PSTT) return fail(nullptr, PSTT2_EINVAL, "bad algo");
   if (desc->algo == PSTT2_ALGO_PSTT && desc->mid == PSTT2_MID_TWOSIDED)
@@ -441,30 +471,15 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   (void)hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (c->ncu <= 0) c->ncu = 256;
 
-  // factors: nested psi_1..psi_{d-1}, omega_2..omega_d; independent: per
-  // split k, psi^(k)_1..psi^(k)_k then omega^(k)_{k+1}..omega^(k)_d
+  // factors: given by the caller, or drawn from the seed (rng.hip)
   c->indep = desc->drm == PSTT2_DRM_INDEPENDENT;
-  int64_t off = 0;
-  if (!c->indep) {
-    for (int q = 1; q <= d - 1; ++q) {
-      c->psi_off[q - 1] = off;
-      off += c->n[q - 1] * c->ell;
-    }
-    for (int q = 2; q <= d; ++q) {
-      c->omega_off[q - 1] = off;
-      off += c->n[q - 1] * c->ell;
-    }
-  } else {
-    for (int k = 1; k <= d - 1; ++k) {
-      for (int q = 1; q <= k; ++q) {
-        c->ipsi_off[k][q - 1] = off;
-        off += c->n[q - 1] * c->ell;
-      }
-      for (int q = k + 1; q <= d; ++q) {
-        c->iom_off[k][q - 1] = off;
-        off += c->n[q - 1] * c->ell;
-      }
-    }
+  const int64_t off = factor_layout(desc, c);
+  std::vector<double> drawn;
+  const double* fac_host = desc->drm_factors;
+  if (!fac_host) {
+    drawn.resize((size_t)off);
+    gaussian_fill(desc->seed, 0, off, drawn.data());
+    fac_host = drawn.data();
   }
   auto bail = [&](hipError_t e, const char* w) {
     pstt2_status st = hfail(c, e, w);
@@ -473,7 +488,7 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   };
   hipError_t e;
   if ((e = dev_malloc(&c->fac, sizeof(double) * off)) != hipSuccess) return bail(e, "hipMalloc(factors)");
-  if ((e = hipMemcpy(c->fac, desc->drm_factors, sizeof(double) * off, hipMemcpyHostToDevice)) != hipSuccess)
+  if ((e = hipMemcpy(c->fac, fac_host, sizeof(double) * off, hipMemcpyHostToDevice)) != hipSuccess)
     return bail(e, "hipMemcpy(factors)");
   if ((e = dev_malloc(&c->Y, sizeof(double) * c->R * c->ell)) != hipSuccess) return bail(e, "hipMalloc(Y)");
   if ((e = dev_malloc(&c->Tt, sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(T)");
@@ -1471,6 +1486,22 @@ pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream)
   }
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hfail(nullptr, e, "tt_cores_copy");
+  return PSTT2_OK;
+}
+
+pstt2_status pstt2_drm_factors(const pstt2_desc* desc, double* host_out, int64_t* count) {
+  if (!desc || !count) return fail(nullptr, PSTT2_EINVAL, "null argument");
+  if (desc->d < 2 || desc->d > PSTT2_MAX_D) return fail(nullptr, PSTT2_EINVAL, "d must be in [2, 32]");
+  if (desc->ell < 1 || desc->ell > PSTT2_MAX_ELL) return fail(nullptr, PSTT2_EINVAL, "ell must be in [1, 32]");
+  if (desc->drm != PSTT2_DRM_NESTED && desc->drm != PSTT2_DRM_INDEPENDENT) return fail(nullptr, PSTT2_EINVAL, "bad drm");
+  for (int q = 0; q < desc->d; ++q)
+    if (desc->n[q] < 1 || desc->n[q] > (1 << 30)) return fail(nullptr, PSTT2_EINVAL, "bad mode size");
+  const int64_t off = factor_layout(desc, nullptr);
+  if (host_out) {
+    if (*count < off) return fail(nullptr, PSTT2_EINVAL, "host_out holds fewer than the factor count");
+    gaussian_fill(desc->seed, 0, off, host_out);
+  }
+  *count = off;
   return PSTT2_OK;
 }
 

@@ -32,6 +32,12 @@ void mem_stats(int64_t* live, int64_t* peak, int64_t* limit);
 void fault_arm(int64_t count);
 bool fault_take();
 
+// ---- seeded Gaussian factors (rng.hip, host code) ----
+// Philox4x32-10 block for (seed, counter); and the standard normals
+// first .. first + count - 1 of the stream defined in rng.hip.
+void philox_block(uint64_t seed, uint64_t counter, uint32_t out[4]);
+void gaussian_fill(uint64_t seed, int64_t first, int64_t count, double* out);
+
 // ---- device workspace (workspace.hip) ----
 struct Arena {
   char* base = nullptr;

@@ -1011,12 +1011,13 @@ hipError_t two_sided_batch(TwoSidedBatch& B, hipStream_t s) {
 
 // The value of a DRM entry as the sketch kernel used it: the FP64 product of
 // factors rounded to the sketch arithmetic (FP32 for FP32 and split BF16, or
-// BF16).  The
+// BF16, or FP16).  The
 // one-pass middle core pairs Y_R with A = P_m^T Omega_m, so both must see the
 // same Omega_m.
 __device__ __forceinline__ double drm_effective(double v, int prec) {
   if (prec == PSTT2_P_F64) return v;
   const float f = (float)v;
+  if (prec == PSTT2_P_F16) return (double)(float)(_Float16)f;
   // split BF16 carries all 24 bits of the FP32 value in its three terms
   if (prec != PSTT2_P_BF16) return (double)f;
   uint32_t u = __float_as_uint(f);

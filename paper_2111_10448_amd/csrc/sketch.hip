@@ -45,7 +45,7 @@ __device__ __forceinline__ b8 join8(s4 lo, s4 hi) {
   return __builtin_bit_cast(b8, v);
 }
 
-enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
+enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3, P_F16 = 4 };
 
 constexpr int KC = 16;  // columns per chunk
 
@@ -106,6 +106,17 @@ struct Eng<P_BF16> {
   using part = float;
   static constexpr int KPL = 4, KSTEP = 16, RW = 128, VEC = 4, PAD = 4, NPL = 1;
 };
+// FP16: as BF16, with IEEE half precision (11-bit significand, range 6.1e-5 ..
+// 65504; larger values become infinite and are reported as non-finite sketches).
+template <>
+struct Eng<P_F16> {
+  using elem = float;
+  using lds_t = uint32_t;  // half in the low half, converted once when staged
+  using acc = float;
+  using accv = f4;
+  using part = float;
+  static constexpr int KPL = 4, KSTEP = 16, RW = 128, VEC = 4, PAD = 4, NPL = 1;
+};
 // Split BF16: X and the DRM are split into three bf16 terms once, when they
 // are staged in LDS (three planes); the six products of order <= 2 are summed.
 template <>
@@ -158,6 +169,21 @@ template <int PREC>
 __device__ __forceinline__ typename Eng<PREC>::lds_t drm_to_lds(double v) {
   if constexpr (PREC == P_F64) return v;
   else return (float)v;
+}
+
+// One-term 16-bit formats (plain BF16 and FP16): round-to-nearest-even bit
+// pattern of an FP32 value, and the 16x16x16 product with FP32 accumulation.
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+template <int PREC>
+__device__ __forceinline__ uint32_t to16(float f) {
+  if constexpr (PREC == P_F16) return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
+  else return bf16_rne(f);
+}
+template <int PREC>
+__device__ __forceinline__ f4 mfma16(s4 a, s4 b, f4 c) {
+  if constexpr (PREC == P_F16)
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b), c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
 // Row of element v of a lane's 16x16 MFMA accumulator tile (column = lane % 16).
@@ -322,7 +348,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
       } else {
         uint32_t p[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) p[v] = bf16_rne((float)psi_row(A, row0w + 16 * ks + 4 * g4 + v, a));
+        for (int v = 0; v < 4; ++v) p[v] = to16<PREC>((float)psi_row(A, row0w + 16 * ks + 4 * g4 + v, a));
         s4 hi, lo;
         unpack4(p[0], p[1], p[2], p[3], hi, lo);
         psiA[ks][mt] = hi;
@@ -371,9 +397,9 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     const int e = 2 * threadIdx.x;
     if (UNC && !omok) omv = double2{0.0, 0.0};
     if (e < KC * LP) {
-      if constexpr (PREC == P_BF16) {
-        Om[buf][e] = bf16_rne((float)omv.x);
-        Om[buf][e + 1] = bf16_rne((float)omv.y);
+      if constexpr (PREC == P_BF16 || PREC == P_F16) {
+        Om[buf][e] = to16<PREC>((float)omv.x);
+        Om[buf][e + 1] = to16<PREC>((float)omv.y);
       } else if constexpr (X3) {
         uint32_t t0, t1, t2;
         split3_pk((float)omv.x, (float)omv.y, t0, t1, t2);
@@ -440,9 +466,9 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
       }
       const int cc = i * (64 * VEC / RW) + lane / (RW / VEC);
       const int r = (lane % (RW / VEC)) * VEC;
-      if constexpr (PREC == P_BF16) {
+      if constexpr (PREC == P_BF16 || PREC == P_F16) {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = bf16_rne(xr[slot][i][v]);
+        for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = to16<PREC>(xr[slot][i][v]);
       } else if constexpr (X3) {
         uint32_t a0, a1, a2, b0, b1, b2;
         split3_pk(xr[slot][i][0], xr[slot][i][1], a0, a1, a2);
@@ -604,8 +630,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
         unpack4(xw[(4 * g4 + 0) * ST + r], xw[(4 * g4 + 1) * ST + r], xw[(4 * g4 + 2) * ST + r],
                 xw[(4 * g4 + 3) * ST + r], ah, al);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[nt], yacc[mt][nt], 0, 0, 0);
+        for (int nt = 0; nt < NT; ++nt) yacc[mt][nt] = mfma16<PREC>(ah, bh[nt], yacc[mt][nt]);
       }
     }
     // left sketch: T(ell, cols) = Psi(rows, ell)^T X(rows, cols)
@@ -659,8 +684,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
           s4 bh, bl;
           unpack4(q.x, q.y, q.z, q.w, bh, bl);
 #pragma unroll
-          for (int mt = 0; mt < NT; ++mt)
-            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(psiA[ks][mt], bh, tacc[mt], 0, 0, 0);
+          for (int mt = 0; mt < NT; ++mt) tacc[mt] = mfma16<PREC>(psiA[ks][mt], bh, tacc[mt]);
         }
       }
     }
@@ -1003,6 +1027,7 @@ void sketch_geometry(int prec, int ell, int* rows_per_block, int* threads, int* 
     case P_F64: *rows_per_block = nwf_for(L4) * Eng<P_F64>::RW; break;
     case P_F32: *rows_per_block = NWS * Eng<P_F32>::RW; break;
     case P_BF16: *rows_per_block = NWS * Eng<P_BF16>::RW; break;
+    case P_F16: *rows_per_block = NWS * Eng<P_F16>::RW; break;
     default: *rows_per_block = NWS * Eng<P_BF16X3>::RW; break;
   }
 }
@@ -1046,6 +1071,8 @@ hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s) {
     case P_F32 * 100 + 32: return launch_t<P_F32, 32>(a, aligned, s);
     case P_BF16 * 100 + 16: return launch_t<P_BF16, 16>(a, aligned, s);
     case P_BF16 * 100 + 32: return launch_t<P_BF16, 32>(a, aligned, s);
+    case P_F16 * 100 + 16: return launch_t<P_F16, 16>(a, aligned, s);
+    case P_F16 * 100 + 32: return launch_t<P_F16, 32>(a, aligned, s);
     case P_BF16X3 * 100 + 16: return launch_t<P_BF16X3, 16>(a, aligned, s);
     case P_BF16X3 * 100 + 32: return launch_t<P_BF16X3, 32>(a, aligned, s);
     default: return hipErrorInvalidValue;

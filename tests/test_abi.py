@@ -45,17 +45,29 @@ def test_enums_match_header():
     assert vals["PSTT2_MID_TWOSIDED"] == 2
 
 
-def test_struct_layouts_match_header():
-    """ctypes layouts mirror the C structs (natural alignment, x86-64)."""
+def test_struct_layouts_match_header(tmp_path):
+    """Every field of the ctypes mirrors sits where gcc lays it out from the header."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
     from paper_2111_10448_amd import _lib as L
-    assert ctypes.sizeof(L.Desc) == 440
-    assert L.Desc.eps.offset == 408 and L.Desc.drm_factors.offset == 424 and L.Desc.drm.offset == 432
-    assert L.Desc.algo.offset == 436
-    # d, pad, n[32], r[33], pad, core[32], owned, pad, stream
-    assert ctypes.sizeof(L.TTCores) == 4 + 4 + 256 + 132 + 4 + 256 + 4 + 4 + 8
-    assert L.TTCores.core.offset == 400 and L.TTCores.stream.offset == 664
-    assert ctypes.sizeof(L.Fn) == 24
-    assert L.Fn.n_terms.offset == 4 and L.Fn.gamma.offset == 8 and L.Fn.centers.offset == 16
+    lines = []
+    for ctype, cname in ((L.Desc, "pstt2_desc"), (L.TTCores, "tt_cores"), (L.Fn, "pstt2_fn")):
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in ctype._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pstt2.h"\nint main(void) {\n' +
+                   "\n".join(lines) + "\nreturn 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.splitlines())
+    for ctype, cname in ((L.Desc, "pstt2_desc"), (L.TTCores, "tt_cores"), (L.Fn, "pstt2_fn")):
+        assert int(got[cname]) == ctypes.sizeof(ctype), cname
+        for fname, _ in ctype._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(ctype, fname).offset, (cname, fname)
 
 
 def test_fn_layout_matches_the_c_compiler(tmp_path):
@@ -114,14 +126,23 @@ def test_null_arguments_are_rejected():
     lib.tt_cores_free(None)
 
 
-def test_missing_factors_rejected():
+def test_seeded_factor_query_validation():
+    """pstt2_drm_factors (host only): the count, a short buffer and a bad order are reported."""
     from paper_2111_10448_amd import _lib as L
     lib = L.lib()
     d = L.Desc()
-    d.d = 2
-    d.n[0] = d.n[1] = 4
+    d.d = 3
+    d.n[0], d.n[1], d.n[2] = 4, 5, 6
     d.ell = 3
-    d.ranks[0] = 1
-    ctx = ctypes.c_void_p()
-    assert lib.pstt2_create(ctypes.byref(d), None, ctypes.byref(ctx)) == L.EINVAL
-    assert "drm_factors" in lib.pstt2_last_error(None).decode()
+    cnt = ctypes.c_int64(0)
+    assert lib.pstt2_drm_factors(ctypes.byref(d), None, ctypes.byref(cnt)) == L.OK
+    assert cnt.value == (4 + 5 + 5 + 6) * 3          # psi_1, psi_2, omega_2, omega_3
+    buf = (ctypes.c_double * 10)()
+    cnt.value = 10
+    assert lib.pstt2_drm_factors(ctypes.byref(d), buf, ctypes.byref(cnt)) == L.EINVAL
+    assert "fewer" in lib.pstt2_last_error(None).decode()
+    d.drm = L.DRM["independent"]
+    assert lib.pstt2_drm_factors(ctypes.byref(d), None, ctypes.byref(cnt)) == L.OK
+    assert cnt.value == ((4 + 5 + 6) + (4 + 5 + 6)) * 3   # split 1: psi_1, omega_2, omega_3; split 2: psi_1, psi_2, omega_3
+    d.d = 1
+    assert lib.pstt2_drm_factors(ctypes.byref(d), None, ctypes.byref(cnt)) == L.EINVAL

@@ -322,3 +322,52 @@ def test_twopass_wide_ranks_split_pass(rank, ell):
     out = compare(ctx, tt, xg, x, w, ref, "f64", check_cores=True)
     say(f"    {out}")
     ctx.close()
+
+
+@pytest.mark.parametrize("name,slabs", [("c3_small", False), ("c4_small", True), ("c4_twin24", True)])
+def test_fp16_sketches(name, slabs):
+    """FP16 sketch arithmetic (IEEE half, FP32 accumulation) against the oracle, at the
+    one-term 16-bit tolerances scaled to half precision.  The 1/sum twin runs in
+    tolerance mode with the oracle's ranks (as plain BF16); the TT twins in fixed rank,
+    streamed as scrambled slabs (16- and 32-wide sketch tiles)."""
+    w = inputs.WORKLOADS[name]
+    say(f"[gpu] FP16 sketches {name} ell={w.ell} slabs={slabs}")
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    sl = None
+    if slabs:
+        sl = inputs.slab_bounds(x.size, w.n[0], w.nslabs)
+        order = np.random.default_rng(16).permutation(len(sl))
+        sl = [sl[i] for i in order]
+    ranks = ref["ranks"] if w.ranks() is None else None
+    ctx, tt, xg = gpu_run(x, w, fac, "f16", slabs=sl, batched=slabs, ranks=ranks)
+    out = compare(ctx, tt, xg, x, w, ref, "f16", check_pivots=False)
+    say(f"    {out}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,n,drm", [("c2_small", None, "nested"), ("c1", (9, 7, 8), "independent"),
+                                        ("c4_small", None, "nested")])
+def test_seeded_factors(name, n, drm):
+    """A context with no caller factors draws them from its seed (Philox4x32-10 +
+    Box-Muller in the library's host code); the oracle gets the same stream from the
+    independent implementation in inputs and must agree as with caller factors."""
+    import dataclasses
+    import torch
+    import paper_2111_10448_amd as P
+    w = inputs.WORKLOADS[name]
+    if n is not None:
+        w = dataclasses.replace(w, name="seeded", index=120 + len(n), n=tuple(n))
+    seed = 0x5EED0000 + w.index
+    say(f"[gpu] seeded factors {w.name} n={w.n} drm={drm} seed={seed:#x}")
+    x = inputs.make_tensor(w)
+    psi, omega = inputs.seeded_factors(w.n, w.ell, seed, drm)
+    ref = oracle_run(x, w, psi, omega, drm=drm)
+    prec = "f64" if w.dtype == "f64" else "f32"
+    xg = torch.from_numpy(x).cuda()
+    ctx = P.PSTT2(w.n, w.ell, None, dtype=w.dtype, prec=prec, ranks=w.ranks(), drm=drm, seed=seed)
+    ctx.sketch(xg)
+    tt = ctx.recover()
+    out = compare(ctx, tt, xg, x, w, ref, prec, check_cores=(prec == "f64"))
+    say(f"    {out}")
+    ctx.close()
