@@ -378,6 +378,26 @@ pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream)
  * NULL is ignored. */
 void tt_cores_free(tt_cores* cores);
 
+/* Parallel-TTSVD (Section 3.1, Algorithm Parallel-TTSVD, Theorem perf_alg1):
+ * the deterministic compress-then-combine TT of a dense FP64 tensor.  For
+ * every split k = 1..d-1 a truncated SVD X_k ~ U_k Sigma_k V_k^T keeps the
+ * smallest rank r_k with sum_{i > r_k} sigma_i(X_k)^2 <= eps^2 ||X||_F^2 / (d-1)
+ * (capped at rmax when rmax > 0, and at PSTT2_MAX_ELL); then G_1 = U_1,
+ * G_k = reshape(U_{k-1}^T reshape(U_k, R_{k-1}, n_k r_k)) (equation "core")
+ * and G_d = Sigma_{d-1} V_{d-1}^T, so that ||X - X~||_F <= eps ||X||_F
+ * (Theorem perf_alg1) when no cap binds.  The SVDs run on the GPU by one-sided
+ * Jacobi on each unfolding's short side, directly on the data (no Gram
+ * matrix: singular values keep their relative accuracy), FP64 throughout.
+ * Scope: every unfolding's short side min(R_k, C_k) must be at most
+ * PSTT2_TTSVD_MAX_SIDE; the work is about 10 sweeps of short side x N
+ * products per split.  x_dev: N = n_1...n_d FP64 entries, column-major,
+ * read-only.  out receives library-owned cores (release with tt_cores_free).
+ * X = 0 gives ranks 1 and X~ = 0.  sync.  Errors: EINVAL (arguments, scope),
+ * ENUMERIC (non-finite X, no convergence in 40 sweeps), ENOMEM, EDEVICE. */
+#define PSTT2_TTSVD_MAX_SIDE 1024
+pstt2_status pstt2_parallel_ttsvd(int32_t d, const int64_t* n, const double* x_dev, double eps, int32_t rmax,
+                                  void* hip_stream, tt_cores* out);
+
 /* The DRM factors a context draws when desc->drm_factors is NULL (Algorithm
  * PSTT: i.i.d. standard Gaussian entries, Section 3.2), in the packed layout of
  * pstt2_desc.drm_factors for desc's d, n, ell and drm (other fields unused).

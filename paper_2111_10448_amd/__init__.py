@@ -23,7 +23,7 @@ from ._lib import PSTT2Error  # noqa: F401
 
 __all__ = ["PSTT2", "TT", "PSTT2Error", "GaussBumps", "decompose", "tt_error", "tt_error_fn", "tt_reconstruct", "version", "cores_struct",
            "PSTT2Reconstruct", "pstt2_reconstruct", "set_memory_limit", "memory_stats", "inject_launch_failure",
-           "drm_factors_from_seed"]
+           "drm_factors_from_seed", "parallel_ttsvd"]
 
 
 def _torch():
@@ -56,6 +56,19 @@ def _check_dev(t):
 
 def version() -> str:
     return L.lib().pstt2_version().decode()
+
+
+def parallel_ttsvd(x, n: Sequence[int], eps: float, rmax: int = 0, stream=None) -> "TT":
+    """Algorithm Parallel-TTSVD on the GPU: truncated SVDs of every unfolding (one-sided
+    Jacobi), cores by equation "core".  x: flat column-major FP64 CUDA tensor."""
+    _check_dev(x)
+    if _dtype_code(x) != L.F64:
+        raise TypeError("Parallel-TTSVD takes an FP64 tensor")
+    nn = (ctypes.c_int64 * len(n))(*[int(v) for v in n])
+    cs = L.TTCores()
+    L.check(L.lib().pstt2_parallel_ttsvd(len(n), nn, ctypes.c_void_p(x.data_ptr()), float(eps), int(rmax),
+                                         ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(cs)))
+    return TT(cs, stream)
 
 
 def drm_factors_from_seed(n: Sequence[int], ell: int, seed: int, drm: str = "nested") -> np.ndarray:

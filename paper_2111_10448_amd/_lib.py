@@ -24,6 +24,7 @@ DRM = {"nested": 0, "independent": 1}
 FN = {"hilbert": 0, "gauss": 1}
 GAUSS_MAX_TERMS = 1024
 NOALLOC_SCRATCH_BYTES = 64 << 20
+TTSVD_MAX_SIDE = 1024
 ALGO = {"pstt2": 0, "pstt": 1}
 
 
@@ -112,11 +113,12 @@ def lib():
     L.pstt2_inject_launch_failure.argtypes = [i64]
     L.tt_error_noalloc.argtypes = [ctypes.POINTER(TTCores), vp, st, vp, vp]
     L.pstt2_drm_factors.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.pstt2_parallel_ttsvd.argtypes = [i32, ctypes.POINTER(i64), vp, ctypes.c_double, i32, vp, ctypes.POINTER(TTCores)]
     for f in ("pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover", "pstt2_middle_pass", "pstt2_vjp",
               "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_reset", "tt_error", "tt_reconstruct", "tt_cores_copy",
               "pstt2_profile", "pstt2_profile_read", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified",
               "pstt2_middle_pass_fn", "pstt2_set_memory_limit", "pstt2_memory_stats",
-              "pstt2_inject_launch_failure", "tt_error_noalloc", "pstt2_drm_factors"):
+              "pstt2_inject_launch_failure", "tt_error_noalloc", "pstt2_drm_factors", "pstt2_parallel_ttsvd"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -134,4 +136,5 @@ EXPORTS = ["pstt2_create", "pstt2_sketch", "pstt2_sketch_slabs", "pstt2_recover"
            "pstt2_get_sketch", "pstt2_get_pivots", "pstt2_profile", "pstt2_profile_read", "pstt2_reset",
            "pstt2_destroy", "tt_error", "tt_reconstruct", "pstt2_sketch_fn", "tt_error_fn", "pstt2_recover_certified",
            "tt_cores_copy", "tt_cores_free", "pstt2_last_error", "pstt2_version", "pstt2_set_memory_limit",
-           "pstt2_memory_stats", "pstt2_inject_launch_failure", "tt_error_noalloc", "pstt2_drm_factors"]
+           "pstt2_memory_stats", "pstt2_inject_launch_failure", "tt_error_noalloc", "pstt2_drm_factors",
+           "pstt2_parallel_ttsvd"]

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpstt2.so")
 SOURCES = ["api.hip", "sketch.hip", "reduce.hip", "recover.hip", "tt_eval.hip", "adjoint.hip", "workspace.hip",
-           "tensor_fn.hip", "rng.hip"]
+           "tensor_fn.hip", "rng.hip", "ttsvd.hip"]
 ARCH = os.environ.get("PSTT2_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1489,6 +1489,152 @@ pstt2_status tt_cores_copy(const tt_cores* src, tt_cores* dst, void* hip_stream)
   return PSTT2_OK;
 }
 
+pstt2_status pstt2_parallel_ttsvd(int32_t d, const int64_t* n, const double* x_dev, double eps, int32_t rmax,
+                                  void* hip_stream, tt_cores* out) {
+  if (!n || !x_dev || !out) return fail(nullptr, PSTT2_EINVAL, "null argument");
+  if (d < 2 || d > PSTT2_MAX_D) return fail(nullptr, PSTT2_EINVAL, "d must be in [2, 32]");
+  if (!(eps > 0.0 && eps < 1.0)) return fail(nullptr, PSTT2_EINVAL, "eps must be in (0, 1)");
+  int64_t Rk[PSTT2_MAX_D + 1];
+  Rk[0] = 1;
+  for (int q = 0; q < d; ++q) {
+    if (n[q] < 1 || n[q] > (1 << 30)) return fail(nullptr, PSTT2_EINVAL, "mode sizes must be in [1, 2^30]");
+    Rk[q + 1] = Rk[q] * n[q];
+    if (Rk[q + 1] > (int64_t(1) << 36)) return fail(nullptr, PSTT2_EINVAL, "tensor too large for the Jacobi SVDs");
+  }
+  const int64_t N = Rk[d];
+  int64_t wmax = 0;
+  int spmax = 2;
+  for (int k = 1; k <= d - 1; ++k) {
+    const int64_t R = Rk[k], C = N / R, sh = std::min(R, C);
+    if (sh > PSTT2_TTSVD_MAX_SIDE)
+      return fail(nullptr, PSTT2_EINVAL, "an unfolding's short side exceeds PSTT2_TTSVD_MAX_SIDE");
+    const int sp = (int)(sh + (sh & 1));
+    spmax = std::max(spmax, sp);
+    wmax = std::max(wmax, std::max(R, C) * sp);
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  double *W = nullptr, *J = nullptr, *sig = nullptr;
+  int *idx = nullptr, *cnt = nullptr;
+  std::vector<double*> U(d + 1, nullptr);
+  int r[PSTT2_MAX_D + 1];
+  r[0] = r[d] = 1;
+  tt_cores tc;
+  std::memset(&tc, 0, sizeof(tc));
+  double* base = nullptr;
+  auto cleanup = [&]() {
+    for (double* u : U) dev_free_async(u, s);
+    dev_free_async(W, s);
+    dev_free_async(J, s);
+    dev_free_async(sig, s);
+    dev_free_async(idx, s);
+    dev_free_async(cnt, s);
+  };
+  auto bail = [&](pstt2_status st) {
+    if (base) dev_free_async(base, s);
+    cleanup();
+    (void)hipStreamSynchronize(s);
+    return st;
+  };
+#define SVDCK(call)                                                \
+  do {                                                             \
+    hipError_t e_ = (call);                                        \
+    if (e_ != hipSuccess) return bail(hfail(nullptr, e_, #call)); \
+  } while (0)
+  SVDCK(dev_malloc_async((void**)&W, sizeof(double) * wmax, s));
+  SVDCK(dev_malloc_async((void**)&J, sizeof(double) * spmax * spmax, s));
+  SVDCK(dev_malloc_async((void**)&sig, sizeof(double) * spmax, s));
+  SVDCK(dev_malloc_async((void**)&idx, sizeof(int) * spmax, s));
+  SVDCK(dev_malloc_async((void**)&cnt, sizeof(int), s));
+  // the last core is formed with its split's SVD; the others from U by equation "core"
+  const int nd = (int)n[d - 1];
+  std::vector<double> g_last;
+  double* glast = nullptr;
+  for (int k = 1; k <= d - 1; ++k) {
+    const int64_t R = Rk[k], C = N / R, L = std::max(R, C);
+    const int sh = (int)std::min(R, C), sp = sh + (sh & 1);
+    const double tol = std::sqrt((double)L) * 2.220446049250313e-16;
+    SVDCK(svd_load(x_dev, R, C, sp, W, s));
+    SVDCK(svd_init(J, sp, cnt, s));
+    bool converged = false;
+    for (int sweep = 0; sweep < 40 && !converged; ++sweep) {
+      int rot = 0;
+      SVDCK(svd_sweep(W, L, J, sp, tol, cnt, s));
+      SVDCK(hipMemcpyAsync(&rot, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+      SVDCK(hipStreamSynchronize(s));
+      converged = rot == 0;
+    }
+    if (!converged) return bail(fail(nullptr, PSTT2_ENUMERIC, "Jacobi SVD did not converge in 40 sweeps"));
+    std::vector<double> sv(sh);
+    SVDCK(svd_colnorms(W, L, sh, sig, s));
+    SVDCK(hipMemcpyAsync(sv.data(), sig, sizeof(double) * sh, hipMemcpyDeviceToHost, s));
+    SVDCK(hipStreamSynchronize(s));
+    double tot = 0.0;
+    for (double v : sv) {
+      if (!std::isfinite(v)) return bail(fail(nullptr, PSTT2_ENUMERIC, "non-finite values in X"));
+      tot += v * v;
+    }
+    // singular values in decreasing order (ties keep column order)
+    std::vector<int> order(sh);
+    for (int i = 0; i < sh; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sv[a] > sv[b]; });
+    // Section 2.2's truncation with the per-unfolding share of Algorithm
+    // Parallel-TTSVD: smallest r with sum_{i > r} sigma_i^2 <= eps^2 ||X||_F^2 / (d - 1)
+    const double thr = eps * eps * tot / (d - 1);
+    int rk = sh;
+    double tail = 0.0;
+    for (int i = sh - 1; i >= 1; --i) {
+      if (tail + sv[order[i]] * sv[order[i]] <= thr) {
+        tail += sv[order[i]] * sv[order[i]];
+        rk = i;
+      } else {
+        break;
+      }
+    }
+    if (rmax > 0) rk = std::min(rk, (int)rmax);
+    rk = std::min(rk, PSTT2_MAX_ELL);
+    r[k] = rk;
+    SVDCK(hipMemcpyAsync(idx, order.data(), sizeof(int) * rk, hipMemcpyHostToDevice, s));
+    SVDCK(dev_malloc_async((void**)&U[k], sizeof(double) * R * rk, s));
+    if (R <= C) SVDCK(svd_gather(J, sp, R, idx, nullptr, rk, U[k], s));   // U = J
+    else SVDCK(svd_gather(W, R, R, idx, sig, rk, U[k], s));              // U = W' / sigma
+    if (k == d - 1) {
+      SVDCK(dev_malloc_async((void**)&glast, sizeof(double) * rk * nd, s));
+      U[0] = glast;   // released with the rest
+      if (R > C) SVDCK(svd_last_core(J, sp, idx, sig, rk, nd, glast, s));   // Sigma V^T from J
+      else SVDCK(svd_last_core(W, C, idx, nullptr, rk, nd, glast, s));      // U^T X = W'^T
+    }
+    // the sizes were read back above: idx may be refilled by the next split
+    SVDCK(hipStreamSynchronize(s));
+  }
+  int64_t tot = 0;
+  for (int k = 0; k < d; ++k) tot += (int64_t)r[k] * n[k] * r[k + 1];
+  SVDCK(dev_malloc_async((void**)&base, sizeof(double) * tot, s));
+  tc.d = d;
+  tc.owned = 1;
+  tc.stream = (void*)s;
+  int64_t o = 0;
+  for (int k = 0; k < d; ++k) {
+    tc.n[k] = n[k];
+    tc.core[k] = base + o;
+    o += (int64_t)r[k] * n[k] * r[k + 1];
+  }
+  for (int k = 0; k <= d; ++k) tc.r[k] = r[k];
+  // G_1 = U_1; G_k = U_{k-1}^T reshape(U_k, R_{k-1}, n_k r_k) (equation "core"); G_d = Sigma V^T
+  SVDCK(hipMemcpyAsync(tc.core[0], U[1], sizeof(double) * n[0] * r[1], hipMemcpyDeviceToDevice, s));
+  for (int k = 2; k <= d - 1; ++k)
+    SVDCK(core_left(U[k - 1], Rk[k - 1], r[k - 1], U[k], (int)n[k - 1], r[k], tc.core[k - 1], s));
+  SVDCK(hipMemcpyAsync(tc.core[d - 1], glast, sizeof(double) * r[d - 1] * nd, hipMemcpyDeviceToDevice, s));
+#undef SVDCK
+  cleanup();
+  const hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    tt_cores_free(&tc);
+    return hfail(nullptr, e, "pstt2_parallel_ttsvd");
+  }
+  *out = tc;
+  return PSTT2_OK;
+}
+
 pstt2_status pstt2_drm_factors(const pstt2_desc* desc, double* host_out, int64_t* count) {
   if (!desc || !count) return fail(nullptr, PSTT2_EINVAL, "null argument");
   if (desc->d < 2 || desc->d > PSTT2_MAX_D) return fail(nullptr, PSTT2_EINVAL, "d must be in [2, 32]");

@@ -243,6 +243,19 @@ hipError_t adj_derive_right(const double* Tbk, double* Tbp, int64_t Ck, int nk, 
 hipError_t adj_out(int dtype, const SketchArgs& g, int prec, const double* Yb, const double* Tbt, const double* L,
                    const double* Rt, int r, const void* x, void* gx, bool acc, hipStream_t s);
 
+// Parallel-TTSVD building blocks (ttsvd.hip).  W is the L x sp work matrix of
+// an unfolding (X_k^T when R_k <= C_k, else X_k; sp = the short side rounded up
+// to even, zero columns past it), J its sp x sp rotation accumulator.
+hipError_t svd_load(const double* x, int64_t R, int64_t C, int sp, double* W, hipStream_t s);
+hipError_t svd_init(double* J, int sp, int* counter, hipStream_t s);
+// one sweep of the round-robin schedule; *counter receives the rotations made
+hipError_t svd_sweep(double* W, int64_t L, double* J, int sp, double tol, int* counter, hipStream_t s);
+hipError_t svd_colnorms(const double* W, int64_t L, int scols, double* sig, hipStream_t s);
+hipError_t svd_gather(const double* src, int64_t ld, int64_t rows, const int* idx, const double* sig, int r,
+                      double* dst, hipStream_t s);
+hipError_t svd_last_core(const double* src, int64_t ld, const int* idx, const double* sig, int r, int nd, double* G,
+                         hipStream_t s);
+
 // TT evaluation (tt_eval.hip).
 hipError_t tt_interfaces(const tt_cores* c, int split, double** L, double** Rt, double** base, hipStream_t s);
 // Bytes of the static scratch the allocation-free error pass of these cores needs.
