@@ -53,6 +53,8 @@ struct pstt2_ctx {
   bool recovered = false;
   double* one = nullptr;       // device scalar 1.0 (Q_0 when m == 1)
   double* om_tab = nullptr;    // Omega_m table, C x L4 (independent scheme: split m's)
+  uint16_t* om16 = nullptr;    // 16-bit precisions: the same rounded per plane (see build_omega16_table)
+  std::vector<uint16_t*> iom16;   // independent scheme: 16-bit tables of the right splits k < m
   int L4 = 4;
   // independent DRM scheme: per-split factor offsets, Omega_m tables of the
   // right splits k < m, the extra sketches of X_m, and sinks for pass groups
@@ -174,6 +176,8 @@ SketchArgs base_args(const pstt2_ctx* c) {
   a.tpart = c->tpart;
   a.gi_count = c->gi;
   a.om_tab = c->om_tab;
+  a.om16 = c->om16;
+  a.tlp = omega16_planes(c->prec) ? c->lp : 0;
   a.L4 = c->L4;
   return a;
 }
@@ -235,6 +239,7 @@ SketchArgs group_args(const pstt2_ctx* c, int g, double** Ydst, double** Tdst) {
   if (kr <= m) {
     for (int q = 0; q < PSTT2_MAX_D; ++q) a.omega_off[q] = c->iom_off[kr][q];
     a.om_tab = kr == m ? c->om_tab : c->iom_tab[kr];
+    a.om16 = kr == m ? c->om16 : c->iom16[kr];
     *Ydst = kr == m ? c->Y : c->iY[kr];
   } else {
     *Ydst = c->sinkY;
@@ -297,10 +302,11 @@ pstt2_status launch_segs(pstt2_ctx* c, const SketchArgs& ga, const std::vector<S
       const size_t s1 = std::min(segs.size(), s0 + kMaxSeg);
       int64_t nch = 0;
       a.nseg = (int32_t)(s1 - s0);
+      const int kc = sketch_chunk_cols(c->prec);
       for (size_t i = s0; i < s1; ++i) {
         Seg sg = segs[i];
         sg.chunk0 = nch;
-        nch += (sg.ncols + 15) / 16;
+        nch += (sg.ncols + kc - 1) / kc;
         a.seg[i - s0] = sg;
       }
       a.nchunks = nch;
@@ -527,14 +533,23 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   c->gj_max = std::max(1, c->ncu * wg_per_cu / c->gi);
   const size_t psz = c->prec == PSTT2_P_F64 ? 8 : 4;
   if ((e = dev_malloc(&c->ypart, psz * c->gj_max * c->ell * c->R)) != hipSuccess) return bail(e, "hipMalloc(ypart)");
-  if ((e = dev_malloc(&c->tpart, psz * (c->gi * c->ell * c->C + kTPartPad))) != hipSuccess)
+  const int64_t trows = omega16_planes(c->prec) ? c->lp : c->ell;   // see SketchArgs::tlp
+  if ((e = dev_malloc(&c->tpart, psz * (c->gi * trows * c->C + kTPartPad))) != hipSuccess)
     return bail(e, "hipMalloc(tpart)");
   c->L4 = (c->ell + 3) / 4 * 4;
   if ((e = dev_malloc(&c->om_tab, sizeof(double) * c->C * c->L4)) != hipSuccess) return bail(e, "hipMalloc(omega)");
   if ((e = build_omega_table(base_args(c), c->L4, c->om_tab, c->stream)) != hipSuccess)
     return bail(e, "omega table");
+  const int npl16 = omega16_planes(c->prec);
+  if (npl16) {
+    const size_t b16 = sizeof(uint16_t) * npl16 * c->lp * c->C;
+    if ((e = dev_malloc(&c->om16, b16)) != hipSuccess) return bail(e, "hipMalloc(omega16)");
+    if ((e = build_omega16_table(c->om_tab, c->C, c->L4, c->ell, c->lp, c->prec, c->om16, c->stream)) != hipSuccess)
+      return bail(e, "omega16 table");
+  }
   if (c->indep) {
     c->iom_tab.assign(d + 1, nullptr);
+    c->iom16.assign(d + 1, nullptr);
     c->iY.assign(d + 1, nullptr);
     c->iT.assign(d + 1, nullptr);
     for (int k = 1; k < c->m; ++k) {
@@ -543,6 +558,13 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
       SketchArgs a = base_args(c);
       for (int q = 0; q < PSTT2_MAX_D; ++q) a.omega_off[q] = c->iom_off[k][q];
       if ((e = build_omega_table(a, c->L4, c->iom_tab[k], c->stream)) != hipSuccess) return bail(e, "omega table");
+      if (npl16) {
+        const size_t b16 = sizeof(uint16_t) * npl16 * c->lp * c->C;
+        if ((e = dev_malloc(&c->iom16[k], b16)) != hipSuccess) return bail(e, "hipMalloc(omega16)");
+        if ((e = build_omega16_table(c->iom_tab[k], c->C, c->L4, c->ell, c->lp, c->prec, c->iom16[k], c->stream)) !=
+            hipSuccess)
+          return bail(e, "omega16 table");
+      }
     }
     for (int k = c->m + 1; k <= d - 1; ++k)
       if ((e = dev_malloc(&c->iT[k], sizeof(double) * c->C * c->ell)) != hipSuccess) return bail(e, "hipMalloc(T)");
@@ -628,6 +650,8 @@ void pstt2_destroy(pstt2_ctx* c) {
   dev_free(c->Bk);
   dev_free(c->chain_dev);
   dev_free(c->om_tab);
+  dev_free(c->om16);
+  for (uint16_t* p : c->iom16) dev_free(p);
   for (double* p : c->iom_tab) dev_free(p);
   for (double* p : c->iY) dev_free(p);
   for (double* p : c->iT) dev_free(p);
@@ -1251,6 +1275,8 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   a.seg[0].chunk0 = 0;
   a.ypart = take((int64_t)a.gj_count * rm * c->R, false);
   a.tpart = take((int64_t)a.gi_count * rm * c->C + kTPartPad, false);
+  a.tlp = 0;   // the FP64 kernel's partial layout
+  a.om16 = nullptr;
   double* U = take(c->R * rm, true);    // Lbar_m = gbar_m Rt^T        (R x r_m)
   double* Vt = take(c->C * rm, true);   // (L_m^T gbar_m)^T           (C x r_m)
   if (e == hipSuccess) e = launch_sketch(PSTT2_P_F64, 0, a, s);

@@ -64,7 +64,7 @@ struct Seg {
   const void* ptr;   // first entry of the run (column gcol0, row 0)
   int64_t gcol0;     // global column index of its first column
   int64_t ncols;     // number of columns
-  int64_t chunk0;    // index of its first 16-column chunk in the launch's chunk list
+  int64_t chunk0;    // index of its first chunk in the launch's chunk list (sketch_chunk_cols wide)
 };
 
 // Everything a sketch launch needs; passed by value as the kernel argument.
@@ -81,11 +81,14 @@ struct SketchArgs {
   int64_t psi_off[PSTT2_MAX_D];    // offset of psi_q (q = 1..d-1) at index q-1
   int64_t omega_off[PSTT2_MAX_D];  // offset of omega_q (q = 2..d) at index q-1
   void* ypart;       // [gj][c][row], ell columns
-  void* tpart;       // [gi][a][gcol], ell rows, indexed by global column; then kTPartPad spare entries
+  void* tpart;       // tlp == 0: [gi][a][gcol], ell rows; tlp > 0: [gi][gcol][tlp] (sketch index
+                     // contiguous); indexed by global column; then kTPartPad spare entries
+  int32_t tlp;       // layout of tpart (see above)
   int64_t C;         // columns of X_m (for the tpart stride)
   const double* om_tab;  // Omega_m(col, c) table, C x L4, FP64
   int32_t L4;            // its row stride: ell rounded up to a multiple of 4
   const double* psi_tab; // optional Psi(row, a) table, R x L4 (else products of the factors)
+  const uint16_t* om16;  // 16-bit precisions: Omega_m rounded per plane, [plane][c < LP][col]
   Seg seg[kMaxSeg];
   // Tensor given by a formula (FP64 kernel only): 0 = X read from the
   // segments; 1 = Hilbert tensor, X(row, col) = fn_rec[fn_row[row] + fn_col[col]]
@@ -142,6 +145,13 @@ hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s);
 // read): every memory operation in the chunk loop is then unconditional, which
 // lets the compiler wait only for the loads it needs.
 constexpr int64_t kTPartPad = 2048;
+// 16-bit sketch precisions (plain BF16, FP16: 1 plane; split BF16: 3 planes; else 0)
+int omega16_planes(int prec);
+// Columns per chunk of the precision's sketch kernel (Seg::chunk0 counts these).
+int sketch_chunk_cols(int prec);
+// om16[(q LP + c) C + col] = plane q of Omega_m(col, c) rounded as the kernel uses it.
+hipError_t build_omega16_table(const double* om_tab, int64_t C, int L4, int ell, int LP, int prec, uint16_t* om16,
+                               hipStream_t s);
 // Build the Omega_m table (C x L4, FP64) from the factors.
 hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream_t s);
 // Per-precision launch geometry: rows of X_m per workgroup, threads per

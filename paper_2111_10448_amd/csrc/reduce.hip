@@ -23,17 +23,27 @@ __global__ void k_reduce_y(const P* __restrict__ yp, int gj_count, int64_t R, in
 // One launch covers every segment of a sketch launch (blockIdx.y = segment).
 // Each thread adds the gi partials of one entry in increasing g, sixteen loads
 // in flight: the order, and so the result, does not depend on the launch shape.
+// Offset of entry (a, col) in one row block's T partial and the stride between
+// row blocks, for both partial layouts (SketchArgs::tlp).
+__device__ __forceinline__ int64_t tpart_at(const SketchArgs& A, int a, int64_t col) {
+  return A.tlp ? col * A.tlp + a : (int64_t)a * A.C + col;
+}
+__device__ __forceinline__ int64_t tpart_stride(const SketchArgs& A) {
+  return A.tlp ? A.C * A.tlp : (int64_t)A.ell * A.C;
+}
+
 template <typename P>
 __global__ void k_reduce_t(const P* __restrict__ tp, const SketchArgs A, double* __restrict__ Tt, int* flag) {
   constexpr int U = 16;
   const int64_t gc0 = A.seg[blockIdx.y].gcol0, ncols = A.seg[blockIdx.y].ncols;
   const int ell = A.ell, gi = A.gi_count;
-  const int64_t C = A.C, st = (int64_t)ell * C;
+  const int64_t C = A.C, st = tpart_stride(A);
   const int64_t tot = ncols * ell;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-    const int a = (int)(i / ncols);
-    const int64_t col = gc0 + i % ncols;
-    const P* p = tp + (int64_t)a * C + col;
+    // sketch index fastest for the contiguous layout, column fastest otherwise (coalesced reads)
+    const int a = (int)(A.tlp ? i % ell : i / ncols);
+    const int64_t col = gc0 + (A.tlp ? i / ell : i % ncols);
+    const P* p = tp + tpart_at(A, a, col);
     double s = Tt[(int64_t)a * C + col];
     int g = 0;
     for (; g + U <= gi; g += U) {
@@ -60,14 +70,14 @@ __global__ void k_reduce_t_split(const P* __restrict__ tp, const SketchArgs A, i
                                  double* __restrict__ out) {
   const int64_t gc0 = A.seg[seg].gcol0, ncols = A.seg[seg].ncols;
   const int ell = A.ell, gi = A.gi_count;
-  const int64_t C = A.C, st = (int64_t)ell * C;
+  const int64_t C = A.C, st = tpart_stride(A);
   const int64_t tot = ncols * ell;
   const int sp = blockIdx.y;
   const int g0 = (int)((int64_t)sp * gi / nsplit), g1 = (int)((int64_t)(sp + 1) * gi / nsplit);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
     const int a = (int)(i / ncols);
     const int64_t col = gc0 + i % ncols;
-    const P* p = tp + (int64_t)a * C + col;
+    const P* p = tp + tpart_at(A, a, col);
     double sum = 0.0;
     for (int g = g0; g < g1; ++g) sum += (double)p[(int64_t)g * st];
     out[(int64_t)sp * tot + i] = sum;

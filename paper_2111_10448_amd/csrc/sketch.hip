@@ -31,7 +31,6 @@ namespace pstt2 {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef short s8 __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
@@ -97,26 +96,6 @@ struct Eng<P_F32> {
   using part = float;
   static constexpr int KPL = 1, KSTEP = 4, RW = 128, VEC = 4, PAD = 4, NPL = 1;
 };
-template <>
-struct Eng<P_BF16> {
-  using elem = float;
-  using lds_t = uint32_t;  // bf16 in the low half, converted once when staged
-  using acc = float;
-  using accv = f4;
-  using part = float;
-  static constexpr int KPL = 4, KSTEP = 16, RW = 128, VEC = 4, PAD = 4, NPL = 1;
-};
-// FP16: as BF16, with IEEE half precision (11-bit significand, range 6.1e-5 ..
-// 65504; larger values become infinite and are reported as non-finite sketches).
-template <>
-struct Eng<P_F16> {
-  using elem = float;
-  using lds_t = uint32_t;  // half in the low half, converted once when staged
-  using acc = float;
-  using accv = f4;
-  using part = float;
-  static constexpr int KPL = 4, KSTEP = 16, RW = 128, VEC = 4, PAD = 4, NPL = 1;
-};
 // Split BF16: X and the DRM are split into three bf16 terms once, when they
 // are staged in LDS (three planes); the six products of order <= 2 are summed.
 template <>
@@ -171,32 +150,12 @@ __device__ __forceinline__ typename Eng<PREC>::lds_t drm_to_lds(double v) {
   else return (float)v;
 }
 
-// One-term 16-bit formats (plain BF16 and FP16): round-to-nearest-even bit
-// pattern of an FP32 value, and the 16x16x16 product with FP32 accumulation.
-typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-template <int PREC>
-__device__ __forceinline__ uint32_t to16(float f) {
-  if constexpr (PREC == P_F16) return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
-  else return bf16_rne(f);
-}
-template <int PREC>
-__device__ __forceinline__ f4 mfma16(s4 a, s4 b, f4 c) {
-  if constexpr (PREC == P_F16)
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b), c, 0, 0, 0);
-  else return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-
 // Row of element v of a lane's 16x16 MFMA accumulator tile (column = lane % 16).
 // FP64 16x16x4 places element v at row 4*v + lane/16; the FP32-accumulating
 // 16x16 instructions at row 4*(lane/16) + v.
 template <int PREC>
 __device__ __forceinline__ int acc_row(int g4, int v) {
   return PREC == P_F64 ? 4 * v + g4 : 4 * g4 + v;
-}
-
-__device__ __forceinline__ void unpack4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, s4& hi, s4& lo) {
-  hi = s4{(short)(a & 0xffff), (short)(b & 0xffff), (short)(c & 0xffff), (short)(d & 0xffff)};
-  lo = s4{(short)(a >> 16), (short)(b >> 16), (short)(c >> 16), (short)(d >> 16)};
 }
 
 // Psi_m(row, a) for a global row of X_m (0 outside the matrix / sketch).
@@ -340,18 +299,11 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
       const int a = 16 * mt + l16;
       if constexpr (E::KPL == 1) {
         psiA[ks][mt] = drm_to_lds<PREC>(psi_row(A, row0w + E::KSTEP * ks + g4, a));
-      } else if constexpr (X3) {
+      } else {
         float p[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) p[v] = (float)psi_row(A, row0w + 16 * ks + 4 * g4 + v, a);
         split3x4(p[0], p[1], p[2], p[3], psiA[ks][mt], psiM[ks][mt], psiL[ks][mt]);
-      } else {
-        uint32_t p[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) p[v] = to16<PREC>((float)psi_row(A, row0w + 16 * ks + 4 * g4 + v, a));
-        s4 hi, lo;
-        unpack4(p[0], p[1], p[2], p[3], hi, lo);
-        psiA[ks][mt] = hi;
       }
     }
   }
@@ -397,10 +349,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     const int e = 2 * threadIdx.x;
     if (UNC && !omok) omv = double2{0.0, 0.0};
     if (e < KC * LP) {
-      if constexpr (PREC == P_BF16 || PREC == P_F16) {
-        Om[buf][e] = to16<PREC>((float)omv.x);
-        Om[buf][e + 1] = to16<PREC>((float)omv.y);
-      } else if constexpr (X3) {
+      if constexpr (X3) {
         uint32_t t0, t1, t2;
         split3_pk((float)omv.x, (float)omv.y, t0, t1, t2);
         *(uint32_t*)&Om[buf][e] = t0;
@@ -466,10 +415,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
       }
       const int cc = i * (64 * VEC / RW) + lane / (RW / VEC);
       const int r = (lane % (RW / VEC)) * VEC;
-      if constexpr (PREC == P_BF16 || PREC == P_F16) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) Xl[w][cc * ST + r + v] = to16<PREC>(xr[slot][i][v]);
-      } else if constexpr (X3) {
+      if constexpr (X3) {
         uint32_t a0, a1, a2, b0, b1, b2;
         split3_pk(xr[slot][i][0], xr[slot][i][1], a0, a1, a2);
         split3_pk(xr[slot][i][2], xr[slot][i][3], b0, b1, b2);
@@ -592,7 +538,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
         y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, w1, y, 0, 0, 0);
         y32[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, w0, y, 0, 0, 0);
       }
-    } else if constexpr (X3) {
+    } else {
       // six products t_i * t_j with i + j <= 2, smallest first
       s4 b0[NT], b1[NT], b2[NT];
 #pragma unroll
@@ -617,21 +563,6 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
           yacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0[nt], y, 0, 0, 0);
         }
       }
-    } else {
-      s4 bh[NT], bl[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-        unpack4(om[(4 * g4 + 0) * LP + 16 * nt + l16], om[(4 * g4 + 1) * LP + 16 * nt + l16],
-                om[(4 * g4 + 2) * LP + 16 * nt + l16], om[(4 * g4 + 3) * LP + 16 * nt + l16], bh[nt], bl[nt]);
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        s4 ah, al;
-        const int r = 16 * mt + l16;
-        unpack4(xw[(4 * g4 + 0) * ST + r], xw[(4 * g4 + 1) * ST + r], xw[(4 * g4 + 2) * ST + r],
-                xw[(4 * g4 + 3) * ST + r], ah, al);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) yacc[mt][nt] = mfma16<PREC>(ah, bh[nt], yacc[mt][nt]);
-      }
     }
     // left sketch: T(ell, cols) = Psi(rows, ell)^T X(rows, cols)
     accv tacc[NT];
@@ -640,9 +571,7 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     if constexpr (X3) {
       // split BF16: two 16-row K steps per 16x16x32 instruction (rows
       // 32j + 4 g4 + v and 32j + 16 + 4 g4 + v in the two halves of an
-      // operand), half the instructions of the 16x16x16 form.  (Plain BF16
-      // keeps 16x16x16: its matrix cores are mostly idle, and pairing there
-      // only adds register pressure.)
+      // operand), half the instructions of the 16x16x16 form
       static_assert(KT % 2 == 0, "pairs of 16-row K steps");
 #pragma unroll
       for (int j = 0; j < KT / 2; ++j) {
@@ -670,21 +599,13 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
     } else {
 #pragma unroll
       for (int ks = 0; ks < KT; ++ks) {
-        if constexpr (E::KPL == 1) {
-          const lds_t b = xw[l16 * ST + 4 * ks + g4];
+        const lds_t b = xw[l16 * ST + 4 * ks + g4];
 #pragma unroll
-          for (int mt = 0; mt < NT; ++mt) {
-            if constexpr (PREC == P_F64)
-              tacc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
-            else
-              tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
-          }
-        } else {
-          const u4 q = *(const u4*)&xw[l16 * ST + 16 * ks + 4 * g4];
-          s4 bh, bl;
-          unpack4(q.x, q.y, q.z, q.w, bh, bl);
-#pragma unroll
-          for (int mt = 0; mt < NT; ++mt) tacc[mt] = mfma16<PREC>(psiA[ks][mt], bh, tacc[mt]);
+        for (int mt = 0; mt < NT; ++mt) {
+          if constexpr (PREC == P_F64)
+            tacc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
+          else
+            tacc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(psiA[ks][mt], b, tacc[mt], 0, 0, 0);
         }
       }
     }
@@ -731,6 +652,362 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
           if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = (part)yacc[mt][nt][v];
         }
   }
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit sketch kernels for FP32 tensors: plain BF16, FP16 and split BF16
+// (three bf16 planes).  Workgroup = NW waves; a wave owns 64 rows of X_m and
+// the workgroup a contiguous share of 32-column chunks.  Per chunk a lane
+// loads eight 16-byte fragments: rows 16 rt + 4 (l / 16) .. + 3 of column
+// 16 ct + l % 16 (rt < 4, ct < 2), which is exactly the B operand of the
+// 16 x 16 x 16 product for the left sketch T = Psi^T X (K = rows).  So:
+//   * the left sketch runs straight from the converted load registers (two
+//     16-row fragments joined into one 32-deep operand, Psi joined the same
+//     way, so element v of every lane pairs the same row in both operands);
+//   * the right sketch Y = X Omega needs K = columns: the converted fragments
+//     are written to a wave-private column-major LDS tile (one 8-byte store
+//     each) and read back with the transposing 16-bit LDS read, which hands
+//     each lane one row and four consecutive columns (lane i of a 16-lane
+//     group receives element e from the address of lane 4 e + i / 4 at
+//     half-word i % 4);
+//   * the Omega operands come pre-rounded (per plane) from a 16-bit table
+//     (L2-resident), loaded into registers one chunk ahead by every wave;
+//   * FP32 -> 16-bit conversion is the hardware packed conversion (round to
+//     nearest even), two values per instruction; split BF16 takes the exact
+//     three-term split of each value (t0 + t1 + t2).
+// Raw X of two chunks is in flight per wave (register double buffer, every
+// load unconditional: out-of-range entries read a valid address and are
+// zeroed when converted).  There is no workgroup barrier in the chunk loop:
+// the waves' T tiles of a chunk go to one of NS LDS slots, each wave then
+// counts itself in with an LDS atomic, and the last wave to arrive adds the
+// NW tiles in increasing wave order (the same order whichever wave it is, so
+// the result is deterministic), writes the T partial and releases the slot
+// (a generation count the waves check before reusing it).  Waves therefore
+// drift freely, up to NS chunks apart.
+// ---------------------------------------------------------------------------
+constexpr int KC16 = 32;   // columns per chunk
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+template <int PREC>
+__device__ __forceinline__ uint32_t cvt_pk16(float a, float b) {
+  const f2v v = {a, b};
+  if constexpr (PREC == P_F16) return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, h2v));
+  else return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf2v));
+}
+
+// 32-deep product of two joined operands with FP32 accumulation
+template <int PREC>
+__device__ __forceinline__ f4 mfma32(s4 alo, s4 ahi, s4 blo, s4 bhi, f4 c) {
+  const s8 a = __builtin_shufflevector(alo, ahi, 0, 1, 2, 3, 4, 5, 6, 7);
+  const s8 b = __builtin_shufflevector(blo, bhi, 0, 1, 2, 3, 4, 5, 6, 7);
+  if constexpr (PREC == P_F16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), c, 0, 0, 0);
+}
+
+// Four FP32 values (zeroed where bit v of ok is clear) -> four 16-bit values.
+template <int PREC>
+__device__ __forceinline__ s4 cvt4(float4 x, uint32_t ok) {
+  const float a = (ok & 1) ? x.x : 0.0f, b = (ok & 2) ? x.y : 0.0f, c = (ok & 4) ? x.z : 0.0f,
+              d = (ok & 8) ? x.w : 0.0f;
+  return __builtin_bit_cast(s4, uint2{cvt_pk16<PREC>(a, b), cvt_pk16<PREC>(c, d)});
+}
+
+typedef __attribute__((address_space(3))) s4 lds_s4;
+
+// Chunk geometry for 32-column chunks, visited in increasing order (segments
+// hold chunk0 counted in 32-column chunks): forward-only segment cursor.
+struct Cursor16 {
+  int sg = 0;
+  template <bool SEG1>
+  __device__ __forceinline__ ChunkInfo at(const SketchArgs& A, int64_t ci) {
+    if constexpr (!SEG1) {
+      while (sg + 1 < A.nseg && A.seg[sg + 1].chunk0 <= ci) ++sg;
+    }
+    ChunkInfo c;
+    c.ptr = (const char*)A.seg[sg].ptr;
+    c.lcol0 = (ci - A.seg[sg].chunk0) * KC16;
+    c.gcol0 = A.seg[sg].gcol0 + c.lcol0;
+    const int64_t left = A.seg[sg].ncols - c.lcol0;
+    c.ncols = (int)(left < KC16 ? left : KC16);
+    return c;
+  }
+};
+
+template <int PREC, int LP, int NW, int NS, bool ALIGNED, bool SEG1>
+__global__ __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) void k_sketch16(const SketchArgs A) {
+  constexpr int RT = 4;                 // 16-row tiles per wave (64 rows)
+  constexpr int CT = KC16 / 16;         // 16-column tiles per chunk
+  constexpr int NT = LP / 16;           // sketch-column tiles
+  constexpr int XS = 64 + 8;            // column stride of the LDS X tile (16-bit words)
+  constexpr int TS = LP + 4;            // column stride of the T tiles (floats; sketch index contiguous)
+  __shared__ __align__(16) uint16_t Xl[NW][KC16 * XS];
+  // stationary Psi operands, in LDS (each lane reads back its own), sparing the
+  // registers for two chunks of X in flight
+  __shared__ __align__(16) s4 Pl[NW][RT][NT][64];
+  __shared__ __align__(16) float Tred[NS][NW][KC16 * TS];
+  __shared__ int arrived[NS];   // waves that have written their tile of the slot's chunk
+  __shared__ int released[NS];  // times the slot has been summed and freed
+
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int gi = blockIdx.x % A.gi_count;
+  const int gj = blockIdx.x / A.gi_count;
+  const int64_t row0w = (int64_t)gi * (NW * 64) + (int64_t)w * 64;
+  const int64_t cb = (int64_t)gj * A.nchunks / A.gj_count;
+  const int64_t ce = (int64_t)(gj + 1) * A.nchunks / A.gj_count;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  if (threadIdx.x < NS) {
+    arrived[threadIdx.x] = 0;
+    released[threadIdx.x] = 0;
+  }
+
+  // ---- stationary left-DRM operands Psi(row0w + 16 rt + 4 g4 + v, 16 mt + l16) ----
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      float p[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) p[v] = (float)psi_row(A, row0w + 16 * rt + 4 * g4 + v, 16 * mt + l16);
+      Pl[w][rt][mt][lane] = cvt4<PREC>(float4{p[0], p[1], p[2], p[3]}, 0xfu);
+    }
+  __syncthreads();   // the slot counters are zero
+
+  Cursor16 cx, co, ct_;   // X loads (two ahead), Omega loads (one ahead), T partial stores
+
+  // ---- raw X of a chunk (two register slots) and its validity bits ----
+  float4 xr[2][RT][CT];
+  uint32_t xok[2];
+  auto load_chunk = [&](int64_t ci, int slot) {
+    const ChunkInfo ch = cx.at<SEG1>(A, ci < ce ? ci : ce - 1);
+    const float* base = (const float*)ch.ptr;
+    uint32_t ok = 0;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int cc = 16 * ct + l16;
+        const int64_t row = row0w + 16 * rt + 4 * g4;
+        const bool colok = cc < ch.ncols;
+        const float* col = base + (ch.lcol0 + (colok ? cc : 0)) * A.R;
+        const int bit = 4 * (rt * CT + ct);
+        if constexpr (ALIGNED) {   // R % 4 == 0: the four rows are in or out together
+          const bool in = colok && row < A.R;
+          xr[slot][rt][ct] = *(const float4*)(col + (in ? row : 0));
+          ok |= (in ? 0xfu : 0u) << bit;
+        } else {
+          float v4[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bool in = colok && row + v < A.R;
+            v4[v] = col[in ? row + v : 0];
+            ok |= (in ? 1u : 0u) << (bit + v);
+          }
+          xr[slot][rt][ct] = float4{v4[0], v4[1], v4[2], v4[3]};
+        }
+      }
+    xok[slot] = ok;
+  };
+
+  // ---- Omega operands of a chunk: lane (g4, l16), tile nt, K step ks holds
+  //      Omega(columns 16 ks + 4 g4 .. + 3, sketch column 16 nt + l16) ----
+  s4 ob[NT][2];
+  auto load_omega = [&](int64_t ci) {
+    const ChunkInfo ch = co.at<SEG1>(A, ci < ce ? ci : ce - 1);
+    const bool al = ((A.C | ch.gcol0) & 3) == 0 && ch.ncols == KC16;   // aligned 8-byte loads
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const int col = 16 * ks + 4 * g4;
+        const uint16_t* src = A.om16 + (int64_t)(16 * nt + l16) * A.C + ch.gcol0;
+        if (al) {
+          ob[nt][ks] = *(const s4*)(src + col);
+        } else {
+          short v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const bool in = col + j < ch.ncols;
+            const uint16_t u = src[in ? col + j : 0];
+            v[j] = in ? (short)u : (short)0;
+          }
+          ob[nt][ks] = s4{v[0], v[1], v[2], v[3]};
+        }
+      }
+  };
+
+  f4 yacc[RT][NT];
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) yacc[mt][nt] = f4{0, 0, 0, 0};
+
+  if (cb < ce) {
+    load_chunk(cb, 0);
+    load_chunk(cb + 1, 1);
+    load_omega(cb);
+  }
+
+  auto chunk_step = [&](int64_t ci, int it, int slot) {
+    // (a) convert this chunk's fragments; write them to the wave's LDS tile
+    s4 fx[RT][CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        fx[rt][ct] = cvt4<PREC>(xr[slot][rt][ct], xok[slot] >> (4 * (rt * CT + ct)));
+        *(s4*)&Xl[w][(16 * ct + l16) * XS + 16 * rt + 4 * g4] = fx[rt][ct];
+      }
+    // (b) prefetch chunk ci + 2 into the slot just converted
+    load_chunk(ci + 2, slot);
+    // (c) left sketch from the registers: T(16 mt + .., 16 ct + l16), K = the wave's 64 rows
+    f4 tacc[CT][NT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) {
+        f4 t = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < RT / 2; ++j) {
+          const int ka = 2 * j, kb = 2 * j + 1;
+          t = mfma32<PREC>(Pl[w][ka][mt][lane], Pl[w][kb][mt][lane], fx[ka][ct], fx[kb][ct], t);
+        }
+        tacc[ct][mt] = t;
+      }
+    // (d) right sketch: X rows from the LDS tile (transposing reads)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int mt = 0; mt < RT; ++mt) {
+      s4 xa[2];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+        xa[ks] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_s4*)&Xl[w][(16 * ks + 4 * g4 + (l16 >> 2)) * XS + 16 * mt + 4 * (l16 & 3)]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        yacc[mt][nt] = mfma32<PREC>(xa[0], xa[1], ob[nt][0], ob[nt][1], yacc[mt][nt]);
+    }
+    // Omega operands of the next chunk (needed only at its right sketch)
+    load_omega(ci + 1);
+    // (e) this wave's T tile into slot it % NS once the slot's previous chunk
+    //     has been summed (bounded wait: see the kernel comment)
+    const int sl = it % NS;
+    const int gen = it / NS;
+    while (__hip_atomic_load(&released[sl], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < gen)
+      __builtin_amdgcn_s_sleep(1);
+    // element v of tacc[ct][mt] is T(16 mt + 4 g4 + v, 16 ct + l16): four consecutive
+    // sketch rows of one column, one 16-byte store
+    float* tr = Tred[sl][w];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) *(f4*)&tr[(16 * ct + l16) * TS + 16 * mt + 4 * g4] = tacc[ct][mt];
+    int before = 0;
+    if (lane == 0)
+      before = __hip_atomic_fetch_add(&arrived[sl], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+    before = __builtin_amdgcn_readfirstlane(before);
+    if (before == NW - 1) {
+      // last to arrive: every wave's tile is in the slot
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // four consecutive sketch rows of one column per item, 16-byte LDS reads and
+      // stores into the T partial [row block][column][LP] (sketch index contiguous)
+      const ChunkInfo ch = ct_.at<SEG1>(A, ci);
+      float* tp = (float*)A.tpart;
+      const int64_t spare = (int64_t)A.gi_count * A.C * LP;
+      constexpr int NA = LP / 4;   // four-row groups per column
+#pragma unroll 2
+      for (int q = 0; q < KC16 * NA / 64; ++q) {
+        const int item = lane + 64 * q;
+        const int col = item / NA, a4 = 4 * (item % NA);
+        f4 sum = *(const f4*)&Tred[sl][0][col * TS + a4];
+#pragma unroll
+        for (int ww = 1; ww < NW; ++ww) sum += *(const f4*)&Tred[sl][ww][col * TS + a4];
+        const bool ok = col < ch.ncols;
+        *(f4*)&tp[ok ? ((int64_t)gi * A.C + ch.gcol0 + col) * LP + a4 : spare + 4 * item] = sum;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) {
+        __hip_atomic_store(&arrived[sl], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&released[sl], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    } else {
+      (void)ct_.at<SEG1>(A, ci);   // keep the cursor in step
+    }
+  };
+
+  int it = 0;
+  int64_t ci = cb;
+  for (; ci + 1 < ce; ci += 2, it += 2) {
+    chunk_step(ci, it, 0);
+    chunk_step(ci + 1, it + 1, 1);
+  }
+  if (ci < ce) chunk_step(ci, it, 0);
+
+  // ---- right-sketch partial of this workgroup: element v of yacc[mt][nt] at
+  //      (row 16 mt + 4 g4 + v, sketch column 16 nt + l16) ----
+  float* yp = (float*)A.ypart;
+#pragma unroll
+  for (int mt = 0; mt < RT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0w + 16 * mt + 4 * g4 + v;
+        const int c = 16 * nt + l16;
+        if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = yacc[mt][nt][v];
+      }
+}
+
+// Omega_m rounded to the 16-bit arithmetic: om16[c C + col] = Omega_m(col, c)
+// (zero for c >= ell).  Same rounding (FP64 -> FP32 -> 16 bits, nearest even)
+// as the effective DRM the middle core uses.
+__global__ void k_omega16_table(const double* __restrict__ om_tab, int64_t C, int L4, int ell, int LP, int prec,
+                                uint16_t* __restrict__ om16) {
+  const int64_t tot = (int64_t)LP * C;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t / C);
+    const int64_t col = t % C;
+    const float f = c < ell ? (float)om_tab[col * L4 + c] : 0.0f;
+    om16[t] = (uint16_t)(prec == P_F16 ? cvt_pk16<P_F16>(f, 0.0f) : cvt_pk16<P_BF16>(f, 0.0f));
+  }
+}
+
+hipError_t build_omega16_table(const double* om_tab, int64_t C, int L4, int ell, int LP, int prec, uint16_t* om16,
+                               hipStream_t s) {
+  const int64_t tot = (int64_t)LP * C;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 16384));
+  hipLaunchKernelGGL(k_omega16_table, dim3(g), dim3(256), 0, s, om_tab, C, L4, ell, LP, prec, om16);
+  return hipGetLastError();
+}
+
+// The one-term 16-bit formats run on k_sketch16.  Split BF16 stays on k_sketch:
+// its six products per element keep the matrix cores busy enough that the
+// barrier-per-chunk kernel with two workgroups per compute unit measured
+// faster (1.3 against 1.7 ms at d = 5, n = 64) than k_sketch16 at the one
+// workgroup per compute unit its register and LDS use allow.
+int omega16_planes(int prec) { return (prec == P_BF16 || prec == P_F16) ? 1 : 0; }
+
+constexpr int kNW16 = 4;   // waves per 16-bit sketch workgroup
+constexpr int kNS16 = 2;   // T-tile slots in flight per workgroup
+
+template <int PREC, int LP>
+static hipError_t launch_16(const SketchArgs& a, bool aligned, hipStream_t s) {
+  dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(kNW16 * 64);
+  const bool seg1 = a.nseg == 1 && a.seg[0].chunk0 == 0;
+  if (!a.om16) return hipErrorInvalidValue;
+  if (aligned) {
+    if (seg1) hipLaunchKernelGGL((k_sketch16<PREC, LP, kNW16, kNS16, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_sketch16<PREC, LP, kNW16, kNS16, true, false>), grid, block, 0, s, a);
+  } else {
+    if (seg1) hipLaunchKernelGGL((k_sketch16<PREC, LP, kNW16, kNS16, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_sketch16<PREC, LP, kNW16, kNS16, false, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1018,16 +1295,22 @@ hipError_t build_omega_table(const SketchArgs& a, int L4, double* tab, hipStream
   return hipGetLastError();
 }
 
+int sketch_chunk_cols(int prec) { return omega16_planes(prec) ? KC16 : KC; }
+
 void sketch_geometry(int prec, int ell, int* rows_per_block, int* threads, int* wg_per_cu) {
   const int L4 = (ell + 3) / 4 * 4;
+  if (omega16_planes(prec)) {
+    *rows_per_block = kNW16 * 64;
+    *threads = kNW16 * 64;
+    *wg_per_cu = 2;
+    return;
+  }
   *threads = prec == P_F64 ? nwf_for(L4) * 64 : NWS * 64;
   // FP64: see nwf_for; the FP32-family kernels always fit two workgroups
   *wg_per_cu = prec == P_F64 ? f64_wg_per_cu(L4) : 2;
   switch (prec) {
     case P_F64: *rows_per_block = nwf_for(L4) * Eng<P_F64>::RW; break;
     case P_F32: *rows_per_block = NWS * Eng<P_F32>::RW; break;
-    case P_BF16: *rows_per_block = NWS * Eng<P_BF16>::RW; break;
-    case P_F16: *rows_per_block = NWS * Eng<P_F16>::RW; break;
     default: *rows_per_block = NWS * Eng<P_BF16X3>::RW; break;
   }
 }
@@ -1069,10 +1352,10 @@ hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s) {
   switch (prec * 100 + lp) {
     case P_F32 * 100 + 16: return launch_t<P_F32, 16>(a, aligned, s);
     case P_F32 * 100 + 32: return launch_t<P_F32, 32>(a, aligned, s);
-    case P_BF16 * 100 + 16: return launch_t<P_BF16, 16>(a, aligned, s);
-    case P_BF16 * 100 + 32: return launch_t<P_BF16, 32>(a, aligned, s);
-    case P_F16 * 100 + 16: return launch_t<P_F16, 16>(a, aligned, s);
-    case P_F16 * 100 + 32: return launch_t<P_F16, 32>(a, aligned, s);
+    case P_BF16 * 100 + 16: return launch_16<P_BF16, 16>(a, aligned, s);
+    case P_BF16 * 100 + 32: return launch_16<P_BF16, 32>(a, aligned, s);
+    case P_F16 * 100 + 16: return launch_16<P_F16, 16>(a, aligned, s);
+    case P_F16 * 100 + 32: return launch_16<P_F16, 32>(a, aligned, s);
     case P_BF16X3 * 100 + 16: return launch_t<P_BF16X3, 16>(a, aligned, s);
     case P_BF16X3 * 100 + 32: return launch_t<P_BF16X3, 32>(a, aligned, s);
     default: return hipErrorInvalidValue;
