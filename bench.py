@@ -14,10 +14,15 @@ sketch size 20.  Inputs are synthetic and seeded (inputs/).
 Prints one JSON line.  `value` is whole-step throughput (bytes of X per step
 time; X is read twice per step: sketch and error).  `roofline` covers the
 dominant kernel (the streaming sketch), timed with HIP events on the stream it
-runs on.  `cpu_baseline` times the CPU FP64 oracle on a bounded sub-tensor.
+runs on, with the rate of a plain read-and-sum over the same bytes beside it.
+`cpu_baseline` times the CPU FP64 oracle on a bounded sub-tensor (sketches,
+recovery and error pass separately), runs the GPU path on the same sub-tensor
+and reports the element-wise sketch differences, ranks and error against the
+oracle's, and times the oracle on C1 and C5 with one thread.
 Unless --no-variants: the two-sided middle core, the independent DRM scheme,
-the precision study, the 64-slab stream, the adjoint, and Table 1's Hilbert
-tensors evaluated inside the kernels (never stored).
+the precision study (FP64, FP32, split BF16, BF16, FP16), the 64-slab stream,
+C1 and C5, the adjoint, Table 1's Hilbert tensors evaluated inside the kernels
+(never stored) and the Gaussian bumps.
 """
 from __future__ import annotations
 
@@ -69,12 +74,16 @@ def traffic_from_profiles(workload: str, launches_per_step: int):
     return float(b.group(1))
 
 
-def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 30.0):
-    """Time the oracle (sketches + recovery + error) on a leading block of the same tensor.
+def cpu_baseline(x: np.ndarray, w, psi, omega, prec: str, target_s: float = 30.0):
+    """Time the oracle (sketches, recovery, error pass) on a leading block of the same tensor.
 
     The sample keeps modes 1..d-1 whole and the first s slices of mode d (a
     contiguous prefix of the column-major array).  A short probe at s = 1
-    sizes s so that the timed oracle run takes about `target_s` seconds.
+    sizes s so that the timed oracle run takes about `target_s` seconds.  The
+    GPU path then runs on the same sample: its right and left sketches of the
+    middle unfolding, ranks and relative error are compared with the oracle's
+    (parity on the benchmarked configuration).  Last, the oracle on the small
+    configurations C1 and C5 with one BLAS thread.
     """
     from oracle import tt_sketch as O
     try:
@@ -90,21 +99,100 @@ def cpu_baseline(x: np.ndarray, w, psi, omega, target_s: float = 30.0):
         sub = np.asarray(x[:slab * s], dtype=np.float64)
         psi_s = {q: psi[q][:ns[q - 1]] for q in psi}
         om_s = {q: omega[q][:ns[q - 1]] for q in omega}
-        t0 = time.perf_counter()
-        out = O.pstt2(sub, ns, O.NestedKR(psi_s, om_s), ranks=w.ranks())
+        tm = {}
+        out = O.pstt2(sub, ns, O.NestedKR(psi_s, om_s), ranks=w.ranks(), timings=tm)
         t1 = time.perf_counter()
         err = O.tt_error(sub, out["cores"])
-        t2 = time.perf_counter()
-        return ns, sub.nbytes, t1 - t0, t2 - t1, err
+        tm["error_s"] = time.perf_counter() - t1
+        return ns, sub, psi_s, om_s, out, tm, err
 
-    _, nb1, a1, b1, _ = run(1)
-    per_byte = (a1 + b1) / nb1
-    s = int(max(1, min(n[-1], round(target_s / (per_byte * nb1)))))
-    ns, nb, ta, tb, err = run(s)
-    gbs = nb / (ta + tb) / 1e9
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"leading block n={tuple(ns)} ({nb // 8} entries, {nb / 1e9:.2f} GB FP64) of the same "
-                      f"tensor: oracle sketches+recovery {ta:.1f} s, error pass {tb:.1f} s, rel. error {err:.3e}"}
+    _, sub1, _, _, _, tm1, _ = run(1)
+    per_byte = sum(tm1.values()) / sub1.nbytes
+    s = int(max(1, min(n[-1], round(target_s / (per_byte * sub1.nbytes)))))
+    ns, sub, psi_s, om_s, out, tm, err = run(s)
+    total = sum(tm.values())
+    nb = sub.nbytes
+    rec = {"value": round(nb / total / 1e9, 4), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"leading block n={tuple(ns)} ({nb // 8} entries, {nb / 1e9:.2f} GB FP64) of the same "
+                     f"tensor: oracle sketches {tm['sketch_s']:.1f} s, recovery {tm['recover_s']:.2f} s, "
+                     f"error pass {tm['error_s']:.1f} s, rel. error {err:.3e}",
+           "phases_s": {k: round(v, 3) for k, v in tm.items()}}
+    try:
+        rec["parity_on_sample"] = _sample_parity(x[:slab * s], ns, w, psi_s, om_s, out, err, prec)
+    except Exception as e:   # report, keep the baseline
+        rec["parity_on_sample"] = {"error": str(e)}
+    del sub
+    rec["one_thread"] = {}
+    for name in ("c1", "c5"):
+        try:
+            rec["one_thread"][name] = _oracle_one_thread(name)
+        except Exception as e:
+            rec["one_thread"][name] = {"error": str(e)}
+    return rec
+
+
+def _sample_parity(xs, ns, w, psi_s, om_s, ref, err_ref, prec):
+    """The GPU path on the oracle's sample: sketches of the middle unfolding element by
+    element, ranks, and the relative error, against the oracle's run on the same block."""
+    import torch
+    import inputs
+    import paper_2111_10448_amd as P
+    from oracle import tt_sketch as O
+    fac = inputs.pack_factors(psi_s, om_s, len(ns))
+    xg = torch.from_numpy(np.ascontiguousarray(xs)).to("cuda:0")
+    ctx = P.PSTT2(ns, w.ell, fac, dtype=w.dtype, prec=prec, ranks=w.ranks())
+    ctx.sketch(xg)
+    tt = ctx.recover()
+    e = tt.error(xg)
+    m = O.middle_index(len(ns))
+    y_ref, t_ref = ref["Y"], ref["T"][m].T
+    y, t = ctx.get_sketch(0, m), ctx.get_sketch(1, m)
+    out = {"Y_R_max_rel": float(np.max(np.abs(y - y_ref)) / np.max(np.abs(y_ref))),
+           "T_m_max_rel": float(np.max(np.abs(t - t_ref)) / np.max(np.abs(t_ref))),
+           "ranks_equal": list(tt.ranks[1:-1]) == [int(v) for v in ref["ranks"]],
+           "tt_rel_error_gpu": e, "tt_rel_error_oracle": err_ref, "tt_rel_error_abs_diff": abs(e - err_ref)}
+    tt.free()
+    ctx.close()
+    del xg
+    torch.cuda.empty_cache()
+    return out
+
+
+def _oracle_one_thread(name):
+    """The oracle on a whole small configuration with one BLAS thread (phases in ms)."""
+    import inputs
+    from oracle import tt_sketch as O
+    from threadpoolctl import threadpool_limits
+    w = inputs.WORKLOADS[name]
+    x = np.asarray(inputs.make_tensor(w), dtype=np.float64)
+    psi, omega = inputs.drm_factors(w)
+    with threadpool_limits(1):
+        tm = {}
+        out = O.pstt2(x, w.n, O.NestedKR(psi, omega), ranks=w.ranks(), timings=tm)
+        t1 = time.perf_counter()
+        err = O.tt_error(x, out["cores"])
+        tm["error_s"] = time.perf_counter() - t1
+    return {"workload": f"{name}: d={w.d} n={w.n[0]} ({x.size} entries)", "threads": 1,
+            "sketch_ms": round(tm["sketch_s"] * 1e3, 3), "recover_ms": round(tm["recover_s"] * 1e3, 3),
+            "error_ms": round(tm["error_s"] * 1e3, 3), "tt_rel_error": err}
+
+
+def read_reduce_gbs(nbytes: int, reps: int = 5) -> float:
+    """Achievable HBM read rate of a plain read-and-sum (torch's reduction) over nbytes, GB/s."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    a.sum()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        a.sum()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    del a
+    torch.cuda.empty_cache()
+    return nbytes / (ms * 1e-3) / 1e9
 
 
 _HOST = {}
@@ -384,8 +472,10 @@ def main():
                                        ("c3", "f32", "onepass", "nested", "pstt2"),
                                        ("c3", "bf16x3", "onepass", "nested", "pstt2"),
                                        ("c3", "bf16", "onepass", "nested", "pstt2"),
+                                       ("c3", "f16", "onepass", "nested", "pstt2"),
                                        ("c4", "f32", "onepass", "nested", "pstt2"),
-                                       ("c4", "bf16x3", "onepass", "nested", "pstt2")):
+                                       ("c4", "bf16x3", "onepass", "nested", "pstt2"),
+                                       ("c4", "f16", "onepass", "nested", "pstt2")):
             key = (f"{wn}_{vp}" + ("" if mid == "onepass" else f"_{mid}") + ("" if drm == "nested" else f"_{drm}")
                    + ("" if algo == "pstt2" else f"_{algo}"))
             try:
@@ -403,6 +493,16 @@ def main():
             except Exception as e:   # report, keep the headline line
                 var[key] = {"error": str(e)}
         record["variants"] = var
+        small = {}
+        for wn, vp in (("c1", "f64"), ("c5", "f32")):   # latency-bound: time only
+            try:
+                rv = run_workload(wn, vp, max(3, args.steps // 2), 1)
+                small[wn] = {"sketch_arithmetic": vp, "ms_per_step": round(rv["ms_per_step"], 4),
+                             "decompose_ms": round(rv["decomp_ms"], 4), "ranks": rv["ranks"],
+                             "tt_rel_error": rv["err"]}
+            except Exception as e:
+                small[wn] = {"error": str(e)}
+        record["small_configs"] = small
         try:
             record["adjoint"] = run_adjoint(max(3, args.steps // 2), 1)
         except Exception as e:
@@ -427,8 +527,12 @@ def main():
                 record[f"gauss_bumps_{pr}"] = run_function("gb_d3", max(3, args.steps // 2), 1, prec=pr)
             except Exception as e:
                 record[f"gauss_bumps_{pr}"] = {"error": str(e)}
+    try:
+        record["roofline"]["read_reduce_gbs"] = round(read_reduce_gbs(r["bytes"]), 1)
+    except Exception as e:
+        record["roofline"]["read_reduce_gbs"] = str(e)
     if not args.no_cpu_baseline:
-        record["cpu_baseline"] = cpu_baseline(r["x"], w, r["psi"], r["omega"])
+        record["cpu_baseline"] = cpu_baseline(r["x"], w, r["psi"], r["omega"], prec)
     print(json.dumps(record), flush=True)
 
 

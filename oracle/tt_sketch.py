@@ -48,6 +48,7 @@ Parity pins (tests/test_oracle_*.py):
 from __future__ import annotations
 
 import math
+import time
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -362,7 +363,7 @@ def _clamp_ranks(n, ranks, ell):
 
 def pstt2(x: np.ndarray, n: Sequence[int], drm, ranks: Optional[Sequence[int]] = None,
           eps: Optional[float] = None, rmax: int = 0, middle: str = "onepass",
-          dense_limit: int = 1 << 22) -> dict:
+          dense_limit: int = 1 << 22, timings: Optional[dict] = None) -> dict:
     """PSTT2 (two-pass) or PSTT2-onepass on a flat column-major FP64 tensor.
 
     drm: NestedKR / IndependentKR / DenseDRM.  Give ranks r_1..r_{d-1} (fixed
@@ -370,8 +371,11 @@ def pstt2(x: np.ndarray, n: Sequence[int], drm, ranks: Optional[Sequence[int]] =
     rmax and at ell - 2 so that the oversampling p >= 2 of Theorem 3 holds).
 
     Returns a dict with cores, ranks, bases Q (k < m) and P (k >= m), the
-    sketches S_k, T_k, Y_R and the middle index m.
+    sketches S_k, T_k, Y_R and the middle index m.  With a `timings` dict, the
+    wall time of the sketches and of the recovery (seconds) is stored in it
+    under "sketch_s" and "recover_s" (measurement only).
     """
+    t_start = time.perf_counter()
     x = np.asarray(x, dtype=np.float64).reshape(-1)
     n = tuple(int(v) for v in n)
     d = len(n)
@@ -381,6 +385,7 @@ def pstt2(x: np.ndarray, n: Sequence[int], drm, ranks: Optional[Sequence[int]] =
     s_sk = {k: _right_sketch(x, n, k, drm, dense_limit) for k in range(1, m)}
     t_sk = {k: _left_sketch(x, n, k, drm, dense_limit) for k in range(m, d)}
     y_r = _right_sketch(x, n, m, drm, dense_limit) if middle in ("onepass", "twosided") else None
+    t_sketched = time.perf_counter()
 
     if ranks is None:
         if eps is None:
@@ -425,6 +430,9 @@ def pstt2(x: np.ndarray, n: Sequence[int], drm, ranks: Optional[Sequence[int]] =
         cores[m - 1] = middle_core_twopass(x, n, q[m - 1], p[m], m)
     else:
         raise ValueError(middle)
+    if timings is not None:
+        timings["sketch_s"] = t_sketched - t_start
+        timings["recover_s"] = time.perf_counter() - t_sketched
     return {"cores": cores, "ranks": ranks, "m": m, "Q": q, "P": p, "S": s_sk, "T": t_sk,
             "Y": y_r, "piv": piv}
 

@@ -3,9 +3,11 @@
 A deterministic second reference for the PSTT2 oracle: reference ranks and
 errors on the same inputs.
 
-Parity pins (tests/test_oracle_ttsvd.py): exact recovery of exact-rank TTs;
-the error bound ||X - X~||_F <= eps ||X||_F of Section 2.2; Parallel-TTSVD
-(Algorithm Parallel-TTSVD) reaching the same bound (Theorem 2).
+Parity pins (tests/test_oracle_pstt2.py: test_ttsvd_exact_and_bound and
+test_inverse_sum_is_low_rank): exact recovery of exact-rank TTs; the error
+bound ||X - X~||_F <= eps ||X||_F of Section 2.2; Parallel-TTSVD (Algorithm
+Parallel-TTSVD) reaching the same bound (Theorem 2).  The GPU Parallel-TTSVD
+is compared with parallel_ttsvd in tests/test_gpu_ttsvd.py.
 """
 from __future__ import annotations
 

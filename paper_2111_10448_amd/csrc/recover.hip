@@ -1174,8 +1174,10 @@ hipError_t middle_ls(const double* Z, int64_t nz, const double* A, int rm, int e
 // Two-pass middle core over a slab of X (flat entries [first, first+count)):
 // G(a, i, b) += sum Qprev(row', a) X(row' + Rp i, col') Pm(col', b).
 // One block per (i, col') fibre present in the slab; FP64.  Used when X_m has a
-// single column (the one-sided algorithm's last core, Pm = 1); otherwise the
-// two fixed-order kernels below.
+// single column (the one-sided algorithm's last core, Pm = 1), where col' = 0
+// and each block owns its own i: a block adds its fibre's share into G with a
+// plain read-modify-write (slabs are applied in stream order), so the result
+// is bitwise repeatable.  Otherwise the two fixed-order kernels below.
 template <typename T>
 __global__ __launch_bounds__(256) void k_middle_twopass(const T* __restrict__ x, int64_t first, int64_t count,
                                                         int64_t Rp, int nm, int64_t Cm, const double* __restrict__ Qp,
@@ -1204,10 +1206,9 @@ __global__ __launch_bounds__(256) void k_middle_twopass(const T* __restrict__ x,
   __syncthreads();
   if (threadIdx.x < rp) za[threadIdx.x] = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
   __syncthreads();
-  // every block with the same i adds into G(:, i, :): FP64 atomics
   for (int t = threadIdx.x; t < rp * rm; t += blockDim.x) {
     const int a = t % rp, b = t / rp;
-    atomicAdd(&G[a + (int64_t)rp * (i + (int64_t)nm * b)], za[a] * Pm[(int64_t)b * Cm + col]);
+    G[a + (int64_t)rp * (i + (int64_t)nm * b)] += za[a] * Pm[(int64_t)b * Cm + col];
   }
 }
 
@@ -1411,6 +1412,8 @@ hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count
     ws_free(Zp, s);
     return e;
   }
+  // a single column: one fibre per i (see k_middle_twopass)
+  if (nb > (unsigned)nm) return hipErrorInvalidValue;
   if (dtype == PSTT2_F64)
     hipLaunchKernelGGL(k_middle_twopass<double>, dim3(nb), dim3(256), 0, s, (const double*)x, first, count, Rprev, nm,
                        Cm, Qprev, rprev, Pm, rm, G);

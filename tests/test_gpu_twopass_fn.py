@@ -60,7 +60,8 @@ def test_twopass_middle_core_over_function(name, prec):
 
 
 def test_pstt_last_core_over_function():
-    """The one-sided algorithm's two-pass last core Q_{d-1}^T X_{d-1} over the Gaussian bumps."""
+    """The one-sided algorithm's two-pass last core Q_{d-1}^T X_{d-1} over the Gaussian bumps,
+    in two calls; a second run gives bitwise the same cores (no atomics in the last-core pass)."""
     import torch
     import paper_2111_10448_amd as P
     w = inputs.WORKLOADS["gb_small4"]
@@ -71,13 +72,24 @@ def test_pstt_last_core_over_function():
     D = O.NestedKR(psi, om)
     ref = O.pstt(x, w.n, D, w.ranks())
     fn = _fn(w)
-    ctx = P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", ranks=w.ranks(), mid="twopass", algo="pstt")
-    ctx.sketch_fn(fn)
-    tt = ctx.recover()
-    ctx.middle_pass_fn(tt, fn)
-    torch.cuda.synchronize()
+    half = (w.n[-1] // 2) * int(np.prod(w.n[:-1]))
+
+    def run():
+        ctx = P.PSTT2(w.n, w.ell, fac, dtype="f64", prec="f64", ranks=w.ranks(), mid="twopass", algo="pstt")
+        ctx.sketch_fn(fn)
+        tt = ctx.recover()
+        ctx.middle_pass_fn(tt, fn, half)
+        ctx.middle_pass_fn(tt, fn, 0, half)
+        torch.cuda.synchronize()
+        return ctx, tt
+
+    ctx, tt = run()
     assert tt.ranks == [1] + list(ref["ranks"]) + [1]
     xt = tt.reconstruct().cpu().numpy()
+    ctx2, tt2 = run()
+    assert np.array_equal(tt2.reconstruct().cpu().numpy(), xt), "last core not bitwise repeatable"
+    tt2.free()
+    ctx2.close()
     d_xt = rel(xt, O.tt_full(ref["cores"]))
     xg = torch.from_numpy(x).cuda()
     e_gpu, e_ref = tt.error(xg), O.tt_error(x, ref["cores"])
