@@ -48,22 +48,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-FP64_KERNEL_BEGIN = "// FP64 kernel with the sketch size covered exactly"
-FP64_KERNEL_END = "template <int PREC, int LP>\nstatic hipError_t launch_t("
-
-
 def kernel_source_hash() -> str:
-    """Hash of the FP64 sketch kernel's source: the kernel, its launcher and the launch-geometry rule."""
-    with open(os.path.join(ROOT, "paper_2111_10448_amd", "csrc", "sketch.hip")) as f:
-        src = f.read()
-    a, b = src.find(FP64_KERNEL_BEGIN), src.find(FP64_KERNEL_END)
-    text = src[a:b] if 0 <= a < b else src
-    return hashlib.sha256(text.encode()).hexdigest()[:16]
+    """Hash of the sketch kernels' source (all of csrc/sketch.hip): stored counter figures
+    are used only while it is unchanged."""
+    with open(os.path.join(ROOT, "paper_2111_10448_amd", "csrc", "sketch.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(workload: str, launches_per_step: int):
-    """HBM bytes per sketch launch from the committed counter summary, if it matches this kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_sketch_{workload}_counters.md")
+def traffic_from_profiles(workload: str, prec: str):
+    """HBM bytes per sketch launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the committed
+    counter summary of this workload and precision, if it matches this kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_sketch_{workload}_{prec}_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -459,7 +454,7 @@ def main():
                    "sketch_kernel_ms": round(r["kernel_ms"], 4),
                    "sketch_gbs": round(achieved, 2), "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(name, 1),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(name, prec),
                      "fp64_frac": round(flops / (r["kernel_ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)},
     }
     if not args.no_variants:
@@ -488,6 +483,8 @@ def main():
                             "sketch_launches_per_step": rv["launches_per_step"],
                            "sketch_kernel_ms": round(rv["kernel_ms"], 4),
                            "sketch_gbs": round(kbv / (rv["kernel_ms"] * 1e-3) / 1e9, 2),
+                           "traffic": traffic_from_profiles(wn, vp) if (mid, drm, algo) == ("onepass", "nested", "pstt2")
+                           else None,
                            "ms_per_step": round(rv["ms_per_step"], 4), "ranks": rv["ranks"],
                            "tt_rel_error": rv["err"]}
             except Exception as e:   # report, keep the headline line
