@@ -460,21 +460,23 @@ __device__ __forceinline__ double psi_prod(const AdjOutArgs& A, int64_t row, int
   return v;
 }
 
-template <typename T, bool FUSED, bool ACC>
+// MX: the sketch size and the rank rounded up to a multiple of 4 (the
+// per-row operands live in registers, and their loops are unrolled to MX).
+template <typename T, bool FUSED, bool ACC, int MX>
 __global__ __launch_bounds__(256) void k_adj_out(const AdjOutArgs A, const T* __restrict__ x, T* __restrict__ gx) {
-  constexpr int MX = PSTT2_MAX_ELL, CB = 16;
-  __shared__ double om[CB][MX], tb[CB][MX], rt[CB][MX];
+  constexpr int CB = 16;
+  __shared__ double om[CB][MX], tb[CB][MX], rt[CB][FUSED ? MX : 1];
   const int64_t gi = blockIdx.x % ((A.R + 255) / 256);
   const int64_t gj = blockIdx.x / ((A.R + 255) / 256);
   const int64_t row = gi * 256 + threadIdx.x;
   const bool ok = row < A.R;
   const bool hy = A.Yb != nullptr, ht = A.Tbt != nullptr;
-  double yb[MX], ps[MX], lr[MX];
+  double yb[MX], ps[MX], lr[FUSED ? MX : 1];
 #pragma unroll
   for (int c = 0; c < MX; ++c) {
     yb[c] = (hy && ok && c < A.ell) ? A.Yb[(int64_t)c * A.R + row] : 0.0;
     ps[c] = (ht && ok && c < A.ell) ? drm_eff(psi_prod(A, row, c), A.prec) : 0.0;
-    lr[c] = (FUSED && ok && c < A.r) ? A.L[(int64_t)c * A.R + row] : 0.0;
+    if constexpr (FUSED) lr[c] = (ok && c < A.r) ? A.L[(int64_t)c * A.R + row] : 0.0;
   }
   const int64_t cb = gj * A.C / A.gj, ce = (gj + 1) * A.C / A.gj;
   for (int64_t c0 = cb; c0 < ce; c0 += CB) {
@@ -485,7 +487,7 @@ __global__ __launch_bounds__(256) void k_adj_out(const AdjOutArgs A, const T* __
       const bool cok = col < ce;
       om[j][c] = (hy && cok && c < A.ell) ? drm_eff(A.om_tab[col * A.L4 + c], A.prec) : 0.0;
       tb[j][c] = (ht && cok && c < A.ell) ? A.Tbt[(int64_t)c * A.C + col] : 0.0;
-      rt[j][c] = (FUSED && cok && c < A.r) ? A.Rt[c + (int64_t)A.r * col] : 0.0;
+      if constexpr (FUSED) rt[j][c] = (cok && c < A.r) ? A.Rt[c + (int64_t)A.r * col] : 0.0;
     }
     __syncthreads();
     if (!ok) continue;
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(256) void k_adj_out(const AdjOutArgs A, const T* __
 #pragma unroll
       for (int c = 0; c < MX; ++c) {
         s += yb[c] * om[j][c] + ps[c] * tb[j][c];
-        if (FUSED) xt += lr[c] * rt[j][c];
+        if constexpr (FUSED) xt += lr[c] * rt[j][c];
       }
       const int64_t f = (c0 + j) * A.R + row;
       if (FUSED) s += 2.0 * ((double)x[f] - xt);
@@ -594,6 +596,27 @@ hipError_t adj_derive_right(const double* Tbk, double* Tbp, int64_t Ck, int nk, 
   return hipGetLastError();
 }
 
+template <int MX>
+static void launch_adj_out(int dtype, bool fused, bool acc, dim3 grid, const AdjOutArgs& A, const void* x, void* gx,
+                           hipStream_t s) {
+  const dim3 block(256);
+  if (dtype == PSTT2_F64) {
+    if (fused)
+      hipLaunchKernelGGL((k_adj_out<double, true, false, MX>), grid, block, 0, s, A, (const double*)x, (double*)gx);
+    else if (acc)
+      hipLaunchKernelGGL((k_adj_out<double, false, true, MX>), grid, block, 0, s, A, (const double*)x, (double*)gx);
+    else
+      hipLaunchKernelGGL((k_adj_out<double, false, false, MX>), grid, block, 0, s, A, (const double*)x, (double*)gx);
+  } else {
+    if (fused)
+      hipLaunchKernelGGL((k_adj_out<float, true, false, MX>), grid, block, 0, s, A, (const float*)x, (float*)gx);
+    else if (acc)
+      hipLaunchKernelGGL((k_adj_out<float, false, true, MX>), grid, block, 0, s, A, (const float*)x, (float*)gx);
+    else
+      hipLaunchKernelGGL((k_adj_out<float, false, false, MX>), grid, block, 0, s, A, (const float*)x, (float*)gx);
+  }
+}
+
 hipError_t adj_out(int dtype, const SketchArgs& g, int prec, const double* Yb, const double* Tbt, const double* L,
                    const double* Rt, int r, const void* x, void* gx, bool acc, hipStream_t s) {
   AdjOutArgs A;
@@ -616,24 +639,23 @@ hipError_t adj_out(int dtype, const SketchArgs& g, int prec, const double* Yb, c
   A.L = L;
   A.Rt = Rt;
   const int64_t gi = (g.R + 255) / 256;
-  A.gj = (int)std::max<int64_t>(1, std::min<int64_t>(g.C, (4096 + gi - 1) / gi));
+  // about four workgroups per CU: a thread's row operands (2 MX loads and the
+  // Psi products) are set up once and then serve its share of the columns
+  A.gj = (int)std::max<int64_t>(1, std::min<int64_t>(g.C, (1024 + gi - 1) / gi));
   const dim3 grid((unsigned)(gi * A.gj)), block(256);
   const bool fused = L != nullptr;
   if (fused && acc) return hipErrorInvalidValue;   // the loss term enters once, in the first group
-  if (dtype == PSTT2_F64) {
-    if (fused)
-      hipLaunchKernelGGL((k_adj_out<double, true, false>), grid, block, 0, s, A, (const double*)x, (double*)gx);
-    else if (acc)
-      hipLaunchKernelGGL((k_adj_out<double, false, true>), grid, block, 0, s, A, (const double*)x, (double*)gx);
-    else
-      hipLaunchKernelGGL((k_adj_out<double, false, false>), grid, block, 0, s, A, (const double*)x, (double*)gx);
-  } else {
-    if (fused)
-      hipLaunchKernelGGL((k_adj_out<float, true, false>), grid, block, 0, s, A, (const float*)x, (float*)gx);
-    else if (acc)
-      hipLaunchKernelGGL((k_adj_out<float, false, true>), grid, block, 0, s, A, (const float*)x, (float*)gx);
-    else
-      hipLaunchKernelGGL((k_adj_out<float, false, false>), grid, block, 0, s, A, (const float*)x, (float*)gx);
+  const int mx = (std::max(A.ell, fused ? r : 0) + 3) / 4 * 4;
+  if (mx < 4 || mx > PSTT2_MAX_ELL) return hipErrorInvalidValue;
+  switch (mx) {
+    case 4: launch_adj_out<4>(dtype, fused, acc, grid, A, x, gx, s); break;
+    case 8: launch_adj_out<8>(dtype, fused, acc, grid, A, x, gx, s); break;
+    case 12: launch_adj_out<12>(dtype, fused, acc, grid, A, x, gx, s); break;
+    case 16: launch_adj_out<16>(dtype, fused, acc, grid, A, x, gx, s); break;
+    case 20: launch_adj_out<20>(dtype, fused, acc, grid, A, x, gx, s); break;
+    case 24: launch_adj_out<24>(dtype, fused, acc, grid, A, x, gx, s); break;
+    case 28: launch_adj_out<28>(dtype, fused, acc, grid, A, x, gx, s); break;
+    default: launch_adj_out<32>(dtype, fused, acc, grid, A, x, gx, s); break;
   }
   return hipGetLastError();
 }
