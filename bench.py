@@ -20,7 +20,8 @@ recovery and error pass separately), runs the GPU path on the same sub-tensor
 and reports the element-wise sketch differences, ranks and error against the
 oracle's, and times the oracle on C1 and C5 with one thread.
 Unless --no-variants: the two-sided middle core, the independent DRM scheme,
-the precision study (FP64, FP32, split BF16, BF16, FP16), the 64-slab stream,
+the precision study (FP64 data; FP32 data in FP64, FP32, split BF16, BF16 and
+FP16 arithmetic), the 64-slab stream,
 C1 and C5, the adjoint, Table 1's Hilbert tensors evaluated inside the kernels
 (never stored) and the Gaussian bumps.
 """
@@ -464,6 +465,7 @@ def main():
                                        ("c2", "f64", "onepass", "independent", "pstt2"),
                                        ("c2", "f64", "onepass", "nested", "pstt"),
                                        ("c3_f64", "f64", "onepass", "nested", "pstt2"),
+                                       ("c3", "f64", "onepass", "nested", "pstt2"),   # FP32 data, FP64 arithmetic
                                        ("c3", "f32", "onepass", "nested", "pstt2"),
                                        ("c3", "bf16x3", "onepass", "nested", "pstt2"),
                                        ("c3", "bf16", "onepass", "nested", "pstt2"),

@@ -70,7 +70,9 @@ typedef enum {
 typedef enum { PSTT2_F64 = 0, PSTT2_F32 = 1 } pstt2_dtype;
 
 /* Arithmetic of the sketch contractions.  Recovery is always FP64.
- *   F64     FP64 products and sums (FP64 matrix cores)
+ *   F64     FP64 products and sums (FP64 matrix cores); with dtype F32 the
+ *           FP32 entries are widened to FP64 as they are loaded (products
+ *           of the stored values, exact up to FP64 summation)
  *   F32     FP32 products, FP32 accumulation within a tile, FP64 across tiles
  *   BF16    X and the DRM rounded to bfloat16, FP32 accumulation
  *   BF16X3  split precision: X and the DRM each split into three bfloat16
@@ -84,7 +86,7 @@ typedef enum { PSTT2_F64 = 0, PSTT2_F32 = 1 } pstt2_dtype;
  *           the DRM past 65504 in magnitude become infinite and recover
  *           reports ENUMERIC; tensors whose entries sit far below 6e-5 lose
  *           relative precision and should be scaled by the caller.
- * F32 / BF16 / BF16X3 / F16 need dtype F32. */
+ * F32 / BF16 / BF16X3 / F16 need dtype F32; F64 takes either dtype. */
 typedef enum {
   PSTT2_P_F64 = 0,
   PSTT2_P_F32 = 1,
@@ -294,7 +296,11 @@ pstt2_status pstt2_middle_pass_fn(pstt2_ctx* ctx, tt_cores* cores, const pstt2_f
  *                     i.e. 2 (X - X~) + J^T (-2 (X - X~)); x_dev must be the
  *                     tensor that was sketched.
  * gx_dev is caller-owned device memory of N entries of the context's dtype.
- * Uses stream-ordered device workspace (about 8 N bytes).  sync.
+ * The cotangent is never stored: gbar (or X, for the Frobenius loss, whose
+ * -2 X~ part is applied through two r_m x r_m Gram matrices of the interfaces)
+ * is streamed from caller memory.  Uses stream-ordered device workspace of
+ * O((R_m + C_m) r_m) doubles plus the workgroup partials of that stream
+ * (8 (gi C_m + gj R_m) r_m bytes), nothing tensor-sized.  sync.
  * Errors: ESTATE (no successful pstt2_recover; a two-pass middle core),
  * EINVAL (null pointers, cores not from this context), ENOMEM, EDEVICE. */
 pstt2_status pstt2_vjp(pstt2_ctx* ctx, const tt_cores* cores, const void* x_dev, const void* gbar_dev,

@@ -10,7 +10,10 @@
 //       L_m (products G_1..G_m per row of X_m) and Rt_{m+1} (G_{m+1}..G_d per
 //       column): Lbar_m = gbar_m Rt^T and Rtbar = L_m^T gbar_m come from the
 //       streaming dual-contraction kernel with dense tables in place of the
-//       Khatri-Rao DRMs, then a backward sweep over the interface products;
+//       Khatri-Rao DRMs, then a backward sweep over the interface products.
+//       For the Frobenius loss, gbar = -2 (X - L_m Rt) and the stream runs over
+//       X itself; the rank-r_m part enters through L_m (Rt Rt^T) and
+//       Rt^T (L_m^T L_m), so the cotangent is never formed;
 //   B2  back through the recovery: middle least squares, outer cores, the
 //       thin QR of the pivoted sketch columns, the mode-by-mode derived sketches
 //       -> (Ybar, Tbar_m);
@@ -187,23 +190,6 @@ __global__ void k_transpose(const double* __restrict__ A, int64_t arows, int64_t
 __global__ void k_axpy(int64_t n, double alpha, const double* __restrict__ X, double* __restrict__ Y) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
     Y[t] += alpha * X[t];
-}
-
-// The cotangent in FP64: gbar itself, or -2 (X - X~) for the Frobenius loss,
-// X~_m(row, col) = sum_b L(row, b) Rt(b, col).
-template <typename T>
-__global__ void k_cotangent(const T* __restrict__ x, const T* __restrict__ gbar, int64_t N, int64_t R, int r,
-                            const double* __restrict__ L, const double* __restrict__ Rt, double* __restrict__ out) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
-    if (gbar) {
-      out[t] = (double)gbar[t];
-    } else {
-      const int64_t row = t % R, col = t / R;
-      double s = 0.0;
-      for (int b = 0; b < r; ++b) s += L[(int64_t)b * R + row] * Rt[b + (int64_t)r * col];
-      out[t] = -2.0 * ((double)x[t] - s);
-    }
-  }
 }
 
 // ---- middle least-squares adjoint (one workgroup; p = r_{m-1} n_m rows) ----
@@ -527,17 +513,6 @@ hipError_t adj_transpose(const double* A, int64_t arows, int64_t acols, double* 
 
 hipError_t adj_axpy(int64_t n, double alpha, const double* X, double* Y, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy, dim3(grid_for(n, 256)), dim3(256), 0, s, n, alpha, X, Y);
-  return hipGetLastError();
-}
-
-hipError_t adj_cotangent(int dtype, const void* x, const void* gbar, int64_t N, int64_t R, int r, const double* L,
-                         const double* Rt, double* out, hipStream_t s) {
-  if (dtype == PSTT2_F64)
-    hipLaunchKernelGGL(k_cotangent<double>, dim3(grid_for(N, 256)), dim3(256), 0, s, (const double*)x,
-                       (const double*)gbar, N, R, r, L, Rt, out);
-  else
-    hipLaunchKernelGGL(k_cotangent<float>, dim3(grid_for(N, 256)), dim3(256), 0, s, (const float*)x,
-                       (const float*)gbar, N, R, r, L, Rt, out);
   return hipGetLastError();
 }
 

@@ -178,6 +178,7 @@ SketchArgs base_args(const pstt2_ctx* c) {
   a.om_tab = c->om_tab;
   a.om16 = c->om16;
   a.tlp = omega16_planes(c->prec) ? c->lp : 0;
+  a.x32 = c->dtype == PSTT2_F32 && c->prec == PSTT2_P_F64;
   a.L4 = c->L4;
   return a;
 }
@@ -432,8 +433,6 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
   if (desc->prec < PSTT2_P_F64 || desc->prec > PSTT2_P_F16) return fail(nullptr, PSTT2_EINVAL, "bad prec");
   if (desc->dtype == PSTT2_F64 && desc->prec != PSTT2_P_F64)
     return fail(nullptr, PSTT2_EINVAL, "FP64 tensors use PSTT2_P_F64 arithmetic");
-  if (desc->dtype == PSTT2_F32 && desc->prec == PSTT2_P_F64)
-    return fail(nullptr, PSTT2_EINVAL, "FP32 tensors use PSTT2_P_F32, PSTT2_P_BF16, PSTT2_P_BF16X3 or PSTT2_P_F16");
   if (desc->mid != PSTT2_MID_ONEPASS && desc->mid != PSTT2_MID_TWOPASS && desc->mid != PSTT2_MID_TWOSIDED)
     return fail(nullptr, PSTT2_EINVAL, "bad mid");
   if (desc->drm != PSTT2_DRM_NESTED && desc->drm != PSTT2_DRM_INDEPENDENT) return fail(nullptr, PSTT2_EINVAL, "bad drm");
@@ -1250,9 +1249,14 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   const int rm = r[m];
   const double* Lm = Lv[m];
   const double* Rtm = Rv[m + 1];
-  // ---- B1: the cotangent and its dual contraction with the interfaces ----
-  double* g64 = take(c->N, false);
-  VJPCK(adj_cotangent(c->dtype, x_dev, gbar_dev, c->N, c->R, rm, Lm, Rtm, g64, s));
+  // ---- B1: U = gbar_m Rt^T (R x r_m) and Vt = gbar_m^T L (C x r_m), the cotangent's
+  //      contraction with the interfaces, by the FP64 dual-sketch kernel with L and
+  //      Rt^T as its DRM tables.  A given gbar is streamed as it is.  For the
+  //      Frobenius loss, gbar = -2 (X - L Rt) and the second term has rank r_m, so
+  //      U = -2 (X_m Rt^T - L (Rt Rt^T)) and Vt = -2 (X_m^T L - Rt^T (L^T L)): the
+  //      kernel streams X itself and two r_m x r_m Gram matrices supply the rest,
+  //      so no tensor-sized cotangent is ever formed. ----
+  const void* src = gbar_dev ? gbar_dev : x_dev;
   const int L4r = (rm + 3) / 4 * 4;
   double* psiT = take(c->R * L4r, false);
   double* omT = take(c->C * L4r, false);
@@ -1269,7 +1273,7 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   a.nchunks = (c->C + 15) / 16;
   a.gj_count = (int)std::max<int64_t>(1, std::min<int64_t>(a.nchunks, std::max(1, c->ncu * wpc / a.gi_count)));
   a.nseg = 1;
-  a.seg[0].ptr = g64;
+  a.seg[0].ptr = src;
   a.seg[0].gcol0 = 0;
   a.seg[0].ncols = c->C;
   a.seg[0].chunk0 = 0;
@@ -1277,10 +1281,19 @@ pstt2_status pstt2_vjp(pstt2_ctx* c, const tt_cores* cores, const void* x_dev, c
   a.tpart = take((int64_t)a.gi_count * rm * c->C + kTPartPad, false);
   a.tlp = 0;   // the FP64 kernel's partial layout
   a.om16 = nullptr;
+  a.x32 = c->dtype == PSTT2_F32;   // FP32 entries are widened as they are loaded
   double* U = take(c->R * rm, true);    // Lbar_m = gbar_m Rt^T        (R x r_m)
   double* Vt = take(c->C * rm, true);   // (L_m^T gbar_m)^T           (C x r_m)
   if (e == hipSuccess) e = launch_sketch(PSTT2_P_F64, 0, a, s);
   if (e == hipSuccess) e = launch_reduce(PSTT2_P_F64, a, U, Vt, c->flag, s);
+  if (!gbar_dev) {
+    double* Gr = take((int64_t)rm * rm, false);   // Rt Rt^T
+    double* Gl = take((int64_t)rm * rm, false);   // L^T L
+    VJPCK(adj_gemm(false, true, rm, rm, c->C, 1.0, Rtm, rm, Rtm, rm, 0.0, Gr, rm, s));
+    VJPCK(adj_gemm(true, false, rm, rm, c->R, 1.0, Lm, c->R, Lm, c->R, 0.0, Gl, rm, s));
+    VJPCK(adj_gemm(false, false, c->R, rm, rm, 2.0, Lm, c->R, Gr, rm, -2.0, U, c->R, s));
+    VJPCK(adj_gemm(true, false, c->C, rm, rm, 2.0, Rtm, rm, Gl, rm, -2.0, Vt, c->C, s));
+  }
   // core cotangents, laid out like the cores
   std::vector<double*> Gb(d, nullptr);
   for (int k = 0; k < d; ++k) Gb[k] = take((int64_t)r[k] * c->n[k] * r[k + 1], true);

@@ -84,6 +84,7 @@ struct SketchArgs {
   void* tpart;       // tlp == 0: [gi][a][gcol], ell rows; tlp > 0: [gi][gcol][tlp] (sketch index
                      // contiguous); indexed by global column; then kTPartPad spare entries
   int32_t tlp;       // layout of tpart (see above)
+  int32_t x32;       // FP64 kernel: the segments hold FP32 entries (widened as loaded)
   int64_t C;         // columns of X_m (for the tpart stride)
   const double* om_tab;  // Omega_m(col, c) table, C x L4, FP64
   int32_t L4;            // its row stride: ell rounded up to a multiple of 4
@@ -236,8 +237,6 @@ hipError_t adj_table(const double* in, int64_t rows, int cnt, int64_t si, int64_
                      hipStream_t s);
 hipError_t adj_transpose(const double* A, int64_t arows, int64_t acols, double* B, hipStream_t s);
 hipError_t adj_axpy(int64_t n, double alpha, const double* X, double* Y, hipStream_t s);
-hipError_t adj_cotangent(int dtype, const void* x, const void* gbar, int64_t N, int64_t R, int r, const double* L,
-                         const double* Rt, double* out, hipStream_t s);
 hipError_t adj_ls(const double* G, const double* Gb, const double* Z, const double* A, int64_t p, int r, int ell,
                   double* Zb, double* Ab, hipStream_t s);
 hipError_t adj_core_right(const double* Gb, const double* Pp, const double* Pk, int64_t Ck, int nk, int rp, int rk,

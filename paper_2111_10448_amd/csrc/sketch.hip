@@ -1029,7 +1029,9 @@ constexpr int f64_wg_per_cu(int L4) { return L4 > 28 ? 1 : 2; }
 
 // FN: the tensor is the Hilbert tensor, evaluated from the index tables in
 // place of the loads of X (one launch segment, no memory behind it).
-template <int L4, bool ALIGNED, bool SEG1, bool FN>
+// X32: X holds FP32 entries, widened to FP64 as they are loaded (FP64
+// arithmetic on FP32 data); the rest of the kernel is the same.
+template <int L4, bool ALIGNED, bool SEG1, bool FN, bool X32 = false>
 __global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_f64(const SketchArgs A) {
   constexpr int NWF = nwf_for(L4);
   constexpr int RW = 64;
@@ -1112,6 +1114,20 @@ __global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_
         const int fc = colok ? A.fn_col[ch.gcol0 + cc] : 0;
         xr[i][0] = (colok && row < A.R) ? A.fn_rec[fr0 + fc] : 0.0;
         xr[i][1] = (colok && row + 1 < A.R) ? A.fn_rec[fr1 + fc] : 0.0;
+      } else if constexpr (X32) {
+        const float* pf = (const float*)ch.ptr + (ch.lcol0 + cc) * A.R + row;
+        if constexpr (ALIGNED) {   // R even, 8-byte pairs
+          if (colok && row < A.R) {
+            const float2 v = *(const float2*)pf;
+            xr[i][0] = (double)v.x;
+            xr[i][1] = (double)v.y;
+          } else {
+            xr[i][0] = xr[i][1] = 0.0;
+          }
+        } else {
+          xr[i][0] = (colok && row < A.R) ? (double)pf[0] : 0.0;
+          xr[i][1] = (colok && row + 1 < A.R) ? (double)pf[1] : 0.0;
+        }
       } else if constexpr (ALIGNED) {
         if (colok && row < A.R) {
           const double2 v = *(const double2*)p;
@@ -1264,8 +1280,16 @@ static hipError_t launch_f64(const SketchArgs& a, bool aligned, hipStream_t s) {
   dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(nwf_for(L4) * 64);
   const bool seg1 = a.nseg == 1 && a.seg[0].chunk0 == 0;
   if (a.fn) {
-    if (!seg1 || a.fn != 1 || !a.fn_rec || !a.fn_row || !a.fn_col) return hipErrorInvalidValue;
+    if (!seg1 || a.fn != 1 || !a.fn_rec || !a.fn_row || !a.fn_col || a.x32) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_sketch_f64<L4, true, true, true>), grid, block, 0, s, a);
+  } else if (a.x32) {
+    if (aligned) {
+      if (seg1) hipLaunchKernelGGL((k_sketch_f64<L4, true, true, false, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_sketch_f64<L4, true, false, false, true>), grid, block, 0, s, a);
+    } else {
+      if (seg1) hipLaunchKernelGGL((k_sketch_f64<L4, false, true, false, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_sketch_f64<L4, false, false, false, true>), grid, block, 0, s, a);
+    }
   } else if (aligned) {
     if (seg1) hipLaunchKernelGGL((k_sketch_f64<L4, true, true, false>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_sketch_f64<L4, true, false, false>), grid, block, 0, s, a);
@@ -1333,7 +1357,7 @@ hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s) {
   if (fault_take()) return hipErrorLaunchFailure;
   if (a.fn && prec != P_F64) return hipErrorInvalidValue;
   // 16-byte loads need every column (and segment start) 16-byte aligned.
-  const int esz = prec == P_F64 ? 8 : 4;
+  const int esz = prec == P_F64 && !a.x32 ? 8 : 4;
   bool aligned = ((a.R * esz) % 16) == 0;
   for (int i = 0; i < a.nseg; ++i) aligned = aligned && (((uintptr_t)a.seg[i].ptr) % 16 == 0);
   if (prec == P_F64) {

@@ -169,3 +169,28 @@ def test_vjp_c5_full_size():
     w, x, fac, drm, ref = _instance("c5")
     say("[gpu] vjp c5 full size")
     _check(w, x, fac, drm, ref, "f32", 5e-5)
+
+
+@pytest.mark.slow
+def test_vjp_workspace_is_not_tensor_sized():
+    """C5 (5.3e6 FP32 entries): the loss gradient and J^T gbar run under a device budget of the
+    library's live bytes plus 4 bytes per entry.  The cotangent is never stored (as FP64 it alone
+    would take 8 bytes per entry); the results match the unbudgeted run bitwise."""
+    import torch
+    import paper_2111_10448_amd as P
+    w, x, fac, drm, ref = _instance("c5")
+    say("[gpu] vjp c5 workspace under a budget of 4 bytes per entry")
+    ctx, tt, xg = _gpu(w, x, fac, "f32")
+    gbar = torch.from_numpy(np.random.default_rng(7).standard_normal(x.size).astype(np.float32)).cuda()
+    torch.cuda.synchronize()
+    P.set_memory_limit(P.memory_stats()["live"] + 4 * x.size)
+    try:
+        g = ctx.vjp(tt, x=xg)
+        jt = ctx.vjp(tt, gbar=gbar)
+        torch.cuda.synchronize()
+    finally:
+        P.set_memory_limit(0)
+    assert torch.equal(g, ctx.vjp(tt, x=xg)) and torch.equal(jt, ctx.vjp(tt, gbar=gbar))
+    assert torch.isfinite(g).all() and torch.isfinite(jt).all()
+    tt.free()
+    ctx.close()

@@ -31,6 +31,23 @@ def test_fp64_and_fp32_workloads(name):
     ctx.close()
 
 
+@pytest.mark.parametrize("name,slabs", [("c3_small", 1), ("c5_small", 1), ("c4_small", 7)])
+def test_fp32_data_fp64_arithmetic(name, slabs):
+    """FP32 tensors sketched in FP64 (the entries widened as loaded): the oracle upcasts the
+    same FP32 values exactly, so every quantity is held to the FP64 tolerances, including
+    the gauge-fixed cores; the 7-slab case runs multi-segment launches with ragged edges."""
+    w = inputs.WORKLOADS[name]
+    say(f"[gpu] parity {name} n={w.n} FP32 data, FP64 arithmetic, slabs={slabs}")
+    assert w.dtype == "f32"
+    x, psi, omega, fac = setup(w)
+    ref = oracle_run(x, w, psi, omega)
+    sl = inputs.slab_bounds(x.size, w.n[0], slabs) if slabs > 1 else None
+    ctx, tt, xg = gpu_run(x, w, fac, "f64", slabs=sl)
+    out = compare(ctx, tt, xg, x, w, ref, "f64", check_cores=True)
+    say(f"    {out}")
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16"])
 def test_mixed_precision_invsum(prec):
     w = inputs.WORKLOADS["c3_small"]
