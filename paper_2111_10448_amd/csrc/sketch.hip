@@ -1092,7 +1092,9 @@ __global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_
     if (e < KC * L4) *(double2*)&Om[buf][e] = omv;
   };
 
-  double xr[NLD][2];
+  // X32: the prefetched pairs stay FP32 in registers and are widened when the
+  // chunk is staged (widening at the load would wait for every load in turn)
+  typename std::conditional<X32, float, double>::type xr[NLD][2];
   // FN: index-table entries of this lane's two rows (fixed for the launch)
   int fr0 = 0, fr1 = 0;
   if constexpr (FN) {
@@ -1119,14 +1121,14 @@ __global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_
         if constexpr (ALIGNED) {   // R even, 8-byte pairs
           if (colok && row < A.R) {
             const float2 v = *(const float2*)pf;
-            xr[i][0] = (double)v.x;
-            xr[i][1] = (double)v.y;
+            xr[i][0] = v.x;
+            xr[i][1] = v.y;
           } else {
-            xr[i][0] = xr[i][1] = 0.0;
+            xr[i][0] = xr[i][1] = 0.0f;
           }
         } else {
-          xr[i][0] = (colok && row < A.R) ? (double)pf[0] : 0.0;
-          xr[i][1] = (colok && row + 1 < A.R) ? (double)pf[1] : 0.0;
+          xr[i][0] = (colok && row < A.R) ? pf[0] : 0.0f;
+          xr[i][1] = (colok && row + 1 < A.R) ? pf[1] : 0.0f;
         }
       } else if constexpr (ALIGNED) {
         if (colok && row < A.R) {
@@ -1147,8 +1149,8 @@ __global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_
     for (int i = 0; i < NLD; ++i) {
       const int cc = 2 * i + (lane >> 5);
       const int r = (lane & 31) * 2;
-      Xl[w][cc * ST + r] = xr[i][0];
-      Xl[w][cc * ST + r + 1] = xr[i][1];
+      Xl[w][cc * ST + r] = (double)xr[i][0];
+      Xl[w][cc * ST + r + 1] = (double)xr[i][1];
     }
   };
   auto reduce_t = [&](int buf, int64_t ci) {
