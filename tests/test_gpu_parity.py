@@ -363,6 +363,36 @@ def test_fp16_sketches(name, slabs):
     ctx.close()
 
 
+def test_fp16_range_overflow_reports_enumeric():
+    """FP16 sketches: an entry past half precision's largest finite value (65504) becomes
+    infinite, and recover reports ENUMERIC instead of returning cores; after reset the
+    same context decomposes the in-range tensor.  Split BF16 (FP32's range) takes the
+    out-of-range entry as it is."""
+    import torch
+    import paper_2111_10448_amd as P
+    from paper_2111_10448_amd import _lib as L
+    w = inputs.WORKLOADS["c5_small"]
+    say("[gpu] FP16 range overflow")
+    x, psi, omega, fac = setup(w)
+    xb = x.copy()
+    xb[123] = np.float32(1.0e5)
+    xg = torch.from_numpy(x).cuda()
+    with P.PSTT2(w.n, w.ell, fac, dtype="f32", prec="f16", ranks=w.ranks()) as ctx:
+        ctx.sketch(torch.from_numpy(xb).cuda())
+        with pytest.raises(P.PSTT2Error) as e:
+            ctx.recover()
+        assert e.value.status == L.ENUMERIC
+        ctx.reset()
+        ctx.sketch(xg)
+        tt = ctx.recover()
+        assert np.isfinite(tt.error(xg))
+        tt.free()
+    with P.PSTT2(w.n, w.ell, fac, dtype="f32", prec="bf16x3", ranks=w.ranks()) as ctx:
+        ctx.sketch(torch.from_numpy(xb).cuda())
+        tt = ctx.recover()
+        tt.free()
+
+
 @pytest.mark.parametrize("name,n,drm", [("c2_small", None, "nested"), ("c1", (9, 7, 8), "independent"),
                                         ("c4_small", None, "nested")])
 def test_seeded_factors(name, n, drm):
