@@ -158,16 +158,15 @@ __device__ __forceinline__ int acc_row(int g4, int v) {
   return PREC == P_F64 ? 4 * v + g4 : 4 * g4 + v;
 }
 
-// Psi_m(row, a) for a global row of X_m (0 outside the matrix / sketch).
-__device__ __forceinline__ double psi_row(const SketchArgs& A, int64_t row, int a) {
-  if (row >= A.R || a >= A.ell) return 0.0;
-  if (A.psi_tab) return A.psi_tab[row * A.L4 + a];
+// Psi_m(row, a) = psi_1(i_1, a) * psi_hi(h, a) for the row i_1 + n_1 h of X_m:
+// psi_hi is the product of the factor entries of modes 2..m (the mixed-radix
+// digits of h), multiplied in increasing mode order.
+__device__ __forceinline__ double psi_hi(const SketchArgs& A, int64_t h, int a) {
   double v = 1.0;
-  if (A.R <= 0xffffffffLL) {
-    // 32-bit index arithmetic (a few instructions per division instead of the
-    // 64-bit sequence): the workgroup prologue forms 32 of these rows per lane
-    uint32_t r = (uint32_t)row;
-    for (int q = 1; q <= A.m; ++q) {
+  if (h <= 0xffffffffLL) {
+    // 32-bit index arithmetic: a few instructions per division instead of the 64-bit sequence
+    uint32_t r = (uint32_t)h;
+    for (int q = 2; q <= A.m; ++q) {
       const uint32_t nq = (uint32_t)A.n[q - 1];
       const uint32_t iq = r % nq;
       r /= nq;
@@ -175,15 +174,57 @@ __device__ __forceinline__ double psi_row(const SketchArgs& A, int64_t row, int 
     }
     return v;
   }
-  int64_t r = row;
-  for (int q = 1; q <= A.m; ++q) {
-    int64_t nq = A.n[q - 1];
-    int64_t iq = r % nq;
+  int64_t r = h;
+  for (int q = 2; q <= A.m; ++q) {
+    const int64_t nq = A.n[q - 1];
+    const int64_t iq = r % nq;
     r /= nq;
     v *= A.fac[A.psi_off[q - 1] + iq * A.ell + a];
   }
   return v;
 }
+
+// Psi_m(row, a) for a global row of X_m (0 outside the matrix / sketch).
+__device__ __forceinline__ double psi_row(const SketchArgs& A, int64_t row, int a) {
+  if (row >= A.R || a >= A.ell) return 0.0;
+  if (A.psi_tab) return A.psi_tab[row * A.L4 + a];
+  const int64_t h = row / A.n[0];
+  const int64_t i1 = row - h * A.n[0];
+  return A.fac[A.psi_off[0] + i1 * A.ell + a] * psi_hi(A, h, a);
+}
+
+// A lane's rows of Psi_m, visited in increasing order by the workgroup
+// prologues: (i_1, h) with row = i_1 + n_1 h is advanced without division, and
+// the caller forms psi_hi again only when h changes (and only inside the
+// matrix, where h's top digit is a valid index).  Values equal psi_row's.
+struct PsiCursor {
+  int64_t row = 0, h = 0, hc = -1;
+  int64_t i1 = 0;
+  __device__ __forceinline__ void init(const SketchArgs& A, int64_t r) {
+    row = r;
+    h = r / A.n[0];
+    i1 = r - h * A.n[0];
+  }
+  __device__ __forceinline__ void advance(const SketchArgs& A, int by) {
+    row += by;
+    i1 += by;
+    while (i1 >= A.n[0]) {
+      i1 -= A.n[0];
+      ++h;
+    }
+  }
+  // true when the caller must recompute its psi_hi values for this row
+  __device__ __forceinline__ bool refresh(const SketchArgs& A) {
+    if (row >= A.R || A.psi_tab || h == hc) return false;
+    hc = h;
+    return true;
+  }
+  __device__ __forceinline__ double at(const SketchArgs& A, int a, double hi) const {
+    if (row >= A.R || a >= A.ell) return 0.0;
+    if (A.psi_tab) return A.psi_tab[row * A.L4 + a];
+    return A.fac[A.psi_off[0] + i1 * A.ell + a] * hi;
+  }
+};
 
 // Omega_m(gcol, c) for a global column of X_m.
 __device__ __forceinline__ double omega_col(const SketchArgs& A, int64_t gcol, int c) {
@@ -292,18 +333,39 @@ __global__ __launch_bounds__(NWS * 64, 2) void k_sketch(const SketchArgs A) {
   s4 psiL[X3 ? KT : 1][X3 ? NT : 1];
   (void)psiM;
   (void)psiL;
+  {
+    PsiCursor pc;
+    double hv[NT];
+    if constexpr (E::KPL == 1) {   // rows row0w + KSTEP ks + g4
+      pc.init(A, row0w + g4);
 #pragma unroll
-  for (int ks = 0; ks < KT; ++ks) {
+      for (int ks = 0; ks < KT; ++ks) {
+        if (ks > 0) pc.advance(A, E::KSTEP);
+        if (pc.refresh(A)) {
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      const int a = 16 * mt + l16;
-      if constexpr (E::KPL == 1) {
-        psiA[ks][mt] = drm_to_lds<PREC>(psi_row(A, row0w + E::KSTEP * ks + g4, a));
-      } else {
-        float p[4];
+          for (int mt = 0; mt < NT; ++mt) hv[mt] = psi_hi(A, pc.h, 16 * mt + l16);
+        }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) p[v] = (float)psi_row(A, row0w + 16 * ks + 4 * g4 + v, a);
-        split3x4(p[0], p[1], p[2], p[3], psiA[ks][mt], psiM[ks][mt], psiL[ks][mt]);
+        for (int mt = 0; mt < NT; ++mt) psiA[ks][mt] = drm_to_lds<PREC>(pc.at(A, 16 * mt + l16, hv[mt]));
+      }
+    } else {   // rows row0w + 16 ks + 4 g4 + v, v = 0..3
+      pc.init(A, row0w + 4 * g4);
+#pragma unroll
+      for (int ks = 0; ks < KT; ++ks) {
+        float p[4][NT];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (ks > 0 || v > 0) pc.advance(A, v > 0 ? 1 : 13);
+          if (pc.refresh(A)) {
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) hv[mt] = psi_hi(A, pc.h, 16 * mt + l16);
+          }
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt) p[v][mt] = (float)pc.at(A, 16 * mt + l16, hv[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+          split3x4(p[0][mt], p[1][mt], p[2][mt], p[3][mt], psiA[ks][mt], psiM[ks][mt], psiL[ks][mt]);
       }
     }
   }
@@ -765,15 +827,28 @@ __global__ __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) void k_sketch16(const Ske
   }
 
   // ---- stationary left-DRM operands Psi(row0w + 16 rt + 4 g4 + v, 16 mt + l16) ----
+  {
+    PsiCursor pc;
+    pc.init(A, row0w + 4 * g4);
+    double hv[NT];
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt) {
+      float p[4][NT];
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      float p[4];
+      for (int v = 0; v < 4; ++v) {
+        if (rt > 0 || v > 0) pc.advance(A, v > 0 ? 1 : 13);
+        if (pc.refresh(A)) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) p[v] = (float)psi_row(A, row0w + 16 * rt + 4 * g4 + v, 16 * mt + l16);
-      Pl[w][rt][mt][lane] = cvt4<PREC>(float4{p[0], p[1], p[2], p[3]}, 0xfu);
+          for (int mt = 0; mt < NT; ++mt) hv[mt] = psi_hi(A, pc.h, 16 * mt + l16);
+        }
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) p[v][mt] = (float)pc.at(A, 16 * mt + l16, hv[mt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+        Pl[w][rt][mt][lane] = cvt4<PREC>(float4{p[0][mt], p[1][mt], p[2][mt], p[3][mt]}, 0xfu);
     }
+  }
   __syncthreads();   // the slot counters are zero
 
   Cursor16 cx, co, ct_;   // X loads (two ahead), Omega loads (one ahead), T partial stores
@@ -1062,13 +1137,24 @@ __global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_
   // stationary left-DRM operands: Psi(row0w + 4 ks + g4, a)
   double psiq[KT][NQ > 0 ? NQ : 1];
   double psis[KT][NS > 0 ? NS : 1];
+  {
+    PsiCursor pc;
+    pc.init(A, row0w + g4);
+    double hq[NQ > 0 ? NQ : 1], hs[NS > 0 ? NS : 1];
 #pragma unroll
-  for (int ks = 0; ks < KT; ++ks) {
-    const int64_t row = row0w + 4 * ks + g4;
+    for (int ks = 0; ks < KT; ++ks) {
+      if (ks > 0) pc.advance(A, 4);
+      if (pc.refresh(A)) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) psiq[ks][q] = psi_row(A, row, 16 * q + l16);
+        for (int q = 0; q < NQ; ++q) hq[q] = psi_hi(A, pc.h, 16 * q + l16);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) psis[ks][s] = psi_row(A, row, 16 * NQ + 4 * s + l4);
+        for (int s = 0; s < NS; ++s) hs[s] = psi_hi(A, pc.h, 16 * NQ + 4 * s + l4);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) psiq[ks][q] = pc.at(A, 16 * q + l16, hq[q]);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) psis[ks][s] = pc.at(A, 16 * NQ + 4 * s + l4, hs[s]);
+    }
   }
 
   // Omega_m rows of a chunk: thread t < KC*L4/2 holds entries (e, e + 1),
