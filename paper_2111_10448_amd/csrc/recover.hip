@@ -911,70 +911,117 @@ hipError_t eye(int k, double* out, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Two-sided sketches of every split in two launches.  B_k = Psi_k^T S_k
 // (k < m, operand S_k = X_k Omega_k, R_k rows) or B_k = T_k Omega_k (k >= m,
-// operand T_k^T, C_k rows).  A workgroup takes TS_ROWS rows of one split's
-// operand, forms the matching Khatri-Rao DRM rows from the factors in LDS,
-// and writes the slice's ell x ell partial product; a wavefront per entry then
-// adds a split's slice partials in slice order (deterministic).
+// operand T_k^T, C_k rows).  A workgroup takes B.steps[p] slices of TS_ROWS
+// rows of one split's operand (up to TS_STEPS, when the operand is tall
+// enough to keep the CUs busy with fewer workgroups).  Per slice it stages the operand rows and the
+// matching Khatri-Rao DRM rows in LDS and adds their ell x ell product into
+// registers (slices in order); it writes one partial, and a wavefront per
+// entry then adds a split's partials in workgroup order (deterministic).
+// A DRM row is the product of the chain's factor rows; with row = i + n_0 h
+// (n_0 the chain's first mode) it is psi_0(i, u) * H(h, u), where H is the
+// product of the other modes' rows: a slice spans at most TS_HMAX values of
+// h when n_0 >= 4, so H is formed once per h into LDS (the divisions it needs
+// are per h, not per entry); smaller n_0 takes the per-entry product.
 // ---------------------------------------------------------------------------
 constexpr int TS_ROWS = 128;
+constexpr int TS_STEPS = 8;   // slices per workgroup at most
+constexpr int TS_HMAX = TS_ROWS / 4 + 2;
+
+__device__ __forceinline__ double chain_product(const TwoSidedBatch& B, const int64_t* off, const int64_t* nmode,
+                                                int q0, int j0, int cnt, int64_t rest, int u) {
+  double fv = 1.0;
+  if (rest <= 0xffffffffLL) {   // 32-bit index arithmetic (far fewer instructions per division)
+    uint32_t r = (uint32_t)rest;
+    for (int j = j0; j < cnt; ++j) {
+      const uint32_t nq = (uint32_t)nmode[q0 + j];
+      const uint32_t i = r % nq;
+      r /= nq;
+      fv *= B.fac[off[j] + (int64_t)i * B.ell + u];
+    }
+  } else {
+    int64_t r = rest;
+    for (int j = j0; j < cnt; ++j) {
+      const int64_t nq = nmode[q0 + j];
+      const int64_t i = r % nq;
+      r /= nq;
+      fv *= B.fac[off[j] + i * B.ell + u];
+    }
+  }
+  return fv;
+}
 
 __global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, double* __restrict__ part) {
   __shared__ double Fs[TS_ROWS][PSTT2_MAX_ELL + 1];
   __shared__ double Ss[TS_ROWS][PSTT2_MAX_ELL + 1];
+  __shared__ double Hs[TS_HMAX][PSTT2_MAX_ELL + 1];
+  __shared__ int32_t ri[TS_ROWS], rh[TS_ROWS];   // a slice row as i + n_0 (h0 + rh)
   const int t = threadIdx.x;
   const int ell = B.ell, d = B.d;
   const int p = batch_find(B.blk0, B.n, blockIdx.x);
   const int64_t K = B.K[p];
-  const int64_t r0 = (blockIdx.x - B.blk0[p]) * (int64_t)TS_ROWS;
+  const int nsteps = B.steps[p];
+  const int64_t r0 = (blockIdx.x - B.blk0[p]) * (int64_t)TS_ROWS * nsteps;
   const int k = B.split[p], right = B.right[p];
   const int q0 = right ? k : 0, cnt = right ? d - k : k;
   const int64_t* off = B.chain + ((int64_t)k * 2 + right) * d;
   const int64_t* nmode = B.chain + (int64_t)(d + 1) * 2 * d;
   const double* __restrict__ S = B.S[p];
   const int sc = B.scols[p] > 0 ? B.scols[p] : ell;
-  for (int e = t; e < TS_ROWS * ell; e += 256) {
-    const int r = e % TS_ROWS, u = e / TS_ROWS;
-    const int64_t row = r0 + r;
-    double sv = 0.0, fv = 0.0;
-    if (row < K) {
-      sv = u < sc ? S[(int64_t)u * K + row] : 0.0;
-      fv = 1.0;
-      if (K <= 0xffffffffLL) {   // 32-bit index arithmetic (far fewer instructions per division)
-        uint32_t rest = (uint32_t)row;
-        for (int j = 0; j < cnt; ++j) {
-          const uint32_t nq = (uint32_t)nmode[q0 + j];
-          const uint32_t i = rest % nq;
-          rest /= nq;
-          fv *= B.fac[off[j] + (int64_t)i * ell + u];
+  const int64_t n0 = nmode[q0];
+  const bool htab = n0 >= 4;
+  const int nout = ell * ell;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int st = 0; st < nsteps; ++st) {
+    const int64_t rb = r0 + (int64_t)st * TS_ROWS;
+    if (rb >= K) break;
+    const int64_t h0 = rb / n0;
+    __syncthreads();   // the last slice's LDS reads are done
+    if (htab) {
+      const int64_t rl = std::min<int64_t>(rb + TS_ROWS, K) - 1;
+      const int nh = (int)(rl / n0 - h0 + 1);   // <= TS_ROWS / n_0 + 2 <= TS_HMAX
+      for (int e = t; e < nh * ell; e += 256) {
+        const int hh = e % nh, u = e / nh;
+        Hs[hh][u] = chain_product(B, off, nmode, q0, 1, cnt, (h0 + hh), u);
+      }
+      if (t < TS_ROWS) {
+        const int64_t row = rb + t, h = row / n0;
+        ri[t] = (int32_t)(row - h * n0);
+        rh[t] = (int32_t)(h - h0);
+      }
+      __syncthreads();
+    }
+    for (int e = t; e < TS_ROWS * ell; e += 256) {
+      const int r = e % TS_ROWS, u = e / TS_ROWS;
+      const int64_t row = rb + r;
+      double sv = 0.0, fv = 0.0;
+      if (row < K) {
+        sv = u < sc ? S[(int64_t)u * K + row] : 0.0;
+        fv = htab ? B.fac[off[0] + (int64_t)ri[r] * ell + u] * Hs[rh[r]][u]
+                  : chain_product(B, off, nmode, q0, 0, cnt, row, u);
+      }
+      Ss[r][u] = sv;
+      Fs[r][u] = fv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = t + 256 * q;
+      if (o < nout) {
+        const int u = o % ell, v = o / ell;
+        double a = acc[q];
+        if (!right) {
+          for (int r = 0; r < TS_ROWS; ++r) a += Fs[r][u] * Ss[r][v];   // Psi_k(row, u) S_k(row, v)
+        } else {
+          for (int r = 0; r < TS_ROWS; ++r) a += Ss[r][u] * Fs[r][v];   // T_k(u, col) Omega_k(col, v)
         }
-      } else {
-        int64_t rest = row;
-        for (int j = 0; j < cnt; ++j) {
-          const int64_t nq = nmode[q0 + j];
-          const int64_t i = rest % nq;
-          rest /= nq;
-          fv *= B.fac[off[j] + i * ell + u];
-        }
+        acc[q] = a;
       }
     }
-    Ss[r][u] = sv;
-    Fs[r][u] = fv;
   }
-  __syncthreads();
-  const int nout = ell * ell;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int o = t + 256 * q;
-    if (o < nout) {
-      const int u = o % ell, v = o / ell;
-      double acc = 0.0;
-      if (!right) {
-        for (int r = 0; r < TS_ROWS; ++r) acc += Fs[r][u] * Ss[r][v];   // Psi_k(row, u) S_k(row, v)
-      } else {
-        for (int r = 0; r < TS_ROWS; ++r) acc += Ss[r][u] * Fs[r][v];   // T_k(u, col) Omega_k(col, v)
-      }
-      part[(int64_t)blockIdx.x * nout + o] = acc;
-    }
+    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = acc[q];
   }
 }
 
@@ -994,7 +1041,10 @@ hipError_t two_sided_batch(TwoSidedBatch& B, hipStream_t s) {
   int64_t nblk = 0;
   for (int p = 0; p < B.n; ++p) {
     B.blk0[p] = nblk;
-    nblk += std::max<int64_t>(1, (B.K[p] + TS_ROWS - 1) / TS_ROWS);
+    // several slices per workgroup only while at least 512 workgroups remain
+    B.steps[p] = (int)std::max<int64_t>(1, std::min<int64_t>(TS_STEPS, B.K[p] / ((int64_t)TS_ROWS * 512)));
+    const int64_t rows = (int64_t)TS_ROWS * B.steps[p];
+    nblk += std::max<int64_t>(1, (B.K[p] + rows - 1) / rows);
   }
   B.blk0[B.n] = nblk;
   if (B.n == 0) return hipSuccess;
