@@ -950,12 +950,20 @@ __device__ __forceinline__ double chain_product(const TwoSidedBatch& B, const in
   return fv;
 }
 
+typedef double ts_d4 __attribute__((ext_vector_type(4)));
+
+// The product on FP64 matrix cores: each wave takes 32 rows of a slice in
+// 16x16x4 steps (K = 4 rows) over the output padded to 32 x 32 (four tiles).
+// Lane (g, l): A operand row 4 kk + g of the first factor at column 16 a + l,
+// B operand the same row of the second at column 16 b + l; tile element e
+// lands at output (16 a + 4 e + g, 16 b + l).  The waves' tiles are added in
+// wave order at the end.
 __global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, double* __restrict__ part) {
-  __shared__ double Fs[TS_ROWS][PSTT2_MAX_ELL + 1];
-  __shared__ double Ss[TS_ROWS][PSTT2_MAX_ELL + 1];
+  __shared__ double Ss[PSTT2_MAX_ELL][TS_ROWS + 1];   // operand slice, [column][row]; reused for the wave sums
   __shared__ double Hs[TS_HMAX][PSTT2_MAX_ELL + 1];
   __shared__ int32_t ri[TS_ROWS], rh[TS_ROWS];   // a slice row as i + n_0 (h0 + rh)
   const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6, g = lane >> 4, l = lane & 15;
   const int ell = B.ell, d = B.d;
   const int p = batch_find(B.blk0, B.n, blockIdx.x);
   const int64_t K = B.K[p];
@@ -970,12 +978,32 @@ __global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, d
   const int64_t n0 = nmode[q0];
   const bool htab = n0 >= 4;
   const int nout = ell * ell;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  ts_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = ts_d4{0.0, 0.0, 0.0, 0.0};
+  // the operand slice is loaded one slice ahead into registers: thread t
+  // holds rows t % TS_ROWS of columns t / TS_ROWS + 2 j (coalesced down the rows)
+  constexpr int NPRE = PSTT2_MAX_ELL * TS_ROWS / 256;
+  static_assert(256 % TS_ROWS == 0 && NPRE * 256 == PSTT2_MAX_ELL * TS_ROWS, "staging layout");
+  double pre[NPRE];
+  auto load_slice = [&](int64_t rb) {
+    const int64_t row = rb + t % TS_ROWS;
+#pragma unroll
+    for (int j = 0; j < NPRE; ++j) {
+      const int u = t / TS_ROWS + (256 / TS_ROWS) * j;
+      pre[j] = (row < K && u < sc) ? S[(int64_t)u * K + row] : 0.0;
+    }
+  };
+  if (r0 < K) load_slice(r0);
   for (int st = 0; st < nsteps; ++st) {
     const int64_t rb = r0 + (int64_t)st * TS_ROWS;
     if (rb >= K) break;
     const int64_t h0 = rb / n0;
     __syncthreads();   // the last slice's LDS reads are done
+#pragma unroll
+    for (int j = 0; j < NPRE; ++j) Ss[t / TS_ROWS + (256 / TS_ROWS) * j][t % TS_ROWS] = pre[j];
     if (htab) {
       const int64_t rl = std::min<int64_t>(rb + TS_ROWS, K) - 1;
       const int nh = (int)(rl / n0 - h0 + 1);   // <= TS_ROWS / n_0 + 2 <= TS_HMAX
@@ -988,40 +1016,49 @@ __global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, d
         ri[t] = (int32_t)(row - h * n0);
         rh[t] = (int32_t)(h - h0);
       }
-      __syncthreads();
-    }
-    for (int e = t; e < TS_ROWS * ell; e += 256) {
-      const int r = e % TS_ROWS, u = e / TS_ROWS;
-      const int64_t row = rb + r;
-      double sv = 0.0, fv = 0.0;
-      if (row < K) {
-        sv = u < sc ? S[(int64_t)u * K + row] : 0.0;
-        fv = htab ? B.fac[off[0] + (int64_t)ri[r] * ell + u] * Hs[rh[r]][u]
-                  : chain_product(B, off, nmode, q0, 0, cnt, row, u);
-      }
-      Ss[r][u] = sv;
-      Fs[r][u] = fv;
     }
     __syncthreads();
+    if (st + 1 < nsteps && rb + TS_ROWS < K) load_slice(rb + TS_ROWS);   // lands during this slice's products
+#pragma unroll 2
+    for (int kk = 0; kk < 8; ++kk) {
+      const int r = 32 * w + 4 * kk + g;
+      const int64_t row = rb + r;
+      double f[2], sv[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int o = t + 256 * q;
-      if (o < nout) {
-        const int u = o % ell, v = o / ell;
-        double a = acc[q];
-        if (!right) {
-          for (int r = 0; r < TS_ROWS; ++r) a += Fs[r][u] * Ss[r][v];   // Psi_k(row, u) S_k(row, v)
-        } else {
-          for (int r = 0; r < TS_ROWS; ++r) a += Ss[r][u] * Fs[r][v];   // T_k(u, col) Omega_k(col, v)
-        }
-        acc[q] = a;
+      for (int a = 0; a < 2; ++a) {
+        const int u = 16 * a + l;
+        sv[a] = Ss[u][r];
+        f[a] = 0.0;
+        if (row < K && u < ell)
+          f[a] = htab ? B.fac[off[0] + (int64_t)ri[r] * ell + u] * Hs[rh[r]][u]
+                      : chain_product(B, off, nmode, q0, 0, cnt, row, u);
       }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          // left: Psi_k(row, u) S_k(row, v); right: T_k(u, col) Omega_k(col, v)
+          const double x = right ? sv[a] : f[a], y = right ? f[c] : sv[c];
+          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[a][c], 0, 0, 0);
+        }
     }
   }
+  // the four waves' tiles through LDS (Ss as scratch), added in wave order
+  __syncthreads();
+  double* red = &Ss[0][0];   // 4 waves x 32 x 32 doubles fit in Ss (32 x 129)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int o = t + 256 * q;
-    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = acc[q];
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[w * 1024 + (16 * a + 4 * e + g) * 32 + 16 * c + l] = acc[a][c][e];
+  __syncthreads();
+  for (int o = t; o < nout; o += 256) {
+    const int u = o % ell, v = o / ell;
+    double sum = red[u * 32 + v];
+#pragma unroll
+    for (int ww = 1; ww < 4; ++ww) sum += red[ww * 1024 + u * 32 + v];
+    part[(int64_t)blockIdx.x * nout + o] = sum;
   }
 }
 
