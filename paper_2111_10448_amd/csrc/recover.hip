@@ -960,6 +960,7 @@ typedef double ts_d4 __attribute__((ext_vector_type(4)));
 // wave order at the end.
 __global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, double* __restrict__ part) {
   __shared__ double Ss[PSTT2_MAX_ELL][TS_ROWS + 1];   // operand slice, [column][row]; reused for the wave sums
+  __shared__ double Fs[PSTT2_MAX_ELL][TS_ROWS + 1];   // the slice's Khatri-Rao rows, [column][row]
   __shared__ double Hs[TS_HMAX][PSTT2_MAX_ELL + 1];
   __shared__ int32_t ri[TS_ROWS], rh[TS_ROWS];   // a slice row as i + n_0 (h0 + rh)
   const int t = threadIdx.x;
@@ -1018,20 +1019,26 @@ __global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, d
       }
     }
     __syncthreads();
+    // the Khatri-Rao rows of the slice, all independent loads in one phase
+    for (int e = t; e < PSTT2_MAX_ELL * TS_ROWS; e += 256) {
+      const int r = e % TS_ROWS, u = e / TS_ROWS;
+      const int64_t row = rb + r;
+      double f = 0.0;
+      if (row < K && u < ell)
+        f = htab ? B.fac[off[0] + (int64_t)ri[r] * ell + u] * Hs[rh[r]][u]
+                 : chain_product(B, off, nmode, q0, 0, cnt, row, u);
+      Fs[u][r] = f;
+    }
+    __syncthreads();
     if (st + 1 < nsteps && rb + TS_ROWS < K) load_slice(rb + TS_ROWS);   // lands during this slice's products
 #pragma unroll 2
     for (int kk = 0; kk < 8; ++kk) {
       const int r = 32 * w + 4 * kk + g;
-      const int64_t row = rb + r;
       double f[2], sv[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const int u = 16 * a + l;
-        sv[a] = Ss[u][r];
-        f[a] = 0.0;
-        if (row < K && u < ell)
-          f[a] = htab ? B.fac[off[0] + (int64_t)ri[r] * ell + u] * Hs[rh[r]][u]
-                      : chain_product(B, off, nmode, q0, 0, cnt, row, u);
+        sv[a] = Ss[16 * a + l][r];
+        f[a] = Fs[16 * a + l][r];
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
