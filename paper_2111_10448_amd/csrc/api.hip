@@ -312,6 +312,10 @@ pstt2_status launch_segs(pstt2_ctx* c, const SketchArgs& ga, const std::vector<S
       }
       a.nchunks = nch;
       a.gj_count = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nch, c->gj_max));
+      if (c->prec == PSTT2_P_F64 && a.gj_count == 1) {
+        a.ydirect = Yd;
+        a.yflag = c->flag;
+      }
       std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
       if (c->profile) {
         if (c->ev_pool.empty()) {

@@ -81,6 +81,11 @@ struct SketchArgs {
   int64_t psi_off[PSTT2_MAX_D];    // offset of psi_q (q = 1..d-1) at index q-1
   int64_t omega_off[PSTT2_MAX_D];  // offset of omega_q (q = 2..d) at index q-1
   void* ypart;       // [gj][c][row], ell columns
+  // FP64 kernel with one column group only: when set, the kernel adds its Y
+  // tile straight into this R x ell column-major sketch (and raises *yflag on
+  // a non-finite sum) instead of writing ypart; the reduction then skips Y.
+  double* ydirect;
+  int* yflag;
   void* tpart;       // tlp == 0: [gi][a][gcol], ell rows; tlp > 0: [gi][gcol][tlp] (sketch index
                      // contiguous); indexed by global column; then kTPartPad spare entries
   int32_t tlp;       // layout of tpart (see above)

@@ -103,10 +103,11 @@ hipError_t launch_reduce(int prec, const SketchArgs& a, double* Y, double* Tt, i
   const int bs = 256;
   const int64_t ny = a.R * a.ell;
   const unsigned gy = (unsigned)std::min<int64_t>((ny + bs - 1) / bs, 4096);
-  if (prec == PSTT2_P_F64)
+  // With ydirect the sketch kernel has already added its one Y partial into Y.
+  if (!a.ydirect && prec == PSTT2_P_F64)
     hipLaunchKernelGGL(k_reduce_y<double>, dim3(gy), dim3(bs), 0, s, (const double*)a.ypart, a.gj_count, a.R,
                        a.ell, Y, flag);
-  else
+  else if (!a.ydirect)
     hipLaunchKernelGGL(k_reduce_y<float>, dim3(gy), dim3(bs), 0, s, (const float*)a.ypart, a.gj_count, a.R,
                        a.ell, Y, flag);
   int64_t nt = 0;

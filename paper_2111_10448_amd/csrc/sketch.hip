@@ -1343,7 +1343,22 @@ __global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_
   __syncthreads();
   if (it >= 1) reduce_t((it - 1) & 1, ce - 1);
 
+  // One column group: each entry of Y_R has this workgroup as its only
+  // writer, so the tile is added into Y_R here (the same single addition the
+  // reduction would make) instead of going through the partial buffer.
   double* yp = (double*)A.ypart;
+  double* yd = A.ydirect;
+  bool bad = false;
+  auto put = [&](int64_t row, int c, double v) {
+    if (yd) {
+      const int64_t i = (int64_t)c * A.R + row;
+      const double s = yd[i] + v;
+      yd[i] = s;
+      bad = bad || !isfinite(s);
+    } else {
+      yp[((int64_t)gj * A.ell + c) * A.R + row] = v;
+    }
+  };
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
@@ -1352,20 +1367,22 @@ __global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_
       for (int v = 0; v < 4; ++v) {
         const int64_t row = row0w + 16 * mt + 4 * v + g4;
         const int c = 16 * q + l16;
-        if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = yq[mt][q][v];
+        if (row < A.R && c < A.ell) put(row, c, yq[mt][q][v]);
       }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int64_t row = row0w + 16 * mt + 4 * blk + g4;
       const int c = 16 * NQ + 4 * s + l4;
-      if (row < A.R && c < A.ell) yp[((int64_t)gj * A.ell + c) * A.R + row] = ys[mt][s];
+      if (row < A.R && c < A.ell) put(row, c, ys[mt][s]);
     }
   }
+  if (bad) atomicOr(A.yflag, 1);
 }
 
 template <int L4>
 static hipError_t launch_f64(const SketchArgs& a, bool aligned, hipStream_t s) {
   dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(nwf_for(L4) * 64);
+  if (a.ydirect && (a.gj_count != 1 || !a.yflag)) return hipErrorInvalidValue;
   const bool seg1 = a.nseg == 1 && a.seg[0].chunk0 == 0;
   if (a.fn) {
     if (!seg1 || a.fn != 1 || !a.fn_rec || !a.fn_row || !a.fn_col || a.x32) return hipErrorInvalidValue;
@@ -1443,7 +1460,7 @@ static hipError_t launch_t(const SketchArgs& a, bool aligned, hipStream_t s) {
 
 hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s) {
   if (fault_take()) return hipErrorLaunchFailure;
-  if (a.fn && prec != P_F64) return hipErrorInvalidValue;
+  if ((a.fn || a.ydirect) && prec != P_F64) return hipErrorInvalidValue;
   // 16-byte loads need every column (and segment start) 16-byte aligned.
   const int esz = prec == P_F64 && !a.x32 ? 8 : 4;
   bool aligned = ((a.R * esz) % 16) == 0;
