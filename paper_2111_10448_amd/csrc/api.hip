@@ -545,7 +545,7 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
     return bail(e, "omega table");
   const int npl16 = omega16_planes(c->prec);
   if (npl16) {
-    const size_t b16 = sizeof(uint16_t) * npl16 * c->lp * c->C;
+    const size_t b16 = sizeof(uint16_t) * npl16 * omega16_entries(c->C, c->lp);
     if ((e = dev_malloc(&c->om16, b16)) != hipSuccess) return bail(e, "hipMalloc(omega16)");
     if ((e = build_omega16_table(c->om_tab, c->C, c->L4, c->ell, c->lp, c->prec, c->om16, c->stream)) != hipSuccess)
       return bail(e, "omega16 table");
@@ -562,7 +562,7 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
       for (int q = 0; q < PSTT2_MAX_D; ++q) a.omega_off[q] = c->iom_off[k][q];
       if ((e = build_omega_table(a, c->L4, c->iom_tab[k], c->stream)) != hipSuccess) return bail(e, "omega table");
       if (npl16) {
-        const size_t b16 = sizeof(uint16_t) * npl16 * c->lp * c->C;
+        const size_t b16 = sizeof(uint16_t) * npl16 * omega16_entries(c->C, c->lp);
         if ((e = dev_malloc(&c->iom16[k], b16)) != hipSuccess) return bail(e, "hipMalloc(omega16)");
         if ((e = build_omega16_table(c->iom_tab[k], c->C, c->L4, c->ell, c->lp, c->prec, c->iom16[k], c->stream)) !=
             hipSuccess)

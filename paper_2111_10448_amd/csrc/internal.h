@@ -153,6 +153,14 @@ hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s);
 constexpr int64_t kTPartPad = 2048;
 // 16-bit sketch precisions (plain BF16, FP16: 1 plane; split BF16: 3 planes; else 0)
 int omega16_planes(int prec);
+// Layout of the 16-bit Omega table: row stride (C rounded up to a multiple of
+// four) and entries to allocate (LP rows plus kOmega16Slack zeroed entries
+// that the 8-byte operand loads of the last columns may reach).
+constexpr int64_t kOmega16Slack = 64;
+__host__ __device__ inline int64_t omega16_stride(int64_t C) { return (C + 3) / 4 * 4; }
+__host__ __device__ inline int64_t omega16_entries(int64_t C, int LP) {
+  return (int64_t)LP * omega16_stride(C) + kOmega16Slack;
+}
 // Columns per chunk of the precision's sketch kernel (Seg::chunk0 counts these).
 int sketch_chunk_cols(int prec);
 // om16[(q LP + c) C + col] = plane q of Omega_m(col, c) rounded as the kernel uses it.

@@ -888,30 +888,38 @@ __global__ __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) void k_sketch16(const Ske
   };
 
   // ---- Omega operands of a chunk: lane (g4, l16), tile nt, K step ks holds
-  //      Omega(columns 16 ks + 4 g4 .. + 3, sketch column 16 nt + l16) ----
-  s4 ob[NT][2];
-  auto load_omega = [&](int64_t ci) {
+  //      Omega(columns 16 ks + 4 g4 .. + 3, sketch column 16 nt + l16).  Two
+  //      register sets: the next chunk's are requested before the X loads of
+  //      the chunk after it, so that waiting for them (loads complete in
+  //      order) never waits for X that is still in flight. ----
+  //      The loads are unconditional: the table rows have a stride that is a
+  //      multiple of four and slack after the last row, so the aligned 8-byte
+  //      word holding a lane's first column and the word after it are always
+  //      in the table; the four columns are shifted out of the pair only when
+  //      the operand is used (a use right after the load would wait for it).
+  //      Columns past the chunk read whatever the table holds there, a finite
+  //      value that meets a zeroed X column. ----
+  uint2 wo[2][NT][2][2];
+  int osh[2];
+  auto load_omega = [&](int64_t ci, int b) {
     const ChunkInfo ch = co.at<SEG1>(A, ci < ce ? ci : ce - 1);
-    const bool al = ((A.C | ch.gcol0) & 3) == 0 && ch.ncols == KC16;   // aligned 8-byte loads
+    const int64_t cs = omega16_stride(A.C);
+    const int sh = (int)(ch.gcol0 & 3);
+    osh[b] = sh;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        const int col = 16 * ks + 4 * g4;
-        const uint16_t* src = A.om16 + (int64_t)(16 * nt + l16) * A.C + ch.gcol0;
-        if (al) {
-          ob[nt][ks] = *(const s4*)(src + col);
-        } else {
-          short v[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const bool in = col + j < ch.ncols;
-            const uint16_t u = src[in ? col + j : 0];
-            v[j] = in ? (short)u : (short)0;
-          }
-          ob[nt][ks] = s4{v[0], v[1], v[2], v[3]};
-        }
+        const uint16_t* src = A.om16 + (int64_t)(16 * nt + l16) * cs + (ch.gcol0 - sh) + 16 * ks + 4 * g4;
+        wo[b][nt][ks][0] = *(const uint2*)src;
+        wo[b][nt][ks][1] = sh ? *(const uint2*)(src + 4) : uint2{0u, 0u};
       }
+  };
+  auto omega_op = [&](int b, int nt, int ks) -> s4 {
+    const uint64_t lo = __builtin_bit_cast(uint64_t, wo[b][nt][ks][0]);
+    const uint64_t hi = __builtin_bit_cast(uint64_t, wo[b][nt][ks][1]);
+    const int sh = osh[b];
+    return __builtin_bit_cast(s4, sh ? (lo >> (16 * sh)) | (hi << (64 - 16 * sh)) : lo);
   };
 
   f4 yacc[RT][NT];
@@ -922,8 +930,8 @@ __global__ __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) void k_sketch16(const Ske
 
   if (cb < ce) {
     load_chunk(cb, 0);
+    load_omega(cb, 0);
     load_chunk(cb + 1, 1);
-    load_omega(cb);
   }
 
   auto chunk_step = [&](int64_t ci, int it, int slot) {
@@ -936,7 +944,9 @@ __global__ __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) void k_sketch16(const Ske
         fx[rt][ct] = cvt4<PREC>(xr[slot][rt][ct], xok[slot] >> (4 * (rt * CT + ct)));
         *(s4*)&Xl[w][(16 * ct + l16) * XS + 16 * rt + 4 * g4] = fx[rt][ct];
       }
-    // (b) prefetch chunk ci + 2 into the slot just converted
+    // (b) Omega operands of the next chunk, then chunk ci + 2 into the X slot
+    //     just converted
+    load_omega(ci + 1, slot ^ 1);
     load_chunk(ci + 2, slot);
     // (c) left sketch from the registers: T(16 mt + .., 16 ct + l16), K = the wave's 64 rows
     f4 tacc[CT][NT];
@@ -965,10 +975,8 @@ __global__ __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) void k_sketch16(const Ske
             (lds_s4*)&Xl[w][(16 * ks + 4 * g4 + (l16 >> 2)) * XS + 16 * mt + 4 * (l16 & 3)]);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
-        yacc[mt][nt] = mfma32<PREC>(xa[0], xa[1], ob[nt][0], ob[nt][1], yacc[mt][nt]);
+        yacc[mt][nt] = mfma32<PREC>(xa[0], xa[1], omega_op(slot, nt, 0), omega_op(slot, nt, 1), yacc[mt][nt]);
     }
-    // Omega operands of the next chunk (needed only at its right sketch)
-    load_omega(ci + 1);
     // (e) this wave's T tile into slot it % NS once the slot's previous chunk
     //     has been summed (bounded wait: see the kernel comment)
     const int sl = it % NS;
@@ -1038,23 +1046,26 @@ __global__ __launch_bounds__(NW * 64, NW == 4 ? 2 : 1) void k_sketch16(const Ske
       }
 }
 
-// Omega_m rounded to the 16-bit arithmetic: om16[c C + col] = Omega_m(col, c)
-// (zero for c >= ell).  Same rounding (FP64 -> FP32 -> 16 bits, nearest even)
-// as the effective DRM the middle core uses.
+// Omega_m rounded to the 16-bit arithmetic: om16[c cs + col] = Omega_m(col, c)
+// with row stride cs = C rounded up to a multiple of four (zero for c >= ell,
+// for the padding columns and for the slack after the last row).  Same
+// rounding (FP64 -> FP32 -> 16 bits, nearest even) as the effective DRM the
+// middle core uses.
 __global__ void k_omega16_table(const double* __restrict__ om_tab, int64_t C, int L4, int ell, int LP, int prec,
                                 uint16_t* __restrict__ om16) {
-  const int64_t tot = (int64_t)LP * C;
+  const int64_t cs = omega16_stride(C);
+  const int64_t tot = omega16_entries(C, LP);
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(t / C);
-    const int64_t col = t % C;
-    const float f = c < ell ? (float)om_tab[col * L4 + c] : 0.0f;
+    const int64_t c = t / cs;
+    const int64_t col = t % cs;
+    const float f = c < ell && col < C ? (float)om_tab[col * L4 + c] : 0.0f;
     om16[t] = (uint16_t)(prec == P_F16 ? cvt_pk16<P_F16>(f, 0.0f) : cvt_pk16<P_BF16>(f, 0.0f));
   }
 }
 
 hipError_t build_omega16_table(const double* om_tab, int64_t C, int L4, int ell, int LP, int prec, uint16_t* om16,
                                hipStream_t s) {
-  const int64_t tot = (int64_t)LP * C;
+  const int64_t tot = omega16_entries(C, LP);
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 16384));
   hipLaunchKernelGGL(k_omega16_table, dim3(g), dim3(256), 0, s, om_tab, C, L4, ell, LP, prec, om16);
   return hipGetLastError();
