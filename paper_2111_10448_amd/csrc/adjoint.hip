@@ -82,19 +82,26 @@ __global__ __launch_bounds__(256) void k_gemm_w(bool ta, bool tb, int64_t M, int
 // steps: workgroup g stages rows [g TN_ROWS, (g+1) TN_ROWS) of both operands in
 // LDS, 64 rows at a time, and writes the partial product of its slice; a
 // wavefront per entry of C then adds the slices' partials in slice order with a
-// fixed butterfly (deterministic for any K).
+// fixed butterfly (deterministic for any K).  A batch of products with the same
+// A, C_i = A^T B_i (B_i = B + i sb, C_i = C + i sc), shares each launch: the
+// batch index runs fastest over the workgroups, so the products of one row
+// slice run together and read that slice of A once from HBM.
 constexpr int TN_ROWS = 128;
 constexpr int TN_SUB = 64;
 
 __global__ __launch_bounds__(256) void k_gemm_tn_part(int M, int N, int64_t K, const double* __restrict__ A,
                                                       int64_t lda, const double* __restrict__ B, int64_t ldb,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part, int nbatch, int64_t sb, int nb) {
   __shared__ double As[TN_SUB][33];
   __shared__ double Bs[TN_SUB][33];
   const int t = threadIdx.x;
   const int nout = M * N;
+  const int bi = (int)(blockIdx.x % nbatch);
+  const int64_t g = blockIdx.x / nbatch;
+  B += bi * sb;
+  part += ((int64_t)bi * nb + g) * nout;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t r0 = (int64_t)blockIdx.x * TN_ROWS;
+  const int64_t r0 = g * TN_ROWS;
   const int64_t r1 = std::min<int64_t>(K, r0 + TN_ROWS);
   for (int64_t k0 = r0; k0 < r1; k0 += TN_SUB) {
     const int nr = (int)std::min<int64_t>(TN_SUB, r1 - k0);
@@ -122,16 +129,20 @@ __global__ __launch_bounds__(256) void k_gemm_tn_part(int M, int N, int64_t K, c
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int o = t + 256 * q;
-    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = acc[q];
+    if (o < nout) part[o] = acc[q];
   }
 }
 
 __global__ __launch_bounds__(256) void k_gemm_tn_sum(const double* __restrict__ part, int nb, int M, int N,
-                                                     double alpha, double beta, double* __restrict__ C, int64_t ldc) {
+                                                     double alpha, double beta, double* __restrict__ C, int64_t ldc,
+                                                     int nbatch, int64_t sc) {
   const int lane = threadIdx.x & 63;
-  const int o = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t ow = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int nout = M * N;
-  if (o >= nout) return;
+  if (ow >= (int64_t)nout * nbatch) return;
+  const int bi = (int)(ow / nout), o = (int)(ow % nout);
+  part += (int64_t)bi * nb * nout;
+  C += bi * sc;
   double s = 0.0;
   for (int g = lane; g < nb; g += 64) s += part[(int64_t)g * nout + o];
   s = wsum(s);
@@ -150,9 +161,10 @@ static hipError_t gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
     double* part = nullptr;
     hipError_t e = ws_alloc((void**)&part, sizeof(double) * nb * M * N, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gemm_tn_part, dim3(nb), dim3(256), 0, s, (int)M, (int)N, K, A, lda, B, ldb, part);
+    hipLaunchKernelGGL(k_gemm_tn_part, dim3(nb), dim3(256), 0, s, (int)M, (int)N, K, A, lda, B, ldb, part, 1,
+                       (int64_t)0, nb);
     hipLaunchKernelGGL(k_gemm_tn_sum, dim3((unsigned)((M * N + 3) / 4)), dim3(256), 0, s, part, nb, (int)M, (int)N,
-                       alpha, beta, C, ldc);
+                       alpha, beta, C, ldc, 1, (int64_t)0);
     e = hipGetLastError();
     ws_free(part, s);
     return e;
@@ -498,6 +510,30 @@ __global__ __launch_bounds__(256) void k_adj_out(const AdjOutArgs A, const T* __
 hipError_t adj_gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                     const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
   return gemm(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+}
+
+hipError_t adj_gemm_tn_batch(int64_t M, int64_t N, int64_t K, int nbatch, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, int64_t sb, double* C, int64_t ldc, int64_t sc,
+                             hipStream_t s) {
+  if (M <= 0 || N <= 0 || nbatch <= 0) return hipSuccess;
+  if (!(M <= 32 && N <= 32 && K >= 2 * TN_ROWS)) {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < nbatch && e == hipSuccess; ++i)
+      e = gemm(true, false, M, N, K, 1.0, A, lda, B + i * sb, ldb, 0.0, C + i * sc, ldc, s);
+    return e;
+  }
+  const int nb = (int)((K + TN_ROWS - 1) / TN_ROWS);
+  const int64_t nout = M * N;
+  double* part = nullptr;
+  hipError_t e = ws_alloc((void**)&part, sizeof(double) * nb * nbatch * nout, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gemm_tn_part, dim3((unsigned)((int64_t)nb * nbatch)), dim3(256), 0, s, (int)M, (int)N, K, A,
+                     lda, B, ldb, part, nbatch, sb, nb);
+  hipLaunchKernelGGL(k_gemm_tn_sum, dim3((unsigned)((nout * nbatch + 3) / 4)), dim3(256), 0, s, part, nb, (int)M,
+                     (int)N, 1.0, 0.0, C, ldc, nbatch, sc);
+  e = hipGetLastError();
+  ws_free(part, s);
+  return e;
 }
 
 hipError_t adj_table(const double* in, int64_t rows, int cnt, int64_t si, int64_t sc, int L4, double* out,

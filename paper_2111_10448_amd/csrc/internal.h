@@ -247,6 +247,13 @@ hipError_t middle_twopass(int dtype, const void* x, int64_t first, int64_t count
 // Adjoint building blocks (adjoint.hip); FP64, column-major.
 hipError_t adj_gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                     const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s);
+// C_i = A^T B_i for i < nbatch (B_i = B + i sb, C_i = C + i sc, each M x N with
+// leading dimension ldc): the same products as nbatch calls of adj_gemm with
+// ta, alpha = 1, beta = 0, bitwise, in one pair of launches where the tall-skinny
+// path applies.
+hipError_t adj_gemm_tn_batch(int64_t M, int64_t N, int64_t K, int nbatch, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, int64_t sb, double* C, int64_t ldc, int64_t sc,
+                             hipStream_t s);
 hipError_t adj_table(const double* in, int64_t rows, int cnt, int64_t si, int64_t sc, int L4, double* out,
                      hipStream_t s);
 hipError_t adj_transpose(const double* A, int64_t arows, int64_t acols, double* B, hipStream_t s);

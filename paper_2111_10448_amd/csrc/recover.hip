@@ -788,13 +788,10 @@ hipError_t core_left(const double* Qprev, int64_t Rprev, int rprev, const double
   if (Rprev >= 4096) {
     // tall Q_{k-1}: one wave per entry would read Q_{k-1} r_{k-1} n_k r_k / R... times
     // over; per i, G(:, i, :) = Q_{k-1}^T Q_k(rows R_{k-1} i ..) is a tall-skinny
-    // product with fixed-order partial sums, writing G with leading dimension r_{k-1} n_k
+    // product with fixed-order partial sums, writing G with leading dimension r_{k-1} n_k;
+    // the n_k products share one launch (and each row slice of Q_{k-1})
     const int64_t Rk = Rprev * nk;
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < nk && e == hipSuccess; ++i)
-      e = adj_gemm(true, false, rprev, rk, Rprev, 1.0, Qprev, Rprev, Qk + Rprev * i, Rk, 0.0, G + (int64_t)rprev * i,
-                   (int64_t)rprev * nk, s);
-    return e;
+    return adj_gemm_tn_batch(rprev, rk, Rprev, nk, Qprev, Rprev, Qk, Rk, Rprev, G, (int64_t)rprev * nk, rprev, s);
   }
   const int64_t tot = (int64_t)rprev * nk * rk;
   hipLaunchKernelGGL(k_core_left, dim3(waves_grid(tot)), dim3(256), 0, s, Qprev, Rprev, rprev, Qk, nk, rk, G);
