@@ -854,6 +854,7 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
     tb.ell = ell;
     tb.fac = c->fac;
     tb.chain = c->chain_dev;
+    for (int q = 0; q < d; ++q) tb.nmode[q] = c->n[q];
     for (int k = 1; k <= d - 1; ++k) {
       const int p = tb.n++;
       const bool col = k < m || c->pstt;   // operand S_k (PSTT: S_{d-1} = Y)
@@ -982,6 +983,7 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
         tb.ell = ell;
         tb.fac = c->fac;
         tb.chain = c->chain_dev;
+        for (int q = 0; q < d; ++q) tb.nmode[q] = c->n[q];
         tb.n = 1;
         tb.split[0] = d - 1;
         tb.right[0] = 0;

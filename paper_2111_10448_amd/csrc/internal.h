@@ -234,6 +234,8 @@ struct TwoSidedBatch {
   int split[PSTT2_MAX_D], right[PSTT2_MAX_D];
   int scols[PSTT2_MAX_D];   // columns of S (0: ell; fewer: the rest of the product is zero)
   int steps[PSTT2_MAX_D];   // TS_ROWS-row slices per workgroup (set by two_sided_batch)
+  int64_t nmode[PSTT2_MAX_D];   // mode sizes n_1 .. n_d (host copy; zero: the per-slice path)
+  const double* H[PSTT2_MAX_D];  // whole H tables (set by two_sided_batch)
   double* out[PSTT2_MAX_D];
   int64_t blk0[PSTT2_MAX_D + 1];
 };

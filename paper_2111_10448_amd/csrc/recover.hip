@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -1077,6 +1078,175 @@ __global__ __launch_bounds__(256) void k_two_sided_part(const TwoSidedBatch B, d
   }
 }
 
+// H(h, u) of one problem for every h, row-major (ell per row): the product of
+// the factor rows of the chain's modes after the first, taken in the order
+// chain_product takes them, so the values equal the per-slice table's.
+// One launch for the whole batch: blockIdx.y is the problem.
+__global__ void k_two_sided_htab(const TwoSidedBatch B) {
+  const int p = blockIdx.y;
+  const int ell = B.ell, d = B.d;
+  const int k = B.split[p], right = B.right[p];
+  const int q0 = right ? k : 0, cnt = right ? d - k : k;
+  const int64_t* off = B.chain + ((int64_t)k * 2 + right) * d;
+  const int64_t* nmode = B.chain + (int64_t)(d + 1) * 2 * d;
+  const int64_t n0 = nmode[q0];
+  const int64_t tot = (B.K[p] + n0 - 1) / n0 * ell;
+  double* __restrict__ H = const_cast<double*>(B.H[p]);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x)
+    H[e] = chain_product(B, off, nmode, q0, 1, cnt, e / ell, (int)(e % ell));
+}
+
+// The same product when every problem of the batch has n_0 >= 4 and a whole H
+// table (k_two_sided_htab): the next slice's operand rows, its H rows (one
+// contiguous run) and each lane's first-mode factor entries are loaded into
+// registers while the current slice runs on the matrix cores, and each lane
+// forms its Khatri-Rao operand (first-mode factor times H) as it feeds it, so a
+// slice costs two barriers and no dependent cache round trip.  Values and the
+// order of every sum are those of k_two_sided_part.
+__global__ __launch_bounds__(256) void k_two_sided_part_h(const TwoSidedBatch B, double* __restrict__ part) {
+  __shared__ double Ss[PSTT2_MAX_ELL][TS_ROWS + 1];   // operand slice, [column][row]; reused for the wave sums
+  __shared__ double Hs[TS_HMAX][PSTT2_MAX_ELL + 1];
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6, g = lane >> 4, l = lane & 15;
+  const int ell = B.ell, d = B.d;
+  const int p = batch_find(B.blk0, B.n, blockIdx.x);
+  const int64_t K = B.K[p];
+  const int nsteps = B.steps[p];
+  const int64_t r0 = (blockIdx.x - B.blk0[p]) * (int64_t)TS_ROWS * nsteps;
+  const int k = B.split[p], right = B.right[p];
+  const int q0 = right ? k : 0;
+  const int64_t* off = B.chain + ((int64_t)k * 2 + right) * d;
+  const int64_t* nmode = B.chain + (int64_t)(d + 1) * 2 * d;
+  const double* __restrict__ S = B.S[p];
+  const double* __restrict__ H = B.H[p];
+  const int sc = B.scols[p] > 0 ? B.scols[p] : ell;
+  const int64_t n0 = nmode[q0];
+  const int64_t off0 = off[0];
+  const int nout = ell * ell;
+  ts_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = ts_d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int NPRE = PSTT2_MAX_ELL * TS_ROWS / 256;
+  constexpr int NHP = (TS_HMAX * PSTT2_MAX_ELL + 255) / 256;
+  double pre[NPRE], hpre[NHP];
+  // lane operands: rows 32 w + 4 kk + g of the slice, columns 16 a + l
+  double fv[2][8][2];
+  int rh[2][8];
+  uint32_t rok[2];
+  // the register buffer is a template argument, so every index stays static
+  auto load_slice = [&](int64_t rb, auto bsel) {
+    constexpr int b = decltype(bsel)::value;
+    const int64_t row = rb + t % TS_ROWS;
+#pragma unroll
+    for (int j = 0; j < NPRE; ++j) {
+      const int u = t / TS_ROWS + (256 / TS_ROWS) * j;
+      pre[j] = (row < K && u < sc) ? S[(int64_t)u * K + row] : 0.0;
+    }
+    const int64_t h0 = rb / n0;
+    const int64_t rl = std::min<int64_t>(rb + TS_ROWS, K) - 1;
+    const int64_t nhe = (rl / n0 - h0 + 1) * ell;   // <= TS_HMAX ell
+#pragma unroll
+    for (int m = 0; m < NHP; ++m) {
+      const int e = t + 256 * m;
+      hpre[m] = e < nhe ? H[h0 * ell + e] : 0.0;
+    }
+    // first-mode index and H row of each of the lane's rows (n_0 >= 4: a step
+    // of four rows wraps the first mode at most once)
+    const int64_t base = rb + 32 * w + g;
+    int64_t i = base % n0, hq = base / n0;
+    uint32_t ok = 0;
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      if (kk > 0) {
+        i += 4;
+        if (i >= n0) {
+          i -= n0;
+          ++hq;
+        }
+      }
+      const bool in = base + 4 * kk < K;
+      ok |= (in ? 1u : 0u) << kk;
+      rh[b][kk] = (int)(hq - h0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int u = 16 * a + l;
+        fv[b][kk][a] = (in && u < ell) ? B.fac[off0 + i * ell + u] : 0.0;
+      }
+    }
+    rok[b] = ok;
+  };
+  auto slice = [&](int64_t rb, auto bsel) {
+    constexpr int b = decltype(bsel)::value;
+    const int64_t h0 = rb / n0;
+    __syncthreads();   // the last slice's LDS reads are done
+#pragma unroll
+    for (int j = 0; j < NPRE; ++j) Ss[t / TS_ROWS + (256 / TS_ROWS) * j][t % TS_ROWS] = pre[j];
+    {
+      const int64_t rl = std::min<int64_t>(rb + TS_ROWS, K) - 1;
+      const int nhe = (int)((rl / n0 - h0 + 1) * ell);
+#pragma unroll
+      for (int m = 0; m < NHP; ++m) {
+        const int e = t + 256 * m;
+        if (e < nhe) Hs[e / ell][e % ell] = hpre[m];
+      }
+    }
+    __syncthreads();
+    if (rb + TS_ROWS < std::min<int64_t>(K, r0 + (int64_t)TS_ROWS * nsteps)) load_slice(rb + TS_ROWS, std::integral_constant<int, b ^ 1>{});
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int r = 32 * w + 4 * kk + g;
+      const bool in = (rok[b] >> kk) & 1u;
+      double f[2], sv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int u = 16 * a + l;
+        sv[a] = Ss[u][r];
+        f[a] = (in && u < ell) ? fv[b][kk][a] * Hs[rh[b][kk]][u] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const double x = right ? sv[a] : f[a], y = right ? f[c] : sv[c];
+          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[a][c], 0, 0, 0);
+        }
+    }
+  };
+  const std::integral_constant<int, 0> b0{};
+  const std::integral_constant<int, 1> b1{};
+  if (r0 < K) load_slice(r0, b0);
+  int st = 0;
+  for (; st + 1 < nsteps; st += 2) {
+    const int64_t rb = r0 + (int64_t)st * TS_ROWS;
+    if (rb >= K) break;
+    slice(rb, b0);
+    if (rb + TS_ROWS >= K) break;
+    slice(rb + TS_ROWS, b1);
+  }
+  if (st + 1 == nsteps) {
+    const int64_t rb = r0 + (int64_t)st * TS_ROWS;
+    if (rb < K) slice(rb, b0);
+  }
+  __syncthreads();
+  double* red = &Ss[0][0];   // 4 waves x 32 x 32 doubles fit in Ss (32 x 129)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[w * 1024 + (16 * a + 4 * e + g) * 32 + 16 * c + l] = acc[a][c][e];
+  __syncthreads();
+  for (int o = t; o < nout; o += 256) {
+    const int u = o % ell, v = o / ell;
+    double sum = red[u * 32 + v];
+#pragma unroll
+    for (int ww = 1; ww < 4; ++ww) sum += red[ww * 1024 + u * 32 + v];
+    part[(int64_t)blockIdx.x * nout + o] = sum;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_two_sided_sum(const TwoSidedBatch B, const double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
   const int nout = B.ell * B.ell;
@@ -1100,13 +1270,43 @@ hipError_t two_sided_batch(TwoSidedBatch& B, hipStream_t s) {
   }
   B.blk0[B.n] = nblk;
   if (B.n == 0) return hipSuccess;
+  // whole H tables when every problem's first chain mode has n_0 >= 4 (mode
+  // sizes known to the caller)
+  bool tab = true;
+  int64_t hrows[PSTT2_MAX_D] = {};
+  int64_t htot = 0;
+  for (int p = 0; p < B.n && tab; ++p) {
+    const int64_t n0 = B.nmode[B.right[p] ? B.split[p] : 0];
+    tab = n0 >= 4;
+    hrows[p] = tab ? (B.K[p] + n0 - 1) / n0 : 0;
+    htot += hrows[p] * B.ell;
+  }
   double* part = nullptr;
+  double* htab = nullptr;
   hipError_t e = ws_alloc((void**)&part, sizeof(double) * nblk * B.ell * B.ell, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_two_sided_part, dim3((unsigned)nblk), dim3(256), 0, s, B, part);
+  if (tab) {
+    e = ws_alloc((void**)&htab, sizeof(double) * std::max<int64_t>(htot, 1), s);
+    if (e != hipSuccess) {
+      ws_free(part, s);
+      return e;
+    }
+    int64_t o = 0, most = 0;
+    for (int p = 0; p < B.n; ++p) {
+      B.H[p] = htab + o;
+      o += hrows[p] * B.ell;
+      most = std::max<int64_t>(most, hrows[p] * B.ell);
+    }
+    const unsigned gh = (unsigned)std::max<int64_t>(1, std::min<int64_t>((most + 255) / 256, 16384));
+    hipLaunchKernelGGL(k_two_sided_htab, dim3(gh, (unsigned)B.n), dim3(256), 0, s, B);
+    hipLaunchKernelGGL(k_two_sided_part_h, dim3((unsigned)nblk), dim3(256), 0, s, B, part);
+  } else {
+    hipLaunchKernelGGL(k_two_sided_part, dim3((unsigned)nblk), dim3(256), 0, s, B, part);
+  }
   const int64_t waves = (int64_t)B.n * B.ell * B.ell;
   hipLaunchKernelGGL(k_two_sided_sum, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, B, part);
   e = hipGetLastError();
+  if (htab) ws_free(htab, s);
   ws_free(part, s);
   return e;
 }
