@@ -111,6 +111,15 @@ hipError_t derive_right(const double* Tin, double* Tout, int64_t Ck, int nk, int
 // ---------------------------------------------------------------------------
 constexpr int RED_LD = 264;   // LDS row stride of the reduction buffer (bank spread)
 
+// Value of v held by lane l of the wavefront (l wave-uniform), through the
+// scalar unit rather than an LDS read.
+__device__ __forceinline__ double lane_f64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Sum Red[c][0..255] for c in [c0, n) into Out[c]; threads t < LP*8 take
 // column t/8 and eight interleaved slices of it.  Caller synchronises.
 template <int LP>
@@ -211,9 +220,13 @@ __global__ __launch_bounds__(256) void k_qr_leaf(const LeafBatch B, int ell) {
       const int lr = t + 256 * k;
       v[k] = lr == j ? 1.0 : (lr > j ? a[k][j] * scal : 0.0);
     }
+    // p_c is formed by lane c of every wave and broadcast from there (one LDS
+    // read per lane instead of two per column)
+    const int lane = t & 63;
+    const double pl = lane < LP ? tj * (scal * Qs[lane] + Rowj[j & 1][lane]) : 0.0;
 #pragma unroll
     for (int c = j + 1; c < LP; ++c) {
-      const double pc = tj * (scal * Qs[c] + Rowj[j & 1][c]);
+      const double pc = lane_f64(pl, c);
 #pragma unroll
       for (int k = 0; k < RPT; ++k) a[k][c] -= pc * v[k];
     }
@@ -301,10 +314,11 @@ __global__ __launch_bounds__(256) void k_qr_apply(const ApplyBatch B, int ell) {
     __syncthreads();
     wg_colsum<RP>(Red, 0, r, Ws);
     __syncthreads();
+    const double wl = (t & 63) < r ? tj * Ws[t & 63] : 0.0;   // lane c holds w_c
 #pragma unroll
     for (int c = 0; c < RP; ++c) {
       if (c < r) {
-        const double wc = tj * Ws[c];
+        const double wc = lane_f64(wl, c);
 #pragma unroll
         for (int k = 0; k < RPT; ++k) z[k][c] -= wc * v[k];
       }
