@@ -83,6 +83,11 @@ struct pstt2_ctx {
   // pstt2_reset
   int64_t accum = 0;
   bool poisoned = false;
+  // Y has not been written since pstt2_reset and stands for zero: reset skips
+  // zeroing it when every sketch launch has one column group (the FP64
+  // kernel's direct Y tile), the first such launch stores its tile instead of
+  // adding it, and any other writer or reader zeroes Y first (y_settle)
+  bool y_unset = false;
   std::string err;
 };
 
@@ -255,6 +260,7 @@ SketchArgs group_args(const pstt2_ctx* c, int g, double** Ydst, double** Tdst) {
 }
 
 pstt2_status launch_segs(pstt2_ctx* c, const SketchArgs& ga, const std::vector<Seg>& segs, double* Yd, double* Td);
+hipError_t y_settle(pstt2_ctx* c);
 
 pstt2_status run_slabs(pstt2_ctx* c, const std::vector<Piece>& ps) {
   const int esz = c->dtype == PSTT2_F64 ? 8 : 4;
@@ -281,6 +287,7 @@ pstt2_status run_slabs(pstt2_ctx* c, const std::vector<Piece>& ps) {
       edges.push_back(Edge{base + (col * R - lo) * esz, 0, hi % R, col});
     }
   }
+  if (!edges.empty()) HIPCK(c, y_settle(c));   // partial columns add into Y
   for (int g = 0; g < pass_groups(c); ++g) {
     double *Yd = nullptr, *Td = nullptr;
     const SketchArgs ga = group_args(c, g, &Yd, &Td);
@@ -315,7 +322,9 @@ pstt2_status launch_segs(pstt2_ctx* c, const SketchArgs& ga, const std::vector<S
       if (c->prec == PSTT2_P_F64 && a.gj_count == 1) {
         a.ydirect = Yd;
         a.yflag = c->flag;
+        a.ystore = Yd == c->Y && c->y_unset;   // Y still stands for zero: store the tile
       }
+      if (Yd == c->Y && c->y_unset && !a.ystore) HIPCK(c, y_settle(c));
       std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
       if (c->profile) {
         if (c->ev_pool.empty()) {
@@ -328,6 +337,7 @@ pstt2_status launch_segs(pstt2_ctx* c, const SketchArgs& ga, const std::vector<S
         HIPCK(c, hipEventRecord(ev.first, c->stream));
       }
       HIPCK(c, launch_sketch(c->prec, c->lp, a, c->stream));
+      if (a.ystore) c->y_unset = false;
       if (c->profile) {
         HIPCK(c, hipEventRecord(ev.second, c->stream));
         c->ev_used.push_back(ev);
@@ -344,7 +354,17 @@ __global__ void k_zero_sketches(double* __restrict__ Y, int64_t ny, double* __re
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int64_t i = t0; i < ny; i += stride) Y[i] = 0.0;
   for (int64_t i = t0; i < nt; i += stride) T[i] = 0.0;
-  if (t0 == 0) *flag = 0;
+  if (t0 == 0 && flag) *flag = 0;
+}
+
+// Zero Y if it still stands for zero (see pstt2_ctx::y_unset).
+hipError_t y_settle(pstt2_ctx* c) {
+  if (!c->y_unset) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_sketches, dim3(1024), dim3(256), 0, c->stream, c->Y, c->R * c->ell, nullptr, 0,
+                     nullptr);
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) c->y_unset = false;
+  return e;
 }
 
 __global__ void k_transpose_last(const double* P, int64_t rows, int r, double* G) {
@@ -590,10 +610,14 @@ pstt2_status pstt2_create(const pstt2_desc* desc, void* hip_stream, pstt2_ctx** 
 pstt2_status pstt2_reset(pstt2_ctx* c) {
   if (!c) return fail(nullptr, PSTT2_EINVAL, "null context");
   free_recovery(c);
-  // one fill launch for both middle sketches and the flag word
-  hipLaunchKernelGGL(k_zero_sketches, dim3(1024), dim3(256), 0, c->stream, c->Y, c->R * c->ell, c->Tt,
+  // one fill launch for both middle sketches and the flag word; Y is left to
+  // the first sketch launch when every launch has one column group (FP64)
+  c->y_unset = false;
+  const bool lazy_y = !c->indep && c->prec == PSTT2_P_F64 && c->gj_max == 1;
+  hipLaunchKernelGGL(k_zero_sketches, dim3(1024), dim3(256), 0, c->stream, c->Y, lazy_y ? 0 : c->R * c->ell, c->Tt,
                      c->C * c->ell, c->flag);
   HIPCK(c, hipGetLastError());
+  c->y_unset = lazy_y;
   for (double* y : c->iY)
     if (y) HIPCK(c, hipMemsetAsync(y, 0, sizeof(double) * c->R * c->ell, c->stream));
   for (double* t : c->iT)
@@ -803,6 +827,7 @@ pstt2_status pstt2_recover(pstt2_ctx* c, tt_cores* out) {
   if (c->poisoned) return fail(c, PSTT2_ESTATE, kPoisoned);
   if (c->covered != c->N) return fail(c, PSTT2_ESTATE, "not every entry of X was streamed exactly once");
   free_recovery(c);
+  HIPCK(c, y_settle(c));
   const int d = c->d, m = c->m, ell = c->ell;
   hipStream_t s = c->stream;
   HIPCK(c, arena_begin(&c->arena, s));

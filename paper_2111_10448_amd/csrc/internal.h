@@ -86,6 +86,8 @@ struct SketchArgs {
   // a non-finite sum) instead of writing ypart; the reduction then skips Y.
   double* ydirect;
   int* yflag;
+  int32_t ystore;    // with ydirect: Y holds no data yet and stands for zero, so
+                     // the tile is stored (0 + y) instead of added
   void* tpart;       // tlp == 0: [gi][a][gcol], ell rows; tlp > 0: [gi][gcol][tlp] (sketch index
                      // contiguous); indexed by global column; then kTPartPad spare entries
   int32_t tlp;       // layout of tpart (see above)

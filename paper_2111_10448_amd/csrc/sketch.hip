@@ -1356,14 +1356,15 @@ __global__ __launch_bounds__(nwf_for(L4) * 64, f64_wg_per_cu(L4)) void k_sketch_
 
   // One column group: each entry of Y_R has this workgroup as its only
   // writer, so the tile is added into Y_R here (the same single addition the
-  // reduction would make) instead of going through the partial buffer.
+  // reduction would make) instead of going through the partial buffer.  The
+  // first launch after a reset that left Y_R unwritten stores 0 + tile.
   double* yp = (double*)A.ypart;
   double* yd = A.ydirect;
   bool bad = false;
   auto put = [&](int64_t row, int c, double v) {
     if (yd) {
       const int64_t i = (int64_t)c * A.R + row;
-      const double s = yd[i] + v;
+      const double s = (A.ystore ? 0.0 : yd[i]) + v;
       yd[i] = s;
       bad = bad || !isfinite(s);
     } else {
@@ -1394,6 +1395,7 @@ template <int L4>
 static hipError_t launch_f64(const SketchArgs& a, bool aligned, hipStream_t s) {
   dim3 grid((unsigned)(a.gi_count * a.gj_count)), block(nwf_for(L4) * 64);
   if (a.ydirect && (a.gj_count != 1 || !a.yflag)) return hipErrorInvalidValue;
+  if (a.ystore && !a.ydirect) return hipErrorInvalidValue;
   const bool seg1 = a.nseg == 1 && a.seg[0].chunk0 == 0;
   if (a.fn) {
     if (!seg1 || a.fn != 1 || !a.fn_rec || !a.fn_row || !a.fn_col || a.x32) return hipErrorInvalidValue;
@@ -1471,7 +1473,7 @@ static hipError_t launch_t(const SketchArgs& a, bool aligned, hipStream_t s) {
 
 hipError_t launch_sketch(int prec, int lp, const SketchArgs& a, hipStream_t s) {
   if (fault_take()) return hipErrorLaunchFailure;
-  if ((a.fn || a.ydirect) && prec != P_F64) return hipErrorInvalidValue;
+  if ((a.fn || a.ydirect || a.ystore) && prec != P_F64) return hipErrorInvalidValue;
   // 16-byte loads need every column (and segment start) 16-byte aligned.
   const int esz = prec == P_F64 && !a.x32 ? 8 : 4;
   bool aligned = ((a.R * esz) % 16) == 0;

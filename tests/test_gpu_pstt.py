@@ -15,7 +15,7 @@ from gpu_common import TOL_SK, TOL_XT, rel, say
 pytestmark = pytest.mark.gpu
 
 
-def _run(name, n, prec, mid, drm, slabs=1):
+def _run(name, n, prec, mid, drm, slabs=1, fibres=False, repeat=False):
     import dataclasses
     import torch
     import paper_2111_10448_amd as P
@@ -38,10 +38,22 @@ def _run(name, n, prec, mid, drm, slabs=1):
     ref = O.pstt(x64, w.n, D, ranks, onepass_psi=D.psi_dense(d - 1) if mid == "onepass" else None)
     xg = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     ctx = P.PSTT2(w.n, w.ell, fac, dtype=w.dtype, prec=prec, ranks=ranks, mid=mid, drm=drm, algo="pstt")
-    bounds = inputs.slab_bounds(x.size, int(np.prod(w.n[:d - 1])), slabs)
+    # whole columns of X_{d-1}, or mode-1 fibres (slabs that cut columns)
+    bounds = inputs.slab_bounds(x.size, w.n[0] if fibres else int(np.prod(w.n[:d - 1])), slabs)
     for f, c in bounds:
         ctx.sketch(xg[f:f + c], f)
     tt = ctx.recover()
+    if repeat:
+        # a reset and the same pass again reproduce every sketch bitwise
+        first = [ctx.get_sketch(0, k) for k in range(1, d)] + [ctx.get_sketch(1, d - 1)]
+        tt.free()
+        ctx.reset()
+        for f, c in bounds:
+            ctx.sketch(xg[f:f + c], f)
+        tt = ctx.recover()
+        again = [ctx.get_sketch(0, k) for k in range(1, d)] + [ctx.get_sketch(1, d - 1)]
+        for a, b in zip(first, again):
+            assert np.array_equal(a, b)
     if mid == "twopass":
         for f, c in bounds:
             ctx.middle_pass(tt, xg[f:f + c], f)
@@ -78,6 +90,17 @@ def _run(name, n, prec, mid, drm, slabs=1):
 ])
 def test_pstt_matches_oracle(name, n, prec, mid, drm, slabs):
     _run(name, n, prec, mid, drm, slabs)
+
+
+@pytest.mark.parametrize("slabs,fibres", [(1, False), (3, False), (5, True)])
+def test_pstt_tall_rows(slabs, fibres):
+    """X_{d-1} with 2^19 rows: more row blocks than the GPU holds workgroups, so
+    every sketch launch has one column group and adds its Y tile directly, and
+    the first launch after a reset stores it (Y is not zeroed at reset).  The
+    whole tensor, three whole-column slabs (the later launches add), and five
+    slabs that cut columns (the partial columns zero Y first), each against the
+    oracle, then reset and streamed again, bitwise equal."""
+    _run("c1", (128, 64, 64, 2), "f64", "onepass", "nested", slabs, fibres=fibres, repeat=True)
 
 
 def test_pstt_exact_recovery():
