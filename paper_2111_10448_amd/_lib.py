@@ -78,6 +78,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2111_10448_amd.build`")
+    # PyTorch's HIP runtime is loaded first, so that the library binds to that
+    # same runtime (one device context for the tensors, streams and kernels)
+    # rather than loading a second copy from the ROCm install
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
     L.pstt2_create.argtypes = [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]

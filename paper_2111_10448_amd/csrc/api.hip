@@ -338,12 +338,13 @@ pstt2_status launch_segs(pstt2_ctx* c, const SketchArgs& ga, const std::vector<S
       }
       HIPCK(c, launch_sketch(c->prec, c->lp, a, c->stream));
       if (a.ystore) c->y_unset = false;
+      if (a.ydirect) ++c->accum;   // Y_R already holds this launch's data
       if (c->profile) {
         HIPCK(c, hipEventRecord(ev.second, c->stream));
         c->ev_used.push_back(ev);
       }
       HIPCK(c, launch_reduce(c->prec, a, Yd, Td, c->flag, c->stream));
-      ++c->accum;
+      if (!a.ydirect) ++c->accum;
     }
   }
   return PSTT2_OK;

@@ -121,7 +121,7 @@ def test_injected_failure_before_any_addition_is_retryable():
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["slabs", "hilbert_groups", "gauss_tables"])
+@pytest.mark.parametrize("case", ["slabs", "hilbert_groups", "gauss_tables", "direct_y"])
 def test_injected_failure_after_an_addition_poisons(case):
     """A call that fails after part of its data was added leaves the context
     poisoned (ESTATE) until pstt2_reset; the retry after the reset matches the oracle."""
@@ -155,6 +155,19 @@ def test_injected_failure_after_an_addition_poisons(case):
         def run():
             ctx.sketch_fn("hilbert")
         prec, fail_after = "f64", 2
+    elif case == "direct_y":
+        # 2^19 rows of X_m: every launch has one column group, so the sketch launch
+        # itself writes Y_R (storing its tile: Y_R is not zeroed at reset); then its
+        # T reduction fails
+        w = dataclasses.replace(inputs.WORKLOADS["c1"], n=(1024, 512, 2, 2))
+        x, psi, omega, fac = setup(w)
+        ref = oracle_run(x, w, psi, omega)
+        xg = torch.from_numpy(x).cuda()
+        ctx = P.PSTT2(w.n, w.ell, fac, ranks=w.ranks())
+
+        def run():
+            ctx.sketch(xg)
+        prec, fail_after = "f64", 1
     else:
         # Gaussian bumps over two calls: the second call's table set-up fails
         # (nothing of it was added: not poisoned), then the retry completes
