@@ -1116,10 +1116,17 @@ __global__ void k_two_sided_htab(const TwoSidedBatch B) {
 // registers while the current slice runs on the matrix cores, and each lane
 // forms its Khatri-Rao operand (first-mode factor times H) as it feeds it, so a
 // slice costs two barriers and no dependent cache round trip.  Values and the
-// order of every sum are those of k_two_sided_part.
-__global__ __launch_bounds__(256) void k_two_sided_part_h(const TwoSidedBatch B, double* __restrict__ part) {
+// order of every sum are those of k_two_sided_part.  FTAB: the first mode's
+// factor rows (n_0 ell <= TS_FTAB entries for every problem) sit in LDS, so a
+// lane keeps only their row indices, and three workgroups fit on a compute unit.
+constexpr int TS_FTAB = 1024;
+
+template <bool FTAB>
+__global__ __launch_bounds__(256, FTAB ? 3 : 2) void k_two_sided_part_h(const TwoSidedBatch B,
+                                                                        double* __restrict__ part) {
   __shared__ double Ss[PSTT2_MAX_ELL][TS_ROWS + 1];   // operand slice, [column][row]; reused for the wave sums
   __shared__ double Hs[TS_HMAX][PSTT2_MAX_ELL + 1];
+  __shared__ double F1[FTAB ? TS_FTAB : 1];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6, g = lane >> 4, l = lane & 15;
   const int ell = B.ell, d = B.d;
@@ -1137,6 +1144,9 @@ __global__ __launch_bounds__(256) void k_two_sided_part_h(const TwoSidedBatch B,
   const int64_t n0 = nmode[q0];
   const int64_t off0 = off[0];
   const int nout = ell * ell;
+  if constexpr (FTAB) {
+    for (int e = t; e < n0 * ell; e += 256) F1[e] = B.fac[off0 + e];   // visible after the first barrier
+  }
   ts_d4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -1146,7 +1156,8 @@ __global__ __launch_bounds__(256) void k_two_sided_part_h(const TwoSidedBatch B,
   constexpr int NHP = (TS_HMAX * PSTT2_MAX_ELL + 255) / 256;
   double pre[NPRE], hpre[NHP];
   // lane operands: rows 32 w + 4 kk + g of the slice, columns 16 a + l
-  double fv[2][8][2];
+  double fv[FTAB ? 1 : 2][8][2];
+  int fi[FTAB ? 2 : 1][8];   // FTAB: first-mode index of each of the lane's rows
   int rh[2][8];
   uint32_t rok[2];
   // the register buffer is a template argument, so every index stays static
@@ -1183,10 +1194,14 @@ __global__ __launch_bounds__(256) void k_two_sided_part_h(const TwoSidedBatch B,
       const bool in = base + 4 * kk < K;
       ok |= (in ? 1u : 0u) << kk;
       rh[b][kk] = (int)(hq - h0);
+      if constexpr (FTAB) {
+        fi[b][kk] = (int)i;
+      } else {
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int u = 16 * a + l;
-        fv[b][kk][a] = (in && u < ell) ? B.fac[off0 + i * ell + u] : 0.0;
+        for (int a = 0; a < 2; ++a) {
+          const int u = 16 * a + l;
+          fv[b][kk][a] = (in && u < ell) ? B.fac[off0 + i * ell + u] : 0.0;
+        }
       }
     }
     rok[b] = ok;
@@ -1217,7 +1232,8 @@ __global__ __launch_bounds__(256) void k_two_sided_part_h(const TwoSidedBatch B,
       for (int a = 0; a < 2; ++a) {
         const int u = 16 * a + l;
         sv[a] = Ss[u][r];
-        f[a] = (in && u < ell) ? fv[b][kk][a] * Hs[rh[b][kk]][u] : 0.0;
+        if constexpr (FTAB) f[a] = (in && u < ell) ? F1[fi[b][kk] * ell + u] * Hs[rh[b][kk]][u] : 0.0;
+        else f[a] = (in && u < ell) ? fv[b][kk][a] * Hs[rh[b][kk]][u] : 0.0;
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -1313,7 +1329,10 @@ hipError_t two_sided_batch(TwoSidedBatch& B, hipStream_t s) {
     }
     const unsigned gh = (unsigned)std::max<int64_t>(1, std::min<int64_t>((most + 255) / 256, 16384));
     hipLaunchKernelGGL(k_two_sided_htab, dim3(gh, (unsigned)B.n), dim3(256), 0, s, B);
-    hipLaunchKernelGGL(k_two_sided_part_h, dim3((unsigned)nblk), dim3(256), 0, s, B, part);
+    bool ftab = true;
+    for (int p = 0; p < B.n; ++p) ftab = ftab && B.nmode[B.right[p] ? B.split[p] : 0] * B.ell <= TS_FTAB;
+    if (ftab) hipLaunchKernelGGL(k_two_sided_part_h<true>, dim3((unsigned)nblk), dim3(256), 0, s, B, part);
+    else hipLaunchKernelGGL(k_two_sided_part_h<false>, dim3((unsigned)nblk), dim3(256), 0, s, B, part);
   } else {
     hipLaunchKernelGGL(k_two_sided_part, dim3((unsigned)nblk), dim3(256), 0, s, B, part);
   }
