@@ -1289,6 +1289,37 @@ __global__ __launch_bounds__(256) void k_two_sided_sum(const TwoSidedBatch B, co
   if (lane == 0) B.out[p][o] = s;
 }
 
+// Two-level sum for problems with many slice partials: workgroup (x, p) adds,
+// for every output, the partials of its contiguous run of problem p's slices in
+// slice order (threads over outputs, so the reads are coalesced), then
+// k_two_sided_sum2 adds the runs in run order with the fixed butterfly.
+constexpr int TS_SPLIT = 256;   // runs per problem
+
+__global__ __launch_bounds__(256) void k_two_sided_split(const TwoSidedBatch B, const double* __restrict__ part,
+                                                         double* __restrict__ runs) {
+  const int p = blockIdx.y;
+  const int nout = B.ell * B.ell;
+  const int64_t b0 = B.blk0[p], nb = B.blk0[p + 1] - b0;
+  const int64_t g0 = b0 + blockIdx.x * nb / TS_SPLIT, g1 = b0 + (blockIdx.x + 1) * nb / TS_SPLIT;
+  for (int o = threadIdx.x; o < nout; o += 256) {
+    double s = 0.0;
+    for (int64_t g = g0; g < g1; ++g) s += part[g * nout + o];
+    runs[((int64_t)p * TS_SPLIT + blockIdx.x) * nout + o] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_two_sided_sum2(const TwoSidedBatch B, const double* __restrict__ runs) {
+  const int lane = threadIdx.x & 63;
+  const int nout = B.ell * B.ell;
+  const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (w >= (int64_t)B.n * nout) return;
+  const int p = (int)(w / nout), o = (int)(w % nout);
+  double s = 0.0;
+  for (int g = lane; g < TS_SPLIT; g += 64) s += runs[((int64_t)p * TS_SPLIT + g) * nout + o];
+  s = wave_sum(s);
+  if (lane == 0) B.out[p][o] = s;
+}
+
 hipError_t two_sided_batch(TwoSidedBatch& B, hipStream_t s) {
   int64_t nblk = 0;
   for (int p = 0; p < B.n; ++p) {
@@ -1337,8 +1368,23 @@ hipError_t two_sided_batch(TwoSidedBatch& B, hipStream_t s) {
     hipLaunchKernelGGL(k_two_sided_part, dim3((unsigned)nblk), dim3(256), 0, s, B, part);
   }
   const int64_t waves = (int64_t)B.n * B.ell * B.ell;
-  hipLaunchKernelGGL(k_two_sided_sum, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, B, part);
-  e = hipGetLastError();
+  int64_t most = 0;
+  for (int p = 0; p < B.n; ++p) most = std::max<int64_t>(most, B.blk0[p + 1] - B.blk0[p]);
+  double* runs = nullptr;
+  if (most >= 16 * TS_SPLIT) {
+    // many slices: two levels (a wave striding over tens of thousands of
+    // partials 8 ell^2 bytes apart reads one double per cache line)
+    e = hipGetLastError();
+    if (e == hipSuccess) e = ws_alloc((void**)&runs, sizeof(double) * B.n * TS_SPLIT * B.ell * B.ell, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_two_sided_split, dim3(TS_SPLIT, (unsigned)B.n), dim3(256), 0, s, B, part, runs);
+      hipLaunchKernelGGL(k_two_sided_sum2, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, B, runs);
+    }
+  } else {
+    hipLaunchKernelGGL(k_two_sided_sum, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, B, part);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (runs) ws_free(runs, s);
   if (htab) ws_free(htab, s);
   ws_free(part, s);
   return e;
